@@ -1,0 +1,216 @@
+/*
+ * psl.h -- C-ABI of libpsl: the subdomain-levelset (PSL) deflated preconditioned
+ * conjugate gradient solve of the heterogeneous pressure equation on AMD gfx950.
+ *
+ * Method: arXiv 1510.02148, "The parallel subdomain-levelset deflation method in
+ * reservoir simulation". The problem is A x = b (Section 2, eq. "coupledsys" restricted
+ * to the reservoir block) for the finite-volume pressure equation -div(K grad p) = q
+ * (Section 2, eq. "pressure"); Z holds one indicator vector per (subdomain, levelset)
+ * region (Section 3.2, eq. "domdefl" and the subdomain-levelset construction);
+ * E = Z^T A Z (Definition 3.1, eq. "E"); the deflated system P1 A xhat = P1 b
+ * (eq. "defsys") is solved and mapped back by x = Z E^-1 Z^T b + P2 xhat
+ * (eq. "projectback"). Z, E and its factorisation are built once and reused by every
+ * solve (Section 3.2: the operators are formed before the iteration starts and stay
+ * constant while the permeability is fixed).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid: nx x ny x nz unit cells, cell c = ix + nx*(iy + ny*iz); nz == 1 is a 2D
+ *     5-point problem. All cell arrays are length n = nx*ny*nz, contiguous.
+ *   - Face arrays (float64): Tx[(nx+1)*ny*nz] with face index ix + (nx+1)*(iy + ny*iz)
+ *     (face ix lies between cells ix-1 and ix); Ty[nx*(ny+1)*nz] with index
+ *     ix + nx*(iy + (ny+1)*iz); Tz[nx*ny*(nz+1)] with index ix + nx*(iy + ny*iz).
+ *     (A p)_c = sum over the six faces f of c of T_f (p_c - p_nbr), with p_nbr = 0
+ *     across an outer face: an outer face with T_f > 0 is a p = 0 Dirichlet face,
+ *     T_f = 0 is a no-flow face.
+ *   - Pointers documented "dev" are device pointers on the current HIP device;
+ *     "host" pointers are host memory. The caller owns every array it passes and the
+ *     library never frees caller memory. Arrays are only read unless marked "out".
+ *   - Every device operation is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream). Calls that return host results (d, psl_stats) synchronise that stream.
+ *   - Return value: PSL_OK (0) or a negative PSL_E* code. No exception crosses the ABI.
+ *     psl_status_str() names a code. A psl_ctx must not be used by two threads at once.
+ */
+#ifndef PSL_H
+#define PSL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define PSL_OK            0
+#define PSL_EINVAL       -1  /* bad argument: null pointer, size out of range, ... */
+#define PSL_ENOMEM       -2  /* device allocation failed */
+#define PSL_EHIP         -3  /* a HIP runtime call failed */
+#define PSL_ENOTSPD      -4  /* E (or diag(A)) not positive definite: Cholesky failed */
+#define PSL_EMAXIT       -5  /* iteration cap reached; x holds the projected last iterate */
+#define PSL_EBREAKDOWN   -6  /* (p, P1 A p) <= 0 inside CG */
+#define PSL_ENONFINITE   -7  /* NaN/Inf in b, x0 or an iterate */
+#define PSL_ESTAGNATION  -8  /* refinement stopped reducing the FP64 residual */
+#define PSL_ENOTSUP      -9  /* valid request this build does not support (limit given) */
+
+/* ---- Dirichlet face mask for psl_assemble_tpfa ----------------------------------- */
+#define PSL_DIRICHLET_X_LO  1u
+#define PSL_DIRICHLET_X_HI  2u
+#define PSL_DIRICHLET_Y_LO  4u
+#define PSL_DIRICHLET_Y_HI  8u
+#define PSL_DIRICHLET_Z_LO 16u
+#define PSL_DIRICHLET_Z_HI 32u
+
+/* ---- solve modes ------------------------------------------------------------------- */
+#define PSL_FP64   0  /* CG vectors and stencil in float64 */
+#define PSL_MIXED  1  /* CG vectors and stencil in float32 inside float64 refinement */
+
+/* Limits of this build. */
+#define PSL_MAX_THRESHOLDS   15     /* levelset thresholds per call (classes <= 16) */
+#define PSL_MAX_DENSE_D      8192   /* coarse dimension d (E and E^-1 are held dense) */
+#define PSL_MAX_TILE_LABELS  16     /* distinct labels inside one work tile */
+
+typedef struct { int32_t nx, ny, nz; } psl_grid;
+
+typedef struct psl_ctx psl_ctx;  /* opaque: owns its copies of T, labels, E, E^-1, work */
+
+typedef struct {
+  double  tol;          /* stop when ||b - A x||_2 <= tol * ||b||_2 (default 1e-8) */
+  int32_t maxit;        /* cap on CG iterations over all refinement steps (default 10000) */
+  int32_t mode;         /* PSL_FP64 or PSL_MIXED */
+  int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
+  int32_t max_outer;    /* cap on refinement steps (default 30) */
+  double  tau_inner;    /* PSL_MIXED: residual reduction asked of each float32 inner solve
+                           (default 1e-4); PSL_FP64 ignores it */
+  int32_t check_every;  /* CG iterations enqueued between host convergence checks
+                           (default 16; iterations after convergence are skipped on device) */
+  int32_t reproject;    /* re-apply P1 to the CG residual every iteration, fused into the
+                           update pass (keeps Z^T rhat = 0 under rounding): 1 on, 0 off,
+                           -1 (default) on for float32 CG and off for float64 CG */
+} psl_solve_opts;
+
+typedef struct {
+  int32_t iters;        /* CG iterations (products with A inside inner loops) */
+  int32_t outer;        /* refinement steps taken (FP64 residual evaluations - 1) */
+  int32_t status;       /* same value the call returned */
+  int32_t fell_back;    /* PSL_MIXED only: 1 if float32 stagnated and float64 finished */
+  double  relres_true;  /* ||b - A x||_2 / ||b||_2 in float64 from a fresh product */
+  double  bnorm;        /* ||b||_2 */
+  double  t_solve_s;    /* wall time of the call (host clock, stream synchronised) */
+} psl_solve_stats;
+
+/* Fill `o` with the defaults listed above. */
+void psl_default_opts(psl_solve_opts* o);
+
+/*
+ * psl_assemble_tpfa -- face transmissibilities of the cell-centred finite-volume
+ * discretisation of -div(K grad p) = q (Section 2, eqs. "pressure"/"mobility" with the
+ * total mobility taken as the permeability K, single phase).
+ *   g              host: grid.
+ *   K              dev[n] float64: isotropic cell permeability (>= 0).
+ *   dirichlet_mask PSL_DIRICHLET_* bits: outer faces held at p = 0.
+ *   Tx, Ty, Tz     dev out, float64, face arrays as described above.
+ * Interior face: 2 Ka Kb / (Ka + Kb) (harmonic mean over unit spacing), 0 if Ka+Kb = 0.
+ * Dirichlet outer face: 2 K of the adjacent cell (half-cell distance). Other outer
+ * faces: 0. Errors: PSL_EINVAL for a non-positive grid size or null pointer.
+ */
+int psl_assemble_tpfa(const psl_grid* g, const double* K, uint32_t dirichlet_mask,
+                      double* Tx, double* Ty, double* Tz, void* stream);
+
+/*
+ * psl_build_Z -- subdomain-levelset deflation space (Section 3.2: subdomain deflation
+ * vectors eq. "domdefl" with a levelset split inside every subdomain, vectors on both
+ * the high- and the low-permeability parts).
+ *   g        host: grid.
+ *   K        dev[n] float64 permeability (ignored when cls != NULL; may then be NULL).
+ *   nsub     host[3]: subdomains per axis (1 <= nsub[a] <= extent). Floor partition:
+ *            subdomain coordinate along x = floor(ix * nsub[0] / nx), likewise y, z;
+ *            subdomain id s = sx + nsub[0] * (sy + nsub[1] * sz).
+ *   thr      host[nthr] float64, ascending: class of a cell = #{t : K >= t}.
+ *   nthr     0..PSL_MAX_THRESHOLDS.
+ *   cls      dev[n] int32 or NULL: manual classes in [0, ncls) (the paper's hand-built
+ *            layer indicators); when given, thr/nthr are ignored.
+ *   ncls     number of manual classes (1..PSL_MAX_THRESHOLDS+1) when cls != NULL.
+ *   labels   dev out [n] int32: column of Z holding the cell, in [0, d).
+ *   d        host out: number of deflation vectors.
+ * The column of a cell is the rank of key = s * ncls + class among the keys that occur
+ * (empty regions get no column, so Z has full rank). Integer result, bit-exact.
+ * Errors: PSL_EINVAL (bad sizes, nsub out of range, unsorted thr, class out of range
+ * is not checked: a manual class outside [0, ncls) gives an undefined labelling).
+ */
+int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
+                const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                int32_t* labels, int32_t* d, void* stream);
+
+/*
+ * psl_setup_E -- build the deflation operators once (Definition 3.1): copies of the
+ * transmissibilities, diag(A), the interface rows of A Z, E = Z^T A Z assembled in
+ * float64 from the faces, its Cholesky factor E = L L^T and E^-1 (float64).
+ *   ctx      host out: new context (free with psl_destroy).
+ *   g        host: grid.   Tx, Ty, Tz: dev face arrays (copied; caller may free them).
+ *   labels   dev[n] int32 in [0, d) (copied; any labelling is accepted, not only the
+ *            output of psl_build_Z, but every column must be non-empty).
+ *   d        1..PSL_MAX_DENSE_D.
+ *   nsub     host[3] or NULL: the subdomain partition used to cut the grid into
+ *            work tiles (one subdomain maps to one or more workgroups; the parallel
+ *            subdomain-per-processor layout of Section 3.2 moved onto compute units).
+ *            NULL lets the library choose boxes of about 16x16x8 cells.
+ * Errors: PSL_EINVAL, PSL_ENOMEM, PSL_ENOTSPD (a cell with diag(A) <= 0 or E not SPD),
+ * PSL_ENOTSUP (d > PSL_MAX_DENSE_D).
+ */
+int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double* Ty,
+                const double* Tz, const int32_t* labels, int32_t d, const int32_t nsub[3],
+                void* stream);
+
+/*
+ * psl_solve -- solve A x = b (eq. "coupledsys", reservoir block) with Jacobi-
+ * preconditioned CG on the deflated system P1 A xhat = P1 b (eqs. "deflops", "defsys";
+ * E built from A itself, Remark 3.1) and the projection back x = Z E^-1 Z^T b + P2 xhat
+ * (eq. "projectback"), inside a float64 refinement loop: r = b - A x;
+ * x += Z E^-1 Z^T r; r = P1 r; stop if ||r|| <= tol ||b||; else CG on the scaled r
+ * (float32 in PSL_MIXED, float64 in PSL_FP64) and x += ||r|| xhat.
+ *   ctx   context from psl_setup_E.
+ *   b     dev[n] float64 right-hand side (not modified).
+ *   x     dev[n] float64: start vector on entry if o->use_x0, solution on exit.
+ *   o     host options (NULL = defaults).
+ *   st    host out statistics (may be NULL).
+ * An inner CG that stops improving (rounding floor: (p, P1 A p) <= 0, or no halving of
+ * ||rhat|| over 512 iterations) returns to the refinement loop, which restarts it from
+ * the new float64 residual; in PSL_MIXED a refinement step that does not halve the
+ * float64 residual switches the remaining steps to float64 CG (stats.fell_back = 1).
+ * Returns PSL_OK when ||b - A x|| <= tol ||b|| was reached; otherwise PSL_EMAXIT
+ * (iteration or refinement cap; x is the projected last iterate), PSL_ESTAGNATION
+ * (float64 refinement stopped reducing the residual), PSL_EBREAKDOWN (breakdown on the
+ * first iteration of a refinement step) or PSL_ENONFINITE. ||b|| = 0 gives x = 0, PSL_OK.
+ */
+int psl_solve(psl_ctx* ctx, const double* b, double* x, const psl_solve_opts* o,
+              psl_solve_stats* st, void* stream);
+
+/*
+ * psl_apply_A -- q = A p in float64 (the stencil product used by every solve; the
+ * matrix-vector product of Algorithm 1). p, q: dev[n] float64, distinct arrays.
+ */
+int psl_apply_A(psl_ctx* ctx, const double* p, double* q, void* stream);
+
+/*
+ * psl_deflate -- apply the deflation operators to one vector (eq. "deflops"):
+ *   c = E^-1 Z^T r (host-independent, dev[d] out, may be NULL),
+ *   out = P1 r = r - A Z c (dev[n] out, may alias r).
+ * Used to check the coarse solve and the projector; r: dev[n] float64.
+ */
+int psl_deflate(psl_ctx* ctx, const double* r, double* out, double* c, void* stream);
+
+/*
+ * psl_get_coarse -- copy E (float64, d x d, row-major) and/or E^-1 into caller device
+ * memory (either pointer may be NULL). d is returned in *d when d != NULL.
+ */
+int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stream);
+
+/* Release everything the context owns. NULL is ignored. */
+void psl_destroy(psl_ctx* ctx);
+
+/* Static string naming a status code. */
+const char* psl_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSL_H */

@@ -1,0 +1,169 @@
+// Internal declarations shared by the libpsl translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <vector>
+
+#include "../../include/psl.h"
+
+namespace psl {
+
+constexpr int kBlock = 256;          // threads per workgroup for every cell kernel
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kMaxSlots = PSL_MAX_TILE_LABELS;
+
+// Work tile: a box of cells inside one subdomain; one workgroup per tile.
+struct Tile {
+  int32_t x0, y0, z0;   // first cell
+  int32_t sx, sy, sz;   // extent
+  int32_t ncell;        // sx*sy*sz
+  int32_t nslot;        // distinct labels in the tile
+};
+
+// Device-resident scalars of one solve; read and written only by kernels.
+struct Scalars {
+  double rho;        // (rhat, M^-1 rhat)
+  double alpha;
+  double beta;
+  double pq;         // (p, A p)
+  double se;         // s^T e
+  double rr;         // ||rhat||^2
+  double goal2;      // inner stop: ||rhat||^2 <= goal2
+  double rnorm;      // FP64 outer residual norm
+  double sigma;      // inner scale: rhat0 = sigma * r
+  double bnorm2;
+  int32_t done;      // inner loop finished (converged or failed)
+  int32_t iters;     // inner iterations done in this inner solve
+  int32_t status;    // PSL_OK or failure code raised on device
+  int32_t maxit;     // remaining iteration budget for this inner solve
+  uint32_t cnt_a;    // last-block counters (reset by the last block)
+  uint32_t cnt_b;
+  uint32_t cnt_c;
+  uint32_t pad;
+};
+
+template <typename R>
+struct VecSet {       // inner CG vectors in precision R
+  R* xh = nullptr;
+  R* rh = nullptr;
+  R* p = nullptr;
+  R* q = nullptr;
+};
+
+}  // namespace psl
+
+struct psl_ctx {
+  int dev = 0;
+  int nx = 0, ny = 0, nz = 0;
+  int64_t n = 0;
+  int d = 0;
+  int ntiles = 0;
+  int nslot_max = 0;
+  int nsub[3] = {1, 1, 1};
+  // operator data (owned copies)
+  double *Tx = nullptr, *Ty = nullptr, *Tz = nullptr;
+  float *Tx32 = nullptr, *Ty32 = nullptr, *Tz32 = nullptr;
+  double* invdiag = nullptr;
+  float* invdiag32 = nullptr;
+  int32_t* labels = nullptr;
+  // tiling
+  psl::Tile* tiles = nullptr;
+  std::vector<psl::Tile> h_tiles;
+  uint8_t* slot = nullptr;            // [n] slot of the cell's label within its tile
+  int32_t* tile_lab = nullptr;        // [ntiles*kMaxSlots] label of each slot, -1 unused
+  int32_t* lab_ptr = nullptr;         // [d+1] CSR: partial indices contributing to label
+  int32_t* lab_part = nullptr;        // [ntiles*kMaxSlots] tile*kMaxSlots+slot
+  // cut faces of A Z (faces between labels, and Dirichlet faces), grouped by tile and cell
+  int32_t* az_ptr = nullptr;          // [ntiles+1]
+  int32_t* az_cell = nullptr;         // [m] local cell index in the tile; bit 31 = first face of its cell
+  int32_t* az_lab = nullptr;          // [m] label of the cell
+  int32_t* az_oth = nullptr;          // [m] label across the face, -1 for an outer face
+  double* az_t = nullptr;             // [m] face transmissibility
+  float* az_t32 = nullptr;            // [m]
+  int64_t m_az = 0;
+  // coarse operator
+  double* E = nullptr;                // [d*d] row-major
+  double* Einv = nullptr;             // [d*d]
+  int coarse_rows_per_block = 8;
+  int coarse_blocks = 1;
+  // work
+  double* zq_part = nullptr;          // [ntiles*kMaxSlots] partials of Z^T q
+  double* zr_part = nullptr;          // [ntiles*kMaxSlots] partials of Z^T rhat
+  double* red_part = nullptr;         // [ntiles*4]
+  double* s = nullptr;                // [d]
+  double* e = nullptr;                // [d]
+  double* sr = nullptr;               // [d] Z^T rhat
+  double* er = nullptr;               // [d] E^-1 Z^T rhat
+  double* se_part = nullptr;          // [coarse_blocks]
+  double* r64 = nullptr;              // [n] FP64 outer residual
+  double* t64 = nullptr;              // [n] FP64 scratch
+  psl::Scalars* sc = nullptr;
+  psl::Scalars* h_sc = nullptr;       // pinned host mirror
+  psl::VecSet<double> v64;
+  psl::VecSet<float> v32;
+  // captured iteration chunks, one per precision
+  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  hipStream_t graph_stream64 = nullptr, graph_stream32 = nullptr;
+  int graph_chunk64 = 0, graph_chunk32 = 0;
+};
+
+#define PSL_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t _e = (call);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      std::fprintf(stderr, "libpsl: %s failed: %s (%s:%d)\n", #call,              \
+                   hipGetErrorString(_e), __FILE__, __LINE__);                     \
+      return PSL_EHIP;                                                             \
+    }                                                                              \
+  } while (0)
+
+namespace psl {
+
+// ---- reductions ----------------------------------------------------------------------
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block-wide sum of NV values per thread in a fixed tree order; result valid in
+// every thread. lds must hold NV * (kBlock / kWave) doubles.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  constexpr int NW = kBlock / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k * NW + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc += lds[k * NW + j];
+    v[k] = acc;
+  }
+  __syncthreads();
+}
+
+// j / d for 0 <= j < 2^22, 1 <= d <= 2^11, via a float reciprocal with exact fix-up.
+__device__ inline int div_small(int j, int d, float inv) {
+  int q = static_cast<int>(static_cast<float>(j) * inv);
+  if ((q + 1) * d <= j) ++q;
+  if (q * d > j) --q;
+  return q;
+}
+
+}  // namespace psl
+
+// host-side helpers implemented in psl_setup.hip
+int psl_internal_alloc(void** p, size_t bytes);

@@ -1,0 +1,1036 @@
+// libpsl set-up path: transmissibilities, subdomain-levelset labels, the work tiling,
+// the interface rows of A Z, E = Z^T A Z and its float64 Cholesky factor and inverse.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "psl_internal.hpp"
+
+using psl::kBlock;
+using psl::kMaxSlots;
+using psl::Tile;
+
+// ---------------------------------------------------------------------------------------
+// status strings and defaults
+// ---------------------------------------------------------------------------------------
+extern "C" const char* psl_status_str(int s) {
+  switch (s) {
+    case PSL_OK: return "ok";
+    case PSL_EINVAL: return "invalid argument";
+    case PSL_ENOMEM: return "device allocation failed";
+    case PSL_EHIP: return "HIP runtime error";
+    case PSL_ENOTSPD: return "matrix not positive definite";
+    case PSL_EMAXIT: return "iteration cap reached";
+    case PSL_EBREAKDOWN: return "CG breakdown (p^T P1 A p <= 0)";
+    case PSL_ENONFINITE: return "non-finite value in input or iterate";
+    case PSL_ESTAGNATION: return "refinement stagnated";
+    case PSL_ENOTSUP: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+extern "C" void psl_default_opts(psl_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->maxit = 10000;
+  o->mode = PSL_FP64;
+  o->use_x0 = 0;
+  o->max_outer = 30;
+  o->tau_inner = 1e-4;
+  o->check_every = 16;
+  o->reproject = -1;
+}
+
+int psl_internal_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return PSL_ENOMEM;
+  }
+  return PSL_OK;
+}
+
+static bool grid_ok(const psl_grid* g) {
+  if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
+  const int64_t n = int64_t(g->nx) * g->ny * g->nz;
+  // faces and cells are indexed with int32 inside kernels
+  const int64_t faces = int64_t(g->nx + 1) * g->ny * g->nz;
+  return n <= (int64_t(1) << 30) && faces < (int64_t(1) << 31) &&
+         int64_t(g->nx) * (g->ny + 1) * g->nz < (int64_t(1) << 31) &&
+         int64_t(g->nx) * g->ny * (g->nz + 1) < (int64_t(1) << 31);
+}
+
+static inline unsigned nblocks(int64_t work, int per = kBlock) {
+  return static_cast<unsigned>((work + per - 1) / per);
+}
+
+template <typename T>
+__global__ void k_fill(T* a, T v, int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// transmissibilities (two-point flux, harmonic mean)
+// ---------------------------------------------------------------------------------------
+__device__ inline double harmonic_face(double a, double b) {
+  const double s = a + b;
+  return s > 0.0 ? 2.0 * a * b / s : 0.0;
+}
+
+// axis 0: faces (nx+1) x ny x nz ; axis 1: nx x (ny+1) x nz ; axis 2: nx x ny x (nz+1)
+__global__ void k_tpfa(const double* __restrict__ K, double* __restrict__ T, int axis,
+                       int nx, int ny, int nz, int lo_dirichlet, int hi_dirichlet) {
+  const int fx = nx + (axis == 0), fy = ny + (axis == 1), fz = nz + (axis == 2);
+  const int nf = fx * fy * fz;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int ix = f % fx;
+  const int iy = (f / fx) % fy;
+  const int iz = f / (fx * fy);
+  const int m = axis == 0 ? ix : (axis == 1 ? iy : iz);          // face coordinate
+  const int ext = axis == 0 ? nx : (axis == 1 ? ny : nz);
+  const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+  // cell on the high side of the face (coordinate m), and on the low side (m-1)
+  const int cx = axis == 0 ? 0 : ix, cy = axis == 1 ? 0 : iy, cz = axis == 2 ? 0 : iz;
+  const int base = cx + nx * (cy + ny * cz);
+  double t;
+  if (m == 0) {
+    t = lo_dirichlet ? 2.0 * K[base] : 0.0;
+  } else if (m == ext) {
+    t = hi_dirichlet ? 2.0 * K[base + (ext - 1) * stride] : 0.0;
+  } else {
+    t = harmonic_face(K[base + (m - 1) * stride], K[base + m * stride]);
+  }
+  T[f] = t;
+}
+
+extern "C" int psl_assemble_tpfa(const psl_grid* g, const double* K, uint32_t mask,
+                                 double* Tx, double* Ty, double* Tz, void* stream) {
+  if (!grid_ok(g) || !K || !Tx || !Ty || !Tz || (mask & ~63u)) return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  double* T[3] = {Tx, Ty, Tz};
+  for (int a = 0; a < 3; ++a) {
+    const int64_t nf = int64_t(nx + (a == 0)) * (ny + (a == 1)) * (nz + (a == 2));
+    hipLaunchKernelGGL(k_tpfa, dim3(nblocks(nf)), dim3(kBlock), 0, st, K, T[a], a, nx, ny,
+                       nz, int((mask >> (2 * a)) & 1u), int((mask >> (2 * a + 1)) & 1u));
+  }
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// subdomain-levelset labels
+// ---------------------------------------------------------------------------------------
+struct ThrPack {
+  double t[PSL_MAX_THRESHOLDS];
+  int nthr;
+};
+
+__device__ inline int cell_key(int c, int nx, int ny, int nz, int sx, int sy, int sz, int ncls,
+                               const double* K, const int32_t* cls, const ThrPack& thr) {
+  const int ix = c % nx, iy = (c / nx) % ny, iz = c / (nx * ny);
+  const int bx = int((int64_t(ix) * sx) / nx);
+  const int by = int((int64_t(iy) * sy) / ny);
+  const int bz = int((int64_t(iz) * sz) / nz);
+  const int s = bx + sx * (by + sy * bz);
+  int k;
+  if (cls) {
+    k = cls[c];
+  } else {
+    const double v = K[c];
+    k = 0;
+    for (int t = 0; t < thr.nthr; ++t) k += (v >= thr.t[t]) ? 1 : 0;
+  }
+  return s * ncls + k;
+}
+
+__global__ void k_key_present(int n, int nx, int ny, int nz, int sx, int sy, int sz, int ncls,
+                              const double* K, const int32_t* cls, ThrPack thr,
+                              int32_t* present, int nkeys, int32_t* bad) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int key = cell_key(c, nx, ny, nz, sx, sy, sz, ncls, K, cls, thr);
+  if (key < 0 || key >= nkeys) {
+    bad[0] = 1;
+    return;
+  }
+  present[key] = 1;
+}
+
+__global__ void k_key_rank(int n, int nx, int ny, int nz, int sx, int sy, int sz, int ncls,
+                           const double* K, const int32_t* cls, ThrPack thr,
+                           const int32_t* rank, int nkeys, int32_t* labels) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int key = cell_key(c, nx, ny, nz, sx, sy, sz, ncls, K, cls, thr);
+  labels[c] = (key >= 0 && key < nkeys) ? rank[key] : -1;
+}
+
+// Exclusive prefix sum of int32 counts in one workgroup of 1024 threads (set-up sizes).
+// out[m] = total.
+__global__ void __launch_bounds__(1024) k_scan_small(const int32_t* in, int32_t* out, int m) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (m + 1023) / 1024;
+  const int a = min(m, t * chunk), b = min(m, a + chunk);
+  int32_t s = 0;
+  for (int i = a; i < b; ++i) s += in[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - s;
+  for (int i = a; i < b; ++i) {
+    const int32_t v = in[i];
+    out[i] = run;
+    run += v;
+  }
+  if (t == 1023) out[m] = part[1023];
+}
+
+extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
+                           const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                           int32_t* labels, int32_t* d, void* stream) {
+  if (!grid_ok(g) || !nsub || !labels || !d) return PSL_EINVAL;
+  if (!cls && !K) return PSL_EINVAL;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int ext[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    if (nsub[a] < 1 || nsub[a] > ext[a]) return PSL_EINVAL;
+  ThrPack tp{};
+  if (cls) {
+    if (ncls < 1 || ncls > PSL_MAX_THRESHOLDS + 1) return PSL_EINVAL;
+    tp.nthr = 0;
+  } else {
+    if (nthr < 0 || nthr > PSL_MAX_THRESHOLDS || (nthr > 0 && !thr)) return PSL_EINVAL;
+    for (int t = 0; t < nthr; ++t) {
+      if (!std::isfinite(thr[t])) return PSL_EINVAL;
+      if (t > 0 && !(thr[t] > thr[t - 1])) return PSL_EINVAL;
+      tp.t[t] = thr[t];
+    }
+    tp.nthr = nthr;
+    ncls = nthr + 1;
+  }
+  const int64_t nkeys64 = int64_t(nsub[0]) * nsub[1] * nsub[2] * ncls;
+  if (nkeys64 > (int64_t(1) << 26)) return PSL_ENOTSUP;
+  const int nkeys = int(nkeys64);
+  const int n = nx * ny * nz;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t *present = nullptr, *rank = nullptr, *bad = nullptr;
+  int rc = psl_internal_alloc((void**)&present, sizeof(int32_t) * nkeys);
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&rank, sizeof(int32_t) * (nkeys + 1));
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bad, sizeof(int32_t));
+  if (rc != PSL_OK) {
+    (void)hipFree(present);
+    (void)hipFree(rank);
+    (void)hipFree(bad);
+    return rc;
+  }
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nkeys)), dim3(kBlock), 0, st, present, 0,
+                     int64_t(nkeys));
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, bad, 0, int64_t(1));
+  hipLaunchKernelGGL(k_key_present, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz,
+                     nsub[0], nsub[1], nsub[2], ncls, K, cls, tp, present, nkeys, bad);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, present, rank, nkeys);
+  hipLaunchKernelGGL(k_key_rank, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, nsub[0],
+                     nsub[1], nsub[2], ncls, K, cls, tp, rank, nkeys, labels);
+  int32_t h[2] = {0, 0};
+  hipError_t e1 = hipMemcpyAsync(&h[0], rank + nkeys, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipMemcpyAsync(&h[1], bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  hipError_t e3 = hipStreamSynchronize(st);
+  (void)hipFree(present);
+  (void)hipFree(rank);
+  (void)hipFree(bad);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return PSL_EHIP;
+  if (h[1]) return PSL_EINVAL;  // a manual class outside [0, ncls)
+  *d = h[0];
+  return PSL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// psl_setup_E kernels
+// ---------------------------------------------------------------------------------------
+struct GridDev {
+  int nx, ny, nz;
+};
+
+// diag(A) = sum of the six face transmissibilities of the cell; its inverse in both
+// precisions; flags a cell whose diagonal is not a positive finite number.
+__global__ void k_diag(GridDev g, const double* __restrict__ Tx, const double* __restrict__ Ty,
+                       const double* __restrict__ Tz, double* invd, float* invd32,
+                       int32_t* bad) {
+  const int n = g.nx * g.ny * g.nz;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+  const int fx = ix + (g.nx + 1) * (iy + g.ny * iz);
+  const int fy = ix + g.nx * (iy + (g.ny + 1) * iz);
+  const int fz = c;
+  const int sz = g.nx * g.ny;
+  const double dg = Tx[fx] + Tx[fx + 1] + Ty[fy] + Ty[fy + g.nx] + Tz[fz] + Tz[fz + sz];
+  if (!(dg > 0.0) || !(dg < INFINITY)) bad[0] = 1;
+  const double inv = 1.0 / dg;
+  invd[c] = inv;
+  invd32[c] = static_cast<float>(inv);
+}
+
+__global__ void k_check_labels(const int32_t* __restrict__ labels, int n, int d, int32_t* bad) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && (labels[c] < 0 || labels[c] >= d)) bad[0] = 1;
+}
+
+__global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<float>(a[i]);
+}
+
+// Per tile: sorted distinct labels (up to kMaxSlots; more is flagged), and for every
+// cell the index of its label in that list.
+__global__ void __launch_bounds__(kBlock) k_tile_labels(GridDev g, const Tile* tiles,
+                                                        const int32_t* __restrict__ labels,
+                                                        int32_t* tile_lab, Tile* tiles_out,
+                                                        uint8_t* slot, int32_t* overflow) {
+  __shared__ int32_t red[kBlock / psl::kWave];
+  __shared__ int32_t list[kMaxSlots];
+  __shared__ int32_t cnt_s;
+  const Tile T = tiles[blockIdx.x];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  int prev = -1;
+  int cnt = 0;
+  for (;;) {
+    int best = 0x7fffffff;
+    for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+      const int lz = psl::div_small(j, T.sx * T.sy, inv_sxy);
+      const int rem = j - lz * T.sx * T.sy;
+      const int ly = psl::div_small(rem, T.sx, inv_sx);
+      const int lx = rem - ly * T.sx;
+      const int c = (T.x0 + lx) + g.nx * ((T.y0 + ly) + g.ny * (T.z0 + lz));
+      const int l = labels[c];
+      if (l > prev && l < best) best = l;
+    }
+    for (int off = psl::kWave / 2; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+    if ((threadIdx.x & (psl::kWave - 1)) == 0) red[threadIdx.x / psl::kWave] = best;
+    __syncthreads();
+    int m = red[0];
+    for (int w = 1; w < kBlock / psl::kWave; ++w) m = min(m, red[w]);
+    __syncthreads();
+    if (m == 0x7fffffff) break;
+    if (cnt == kMaxSlots) {
+      cnt = kMaxSlots + 1;
+      break;
+    }
+    if (threadIdx.x == 0) list[cnt] = m;
+    ++cnt;
+    prev = m;
+  }
+  if (threadIdx.x == 0) {
+    cnt_s = cnt;
+    if (cnt > kMaxSlots) overflow[0] = 1;
+  }
+  __syncthreads();
+  cnt = min(cnt_s, kMaxSlots);
+  if (threadIdx.x < kMaxSlots)
+    tile_lab[blockIdx.x * kMaxSlots + threadIdx.x] = threadIdx.x < cnt ? list[threadIdx.x] : -1;
+  if (threadIdx.x == 0) {
+    Tile o = T;
+    o.nslot = cnt;
+    tiles_out[blockIdx.x] = o;
+  }
+  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+    const int lz = psl::div_small(j, T.sx * T.sy, inv_sxy);
+    const int rem = j - lz * T.sx * T.sy;
+    const int ly = psl::div_small(rem, T.sx, inv_sx);
+    const int lx = rem - ly * T.sx;
+    const int c = (T.x0 + lx) + g.nx * ((T.y0 + ly) + g.ny * (T.z0 + lz));
+    const int l = labels[c];
+    int k = 0;
+    for (int s = 0; s < cnt; ++s)
+      if (list[s] == l) k = s;
+    slot[c] = static_cast<uint8_t>(k);
+  }
+}
+
+// label -> (tile, slot) lists: count, fill at atomic cursors, then sort each list.
+__global__ void k_lab_count(const int32_t* tile_lab, int nparts, int32_t* cnt, int d,
+                            int32_t* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nparts) return;
+  const int l = tile_lab[i];
+  if (l < 0) return;
+  if (l >= d) {
+    bad[0] = 1;
+    return;
+  }
+  atomicAdd(&cnt[l], 1);
+}
+
+__global__ void k_lab_fill(const int32_t* tile_lab, int nparts, const int32_t* ptr,
+                           int32_t* cursor, int32_t* part, int d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nparts) return;
+  const int l = tile_lab[i];
+  if (l < 0 || l >= d) return;
+  const int pos = atomicAdd(&cursor[l], 1);
+  part[ptr[l] + pos] = i;
+}
+
+__global__ void k_lab_sort(const int32_t* ptr, int32_t* part, int d, int32_t* empty) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= d) return;
+  const int a = ptr[l], b = ptr[l + 1];
+  if (a == b) empty[0] = 1;  // a column of Z without cells
+  for (int i = a + 1; i < b; ++i) {
+    const int v = part[i];
+    int j = i - 1;
+    while (j >= a && part[j] > v) {
+      part[j + 1] = part[j];
+      --j;
+    }
+    part[j + 1] = v;
+  }
+}
+
+// Cut faces of A Z. A face f of cell i with T_f > 0 is "cut" when it is an outer face or
+// its neighbour j carries another label. Then
+//   (A Z e)_i = sum over the cut faces of i of T_f (e_l(i) - e_l(j))   (e_l(j) = 0 outside),
+// the flux form of A (Z e), which keeps the cancellation between neighbouring coarse
+// values exact instead of summing rounded per-label coefficients. Cells with no cut face
+// have (A Z)_i = 0 and no entry. Entries of one cell are contiguous, in face order
+// (-x, +x, -y, +y, -z, +z); the first carries bit 31 in az_cell.
+struct CutFaces {
+  int n;
+  int oth[6];
+  double t[6];
+};
+
+__device__ inline void cut_faces(GridDev g, const double* __restrict__ Tx,
+                                 const double* __restrict__ Ty, const double* __restrict__ Tz,
+                                 const int32_t* __restrict__ labels, int c, CutFaces& cf) {
+  const int ix = c % g.nx, iy = (c / g.nx) % g.ny, iz = c / (g.nx * g.ny);
+  const int fx = ix + (g.nx + 1) * (iy + g.ny * iz);
+  const int fy = ix + g.nx * (iy + (g.ny + 1) * iz);
+  const int sxy = g.nx * g.ny;
+  const int li = labels[c];
+  const double tf[6] = {Tx[fx], Tx[fx + 1], Ty[fy], Ty[fy + g.nx], Tz[c], Tz[c + sxy]};
+  const int nb[6] = {ix > 0 ? c - 1 : -1,       ix < g.nx - 1 ? c + 1 : -1,
+                     iy > 0 ? c - g.nx : -1,    iy < g.ny - 1 ? c + g.nx : -1,
+                     iz > 0 ? c - sxy : -1,     iz < g.nz - 1 ? c + sxy : -1};
+  cf.n = 0;
+  for (int f = 0; f < 6; ++f) {
+    if (tf[f] == 0.0) continue;
+    const int lj = nb[f] < 0 ? -1 : labels[nb[f]];
+    if (lj == li) continue;
+    cf.oth[cf.n] = lj;
+    cf.t[cf.n] = tf[f];
+    ++cf.n;
+  }
+}
+
+__device__ inline int tile_cell(GridDev g, const Tile& T, int j, float inv_sx, float inv_sxy) {
+  const int lz = psl::div_small(j, T.sx * T.sy, inv_sxy);
+  const int rem = j - lz * T.sx * T.sy;
+  const int ly = psl::div_small(rem, T.sx, inv_sx);
+  const int lx = rem - ly * T.sx;
+  return (T.x0 + lx) + g.nx * ((T.y0 + ly) + g.ny * (T.z0 + lz));
+}
+
+__global__ void __launch_bounds__(kBlock) k_az_count(GridDev g, const Tile* tiles,
+                                                     const double* Tx, const double* Ty,
+                                                     const double* Tz, const int32_t* labels,
+                                                     int32_t* tile_cnt) {
+  __shared__ double red[kBlock / psl::kWave];
+  const Tile T = tiles[blockIdx.x];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  double cnt = 0;
+  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+    CutFaces cf;
+    cut_faces(g, Tx, Ty, Tz, labels, tile_cell(g, T, j, inv_sx, inv_sxy), cf);
+    cnt += cf.n;
+  }
+  double v[1] = {cnt};
+  psl::block_sum<1>(v, red);
+  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = static_cast<int32_t>(v[0]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_az_fill(GridDev g, const Tile* tiles,
+                                                    const double* Tx, const double* Ty,
+                                                    const double* Tz, const int32_t* labels,
+                                                    const int32_t* az_ptr, int32_t* az_cell,
+                                                    int32_t* az_lab, int32_t* az_oth,
+                                                    double* az_t, float* az_t32) {
+  __shared__ int32_t wsum[kBlock / psl::kWave];
+  __shared__ int32_t base_s;
+  const Tile T = tiles[blockIdx.x];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  const int lane = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
+  if (threadIdx.x == 0) base_s = az_ptr[blockIdx.x];
+  __syncthreads();
+  for (int j0 = 0; j0 < T.ncell; j0 += kBlock) {
+    const int j = j0 + threadIdx.x;
+    CutFaces cf;
+    cf.n = 0;
+    int c = 0;
+    if (j < T.ncell) {
+      c = tile_cell(g, T, j, inv_sx, inv_sxy);
+      cut_faces(g, Tx, Ty, Tz, labels, c, cf);
+    }
+    // block-exclusive prefix of cf.n in thread order
+    int incl = cf.n;
+    for (int off = 1; off < psl::kWave; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == psl::kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < kBlock / psl::kWave; ++k) {
+      if (k < w) before += wsum[k];
+      total += wsum[k];
+    }
+    const int pos = base_s + before + incl - cf.n;
+    const int li = cf.n ? labels[c] : 0;
+    for (int k = 0; k < cf.n; ++k) {
+      az_cell[pos + k] = j | (k == 0 ? int32_t(0x80000000u) : 0);
+      az_lab[pos + k] = li;
+      az_oth[pos + k] = cf.oth[k];
+      az_t[pos + k] = cf.t[k];
+      az_t32[pos + k] = static_cast<float>(cf.t[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base_s += total;
+    __syncthreads();
+  }
+}
+
+// E row l = sum over the cells of label l of their A Z rows: each cut face adds T to
+// E[l][l] and -T to E[l][other]. One workgroup per row; column c is accumulated only by
+// thread c % kBlock, in a fixed scan order (deterministic).
+constexpr int kEChunk = 4096;
+__global__ void __launch_bounds__(kBlock) k_E_rows(GridDev g, const Tile* tiles,
+                                                   const int32_t* lab_ptr,
+                                                   const int32_t* lab_part,
+                                                   const int32_t* az_ptr,
+                                                   const int32_t* az_lab,
+                                                   const int32_t* az_oth,
+                                                   const double* az_t, double* E, int d) {
+  __shared__ double rowbuf[kEChunk];
+  const int l = blockIdx.x;
+  for (int c0 = 0; c0 < d; c0 += kEChunk) {
+    const int c1 = min(d, c0 + kEChunk);
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) rowbuf[c - c0] = 0.0;
+    __syncthreads();
+    const bool own_diag = (l >= c0 && l < c1 && (l % kBlock) == threadIdx.x);
+    for (int pi = lab_ptr[l]; pi < lab_ptr[l + 1]; ++pi) {
+      const int tile = lab_part[pi] / kMaxSlots;
+      for (int k = az_ptr[tile]; k < az_ptr[tile + 1]; ++k) {
+        if (az_lab[k] != l) continue;
+        const double t = az_t[k];
+        if (own_diag) rowbuf[l - c0] += t;
+        const int o = az_oth[k];
+        if (o >= c0 && o < c1 && (o % kBlock) == threadIdx.x) rowbuf[o - c0] -= t;
+      }
+    }
+    __syncthreads();
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) E[int64_t(l) * d + c] = rowbuf[c - c0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// dense float64 Cholesky E = L L^T (lower, in place) and E^-1 = L^-T L^-1
+// ---------------------------------------------------------------------------------------
+constexpr int kNB = 64;
+
+// factor the kb diagonal block in LDS; flags a non-positive pivot
+__global__ void __launch_bounds__(kBlock) k_potrf_diag(double* A, int d, int kb, int32_t* bad) {
+  __shared__ double a[kNB][kNB + 1];
+  const int nb = min(kNB, d - kb);
+  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
+    const int i = t / nb, j = t % nb;
+    a[i][j] = A[int64_t(kb + i) * d + kb + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (threadIdx.x == 0) {
+      const double p = a[k][k];
+      if (!(p > 0.0) || !(p < INFINITY)) bad[0] = 1;
+      a[k][k] = sqrt(p > 0.0 ? p : 1.0);
+    }
+    __syncthreads();
+    const double piv = a[k][k];
+    for (int i = k + 1 + threadIdx.x; i < nb; i += kBlock) a[i][k] /= piv;
+    __syncthreads();
+    const int m = nb - k - 1;
+    for (int t = threadIdx.x; t < m * m; t += kBlock) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j <= i) a[i][j] -= a[i][k] * a[j][k];
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
+    const int i = t / nb, j = t % nb;
+    A[int64_t(kb + i) * d + kb + j] = (j <= i) ? a[i][j] : 0.0;
+  }
+}
+
+// rows below the diagonal block: L[i, kb:kb+nb] = A[i, kb:kb+nb] L_kk^-T (one row per thread)
+__global__ void __launch_bounds__(kBlock) k_trsm_panel(double* A, int d, int kb) {
+  __shared__ double l[kNB][kNB + 1];
+  const int nb = min(kNB, d - kb);
+  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
+    const int i = t / nb, j = t % nb;
+    l[i][j] = A[int64_t(kb + i) * d + kb + j];
+  }
+  __syncthreads();
+  const int i = kb + nb + blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d) return;
+  double x[kNB];
+  double* row = A + int64_t(i) * d + kb;
+  for (int j = 0; j < nb; ++j) {
+    double v = row[j];
+    for (int m = 0; m < j; ++m) v -= x[m] * l[j][m];
+    x[j] = v / l[j][j];
+  }
+  for (int j = 0; j < nb; ++j) row[j] = x[j];
+}
+
+// C[i][j] -= sum_k A(i,k) B(k,j) for a 64x64 output tile per workgroup, K <= kNB.
+// AM = 0: A(i,k) = A[i*lda + k]; AM = 1: A(i,k) = A[k*lda + i].
+// BM = 0: B(k,j) = B[k*ldb + j]; BM = 1: B(k,j) = B[j*ldb + k].
+// LOWER: only entries with j <= i are updated (tiles wholly above the diagonal exit).
+template <int AM, int BM, int LOWER>
+__global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const double* A,
+                                                     int lda, const double* B, int ldb, int M,
+                                                     int N, int K) {
+  __shared__ double sa[kNB][64 + 1];  // sa[k][i]
+  __shared__ double sb[kNB][64 + 1];  // sb[k][j]
+  const int ti = blockIdx.y * 64, tj = blockIdx.x * 64;
+  if (LOWER && tj > ti + 63) return;
+  for (int t = threadIdx.x; t < K * 64; t += kBlock) {
+    // walk the contiguous dimension of each operand fastest
+    const int ka = AM ? t / 64 : t % K, ra = AM ? t % 64 : t / K;
+    const int kb = BM ? t % K : t / 64, rb = BM ? t / K : t % 64;
+    const int i = ti + ra, j = tj + rb;
+    sa[ka][ra] = i < M ? (AM ? A[int64_t(ka) * lda + i] : A[int64_t(i) * lda + ka]) : 0.0;
+    sb[kb][rb] = j < N ? (BM ? B[int64_t(j) * ldb + kb] : B[int64_t(kb) * ldb + j]) : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[4][4] = {};
+  for (int k = 0; k < K; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = sa[k][ty + 16 * u];
+      b[u] = sb[k][tx + 16 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + ty + 16 * u, j = tj + tx + 16 * v;
+      if (i < M && j < N && (!LOWER || j <= i)) C[int64_t(i) * ldc + j] -= acc[u][v];
+    }
+}
+
+// X[kb:kb+nb, :] = L_kk^-1 X[kb:kb+nb, :] (trans = 0) or L_kk^-T X[...] (trans = 1);
+// one column per thread.
+__global__ void __launch_bounds__(kBlock) k_trsm_cols(const double* L, double* X, int d, int kb,
+                                                      int trans) {
+  __shared__ double l[kNB][kNB + 1];
+  const int nb = min(kNB, d - kb);
+  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
+    const int i = t / nb, j = t % nb;
+    l[i][j] = L[int64_t(kb + i) * d + kb + j];
+  }
+  __syncthreads();
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= d) return;
+  double x[kNB];
+  for (int j = 0; j < nb; ++j) x[j] = X[int64_t(kb + j) * d + c];
+  if (!trans) {
+    for (int j = 0; j < nb; ++j) {
+      double v = x[j];
+      for (int m = 0; m < j; ++m) v -= l[j][m] * x[m];
+      x[j] = v / l[j][j];
+    }
+  } else {
+    for (int j = nb - 1; j >= 0; --j) {
+      double v = x[j];
+      for (int m = j + 1; m < nb; ++m) v -= l[m][j] * x[m];
+      x[j] = v / l[j][j];
+    }
+  }
+  for (int j = 0; j < nb; ++j) X[int64_t(kb + j) * d + c] = x[j];
+}
+
+__global__ void k_identity(double* X, int d) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(d) * d) return;
+  X[t] = (t / d == t % d) ? 1.0 : 0.0;
+}
+
+// E (in L, overwritten by its lower Cholesky factor) -> X = E^-1 = L^-T L^-1.
+// A non-positive pivot raises *bad.
+static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream_t st) {
+  for (int kb = 0; kb < d; kb += kNB) {
+    const int nb = std::min(kNB, d - kb);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kBlock), 0, st, L, d, kb, bad);
+    const int rest = d - kb - nb;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_trsm_panel, dim3(nblocks(rest)), dim3(kBlock), 0, st, L, d, kb);
+      const double* P = L + int64_t(kb + nb) * d + kb;   // rest x nb panel
+      double* C = L + int64_t(kb + nb) * d + kb + nb;    // trailing block
+      dim3 grid(nblocks(rest, 64), nblocks(rest, 64));
+      hipLaunchKernelGGL((k_gemm_sub<0, 1, 1>), grid, dim3(kBlock), 0, st, C, d, P, d, P, d,
+                         rest, rest, nb);
+    }
+  }
+  hipLaunchKernelGGL(k_identity, dim3(nblocks(int64_t(d) * d)), dim3(kBlock), 0, st, X, d);
+  // forward: L Y = I (Y lower triangular, block row kb has no entries right of kb+nb)
+  for (int kb = 0; kb < d; kb += kNB) {
+    const int nb = std::min(kNB, d - kb);
+    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d)), dim3(kBlock), 0, st, L, X, d, kb, 0);
+    const int rest = d - kb - nb;
+    if (rest > 0) {
+      const int ncol = kb + nb;
+      dim3 grid(nblocks(ncol, 64), nblocks(rest, 64));
+      hipLaunchKernelGGL((k_gemm_sub<0, 0, 0>), grid, dim3(kBlock), 0, st,
+                         X + int64_t(kb + nb) * d, d, L + int64_t(kb + nb) * d + kb, d,
+                         X + int64_t(kb) * d, d, rest, ncol, nb);
+    }
+  }
+  // backward: L^T X = Y
+  for (int kb = ((d - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {
+    const int nb = std::min(kNB, d - kb);
+    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d)), dim3(kBlock), 0, st, L, X, d, kb, 1);
+    if (kb > 0) {
+      dim3 grid(nblocks(d, 64), nblocks(kb, 64));
+      hipLaunchKernelGGL((k_gemm_sub<1, 0, 0>), grid, dim3(kBlock), 0, st, X, d,
+                         L + int64_t(kb) * d, d, X + int64_t(kb) * d, d, kb, d, nb);
+    }
+  }
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// work tiling: subdomain boxes of the floor partition, split to at most tile_max cells
+// ---------------------------------------------------------------------------------------
+static inline int part_lo(int b, int n, int s) {  // first index of part b in a floor partition
+  return int((int64_t(b) * n + s - 1) / s);
+}
+
+static std::vector<Tile> make_tiles(int nx, int ny, int nz, const int nsub[3], int tile_max) {
+  std::vector<Tile> out;
+  for (int bz = 0; bz < nsub[2]; ++bz)
+    for (int by = 0; by < nsub[1]; ++by)
+      for (int bx = 0; bx < nsub[0]; ++bx) {
+        const int x0 = part_lo(bx, nx, nsub[0]), x1 = part_lo(bx + 1, nx, nsub[0]);
+        const int y0 = part_lo(by, ny, nsub[1]), y1 = part_lo(by + 1, ny, nsub[1]);
+        const int z0 = part_lo(bz, nz, nsub[2]), z1 = part_lo(bz + 1, nz, nsub[2]);
+        const int ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
+        if (ex <= 0 || ey <= 0 || ez <= 0) continue;
+        int cz = 1, cy = 1, cx = 1;
+        const int64_t vol = int64_t(ex) * ey * ez;
+        if (vol > tile_max) {
+          cz = int(std::min<int64_t>(ez, (vol + tile_max - 1) / tile_max));
+          if (int64_t(ex) * ey * ((ez + cz - 1) / cz) > tile_max) {
+            cz = ez;
+            cy = int(std::min<int64_t>(ey, (int64_t(ex) * ey + tile_max - 1) / tile_max));
+            if (int64_t(ex) * ((ey + cy - 1) / cy) > tile_max) {
+              cy = ey;
+              cx = (ex + tile_max - 1) / tile_max;
+            }
+          }
+        }
+        for (int kz = 0; kz < cz; ++kz)
+          for (int ky = 0; ky < cy; ++ky)
+            for (int kx = 0; kx < cx; ++kx) {
+              Tile t;
+              t.x0 = x0 + part_lo(kx, ex, cx);
+              t.sx = part_lo(kx + 1, ex, cx) - part_lo(kx, ex, cx);
+              t.y0 = y0 + part_lo(ky, ey, cy);
+              t.sy = part_lo(ky + 1, ey, cy) - part_lo(ky, ey, cy);
+              t.z0 = z0 + part_lo(kz, ez, cz);
+              t.sz = part_lo(kz + 1, ez, cz) - part_lo(kz, ez, cz);
+              t.ncell = t.sx * t.sy * t.sz;
+              t.nslot = 0;
+              if (t.ncell > 0) out.push_back(t);
+            }
+      }
+  return out;
+}
+
+// ---------------------------------------------------------------------------------------
+// context life cycle
+// ---------------------------------------------------------------------------------------
+extern "C" void psl_destroy(psl_ctx* c) {
+  if (!c) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(c->dev);
+  (void)hipDeviceSynchronize();
+  if (c->graph64) (void)hipGraphExecDestroy(c->graph64);
+  if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
+  if (c->graph_stream64) (void)hipStreamDestroy(c->graph_stream64);
+  if (c->graph_stream32) (void)hipStreamDestroy(c->graph_stream32);
+  void* ptrs[] = {c->Tx, c->Ty, c->Tz, c->Tx32, c->Ty32, c->Tz32, c->invdiag, c->invdiag32,
+                  c->labels, c->tiles, c->slot, c->tile_lab, c->lab_ptr, c->lab_part,
+                  c->az_ptr, c->az_cell, c->az_lab, c->az_oth, c->az_t, c->az_t32, c->E, c->Einv,
+                  c->zq_part, c->zr_part, c->red_part, c->s, c->e, c->sr, c->er, c->se_part,
+                  c->r64, c->t64, c->sc,
+                  c->v64.xh, c->v64.rh, c->v64.p, c->v64.q, c->v32.xh, c->v32.rh, c->v32.p,
+                  c->v32.q};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
+  (void)hipSetDevice(cur);
+  delete c;
+}
+
+#define PSL_TRY(expr)            \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != PSL_OK) {         \
+      psl_destroy(c);            \
+      return _rc;                \
+    }                            \
+  } while (0)
+
+#define PSL_TRYHIP(call)                                                          \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      std::fprintf(stderr, "libpsl: %s failed: %s\n", #call, hipGetErrorString(_e)); \
+      psl_destroy(c);                                                             \
+      return PSL_EHIP;                                                            \
+    }                                                                             \
+  } while (0)
+
+template <typename T>
+static int dalloc(T** p, int64_t count) {
+  return psl_internal_alloc(reinterpret_cast<void**>(p), sizeof(T) * size_t(count));
+}
+
+extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
+                           const double* Ty, const double* Tz, const int32_t* labels,
+                           int32_t d, const int32_t nsub[3], void* stream) {
+  if (!out) return PSL_EINVAL;
+  *out = nullptr;
+  if (!grid_ok(g) || !Tx || !Ty || !Tz || !labels || d < 1) return PSL_EINVAL;
+  if (d > PSL_MAX_DENSE_D) return PSL_ENOTSUP;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  int ns[3];
+  if (nsub) {
+    const int ext[3] = {nx, ny, nz};
+    for (int a = 0; a < 3; ++a) {
+      if (nsub[a] < 1 || nsub[a] > ext[a]) return PSL_EINVAL;
+      ns[a] = nsub[a];
+    }
+  } else {
+    ns[0] = (nx + 15) / 16;
+    ns[1] = (ny + 15) / 16;
+    ns[2] = (nz + 7) / 8;
+  }
+  if (int64_t(d) > int64_t(nx) * ny * nz) return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  psl_ctx* c = new psl_ctx();
+  (void)hipGetDevice(&c->dev);
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->n = int64_t(nx) * ny * nz;
+  c->d = d;
+  for (int a = 0; a < 3; ++a) c->nsub[a] = ns[a];
+  const int n = int(c->n);
+  const int64_t nfx = int64_t(nx + 1) * ny * nz, nfy = int64_t(nx) * (ny + 1) * nz,
+                nfz = int64_t(nx) * ny * (nz + 1);
+  GridDev gd{nx, ny, nz};
+
+  PSL_TRY(dalloc(&c->Tx, nfx));
+  PSL_TRY(dalloc(&c->Ty, nfy));
+  PSL_TRY(dalloc(&c->Tz, nfz));
+  PSL_TRY(dalloc(&c->Tx32, nfx));
+  PSL_TRY(dalloc(&c->Ty32, nfy));
+  PSL_TRY(dalloc(&c->Tz32, nfz));
+  PSL_TRY(dalloc(&c->invdiag, n));
+  PSL_TRY(dalloc(&c->invdiag32, n));
+  PSL_TRY(dalloc(&c->labels, n));
+  PSL_TRY(dalloc(&c->slot, n));
+  int32_t* flags = nullptr;  // 0 diag, 1 tile overflow, 2 empty column, 3 label range, 4 E pivot
+  PSL_TRY(dalloc(&flags, 8));
+  auto free_flags = [&]() {
+    if (flags) (void)hipFree(flags);
+    flags = nullptr;
+  };
+  int32_t hflags[8] = {0};
+  auto read_flags = [&]() -> int {
+    if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return PSL_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PSL_EHIP;
+    return PSL_OK;
+  };
+#define PSL_FAIL(rc)   \
+  do {                 \
+    free_flags();      \
+    psl_destroy(c);    \
+    return (rc);       \
+  } while (0)
+
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, flags, 0, int64_t(8));
+  if (hipMemcpyAsync(c->Tx, Tx, sizeof(double) * nfx, hipMemcpyDeviceToDevice, st) ||
+      hipMemcpyAsync(c->Ty, Ty, sizeof(double) * nfy, hipMemcpyDeviceToDevice, st) ||
+      hipMemcpyAsync(c->Tz, Tz, sizeof(double) * nfz, hipMemcpyDeviceToDevice, st) ||
+      hipMemcpyAsync(c->labels, labels, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st))
+    PSL_FAIL(PSL_EHIP);
+  hipLaunchKernelGGL(k_check_labels, dim3(nblocks(n)), dim3(kBlock), 0, st, c->labels, n, d,
+                     flags + 3);
+  hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(kBlock), 0, st, gd, c->Tx, c->Ty, c->Tz,
+                     c->invdiag, c->invdiag32, flags);
+  if (read_flags()) PSL_FAIL(PSL_EHIP);
+  if (hflags[3]) PSL_FAIL(PSL_EINVAL);  // a label outside [0, d)
+  if (hflags[0]) PSL_FAIL(PSL_ENOTSPD);
+  hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfx)), dim3(kBlock), 0, st, c->Tx, c->Tx32, nfx);
+  hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfy)), dim3(kBlock), 0, st, c->Ty, c->Ty32, nfy);
+  hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfz)), dim3(kBlock), 0, st, c->Tz, c->Tz32, nfz);
+
+  // tiles: shrink the tile size until no tile holds more than kMaxSlots labels
+  int tile_max = 2048;
+  for (;;) {
+    c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
+    c->ntiles = int(c->h_tiles.size());
+    if (c->tiles) (void)hipFree(c->tiles);
+    if (c->tile_lab) (void)hipFree(c->tile_lab);
+    c->tiles = nullptr;
+    c->tile_lab = nullptr;
+    if (dalloc(&c->tiles, c->ntiles) || dalloc(&c->tile_lab, int64_t(c->ntiles) * kMaxSlots))
+      PSL_FAIL(PSL_ENOMEM);
+    if (hipMemcpyAsync(c->tiles, c->h_tiles.data(), sizeof(Tile) * c->ntiles,
+                       hipMemcpyHostToDevice, st))
+      PSL_FAIL(PSL_EHIP);
+    hipLaunchKernelGGL(k_tile_labels, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles,
+                       c->labels, c->tile_lab, c->tiles, c->slot, flags + 1);
+    if (read_flags()) PSL_FAIL(PSL_EHIP);
+    if (hflags[0]) PSL_FAIL(PSL_ENOTSPD);
+    if (!hflags[1]) break;
+    if (tile_max == 1) PSL_FAIL(PSL_EINVAL);
+    tile_max = std::max(1, tile_max / 2);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, flags, 0, int64_t(8));
+  }
+  if (hipMemcpyAsync(c->h_tiles.data(), c->tiles, sizeof(Tile) * c->ntiles,
+                     hipMemcpyDeviceToHost, st) ||
+      hipStreamSynchronize(st))
+    PSL_FAIL(PSL_EHIP);
+  c->nslot_max = 1;
+  for (const Tile& t : c->h_tiles) c->nslot_max = std::max(c->nslot_max, t.nslot);
+
+  // label -> partial lists
+  const int nparts = c->ntiles * kMaxSlots;
+  int32_t* cnt = nullptr;
+  if (dalloc(&cnt, d + 1) || dalloc(&c->lab_ptr, d + 1) || dalloc(&c->lab_part, nparts))
+    PSL_FAIL(PSL_ENOMEM);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(d + 1)), dim3(kBlock), 0, st, cnt, 0,
+                     int64_t(d + 1));
+  hipLaunchKernelGGL(k_lab_count, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->tile_lab,
+                     nparts, cnt, d, flags + 3);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, cnt, c->lab_ptr, d);
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(d + 1)), dim3(kBlock), 0, st, cnt, 0,
+                     int64_t(d + 1));
+  hipLaunchKernelGGL(k_lab_fill, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->tile_lab,
+                     nparts, c->lab_ptr, cnt, c->lab_part, d);
+  hipLaunchKernelGGL(k_lab_sort, dim3(nblocks(d)), dim3(kBlock), 0, st, c->lab_ptr,
+                     c->lab_part, d, flags + 2);
+
+  // interface rows of A Z
+  int32_t* tile_cnt = nullptr;
+  if (dalloc(&tile_cnt, c->ntiles + 1) || dalloc(&c->az_ptr, c->ntiles + 1)) {
+    (void)hipFree(cnt);
+    PSL_FAIL(PSL_ENOMEM);
+  }
+  hipLaunchKernelGGL(k_az_count, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
+                     c->Ty, c->Tz, c->labels, tile_cnt);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, tile_cnt, c->az_ptr, c->ntiles);
+  int32_t m = 0;
+  if (hipMemcpyAsync(&m, c->az_ptr + c->ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
+      hipStreamSynchronize(st)) {
+    (void)hipFree(cnt);
+    (void)hipFree(tile_cnt);
+    PSL_FAIL(PSL_EHIP);
+  }
+  (void)hipFree(cnt);
+  (void)hipFree(tile_cnt);
+  c->m_az = m;
+  if (dalloc(&c->az_cell, m) || dalloc(&c->az_lab, m) || dalloc(&c->az_oth, m) ||
+      dalloc(&c->az_t, m) || dalloc(&c->az_t32, m))
+    PSL_FAIL(PSL_ENOMEM);
+  hipLaunchKernelGGL(k_az_fill, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
+                     c->Ty, c->Tz, c->labels, c->az_ptr, c->az_cell, c->az_lab, c->az_oth,
+                     c->az_t, c->az_t32);
+
+  // E = Z^T A Z, then Cholesky and inverse
+  const int64_t dd = int64_t(d) * d;
+  double* Lw = nullptr;
+  if (dalloc(&c->E, dd) || dalloc(&c->Einv, dd) || dalloc(&Lw, dd)) {
+    (void)hipFree(Lw);
+    PSL_FAIL(PSL_ENOMEM);
+  }
+  hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, gd, c->tiles, c->lab_ptr,
+                     c->lab_part, c->az_ptr, c->az_lab, c->az_oth, c->az_t, c->E, d);
+  if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st)) {
+    (void)hipFree(Lw);
+    PSL_FAIL(PSL_EHIP);
+  }
+  int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, st);
+  if (rc == PSL_OK) rc = read_flags();
+  (void)hipFree(Lw);
+  if (rc != PSL_OK) PSL_FAIL(rc);
+  if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range
+  if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
+
+  // coarse GEMV layout and solve work space
+  c->coarse_rows_per_block = 8;
+  c->coarse_blocks = (d + c->coarse_rows_per_block - 1) / c->coarse_rows_per_block;
+  if (dalloc(&c->zq_part, nparts) || dalloc(&c->zr_part, nparts) ||
+      dalloc(&c->red_part, int64_t(c->ntiles) * 4) || dalloc(&c->s, d) || dalloc(&c->e, d) ||
+      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->se_part, c->coarse_blocks) ||
+      dalloc(&c->r64, n) || dalloc(&c->t64, n) || dalloc(&c->sc, 1))
+    PSL_FAIL(PSL_ENOMEM);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(psl::Scalars)) != hipSuccess)
+    PSL_FAIL(PSL_ENOMEM);
+  std::memset(c->h_sc, 0, sizeof(psl::Scalars));
+  if (hipMemcpyAsync(c->sc, c->h_sc, sizeof(psl::Scalars), hipMemcpyHostToDevice, st) ||
+      hipStreamSynchronize(st))
+    PSL_FAIL(PSL_EHIP);
+  free_flags();
+#undef PSL_FAIL
+  *out = c;
+  return PSL_OK;
+}
+
+extern "C" int psl_get_coarse(psl_ctx* c, double* E, double* Einv, int32_t* d, void* stream) {
+  if (!c) return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = sizeof(double) * size_t(c->d) * c->d;
+  if (E) PSL_HIP(hipMemcpyAsync(E, c->E, bytes, hipMemcpyDeviceToDevice, st));
+  if (Einv) PSL_HIP(hipMemcpyAsync(Einv, c->Einv, bytes, hipMemcpyDeviceToDevice, st));
+  if (d) *d = c->d;
+  return PSL_OK;
+}

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libpsl (include/psl.h): argument marshalling only.
+
+Every function here forwards device pointers of torch tensors, host scalars and the
+current HIP stream to the C-ABI entry point of the same name. All arithmetic happens
+in the library's HIP kernels; there is no host or CPU fallback. Importing this module
+without the built library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libpsl.so not found at {LIB_PATH}; build it with "
+        "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- status codes and constants (mirrors include/psl.h) ----------------------------------
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EMAXIT, EBREAKDOWN, ENONFINITE, ESTAGNATION, ENOTSUP = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
+DIRICHLET_X_LO, DIRICHLET_X_HI, DIRICHLET_Y_LO, DIRICHLET_Y_HI, DIRICHLET_Z_LO, DIRICHLET_Z_HI = (
+    1, 2, 4, 8, 16, 32)
+FP64, MIXED = 0, 1
+MAX_THRESHOLDS = 15
+MAX_DENSE_D = 8192
+MAX_TILE_LABELS = 16
+
+
+class psl_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class psl_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("tau_inner", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("reproject", ctypes.c_int32)]
+
+
+class psl_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("relres_true", ctypes.c_double),
+                ("bnorm", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_assemble = _sig("psl_assemble_tpfa", ctypes.c_int,
+                 [ctypes.POINTER(psl_grid), _P, ctypes.c_uint32, _P, _P, _P, _P])
+_build_z = _sig("psl_build_Z", ctypes.c_int,
+                [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
+_setup_e = _sig("psl_setup_E", ctypes.c_int,
+                [ctypes.POINTER(_P), ctypes.POINTER(psl_grid), _P, _P, _P, _P, _I32, _I32P, _P])
+_solve = _sig("psl_solve", ctypes.c_int,
+              [_P, _P, _P, ctypes.POINTER(psl_solve_opts), ctypes.POINTER(psl_solve_stats), _P])
+_apply_a = _sig("psl_apply_A", ctypes.c_int, [_P, _P, _P, _P])
+_deflate = _sig("psl_deflate", ctypes.c_int, [_P, _P, _P, _P, _P])
+_get_coarse = _sig("psl_get_coarse", ctypes.c_int, [_P, _P, _P, _I32P, _P])
+_destroy = _sig("psl_destroy", None, [_P])
+_status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
+_default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
+
+EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_setup_E", "psl_solve", "psl_apply_A",
+            "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
+            "psl_default_opts")
+
+
+class PslError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {psl_status_str(status)} ({status})")
+
+
+def psl_status_str(status: int) -> str:
+    return _status_str(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise PslError(status, where)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, n: Optional[int] = None, name: str = "") -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous {dtype} tensor, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _grid(grid: Sequence[int]) -> psl_grid:
+    nx, ny, nz = (int(v) for v in grid)
+    return psl_grid(nx, ny, nz)
+
+
+def face_counts(grid: Sequence[int]) -> Tuple[int, int, int]:
+    nx, ny, nz = (int(v) for v in grid)
+    return (nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)
+
+
+def psl_assemble_tpfa(grid, K: torch.Tensor, dirichlet_mask: int,
+                      Tx: Optional[torch.Tensor] = None, Ty: Optional[torch.Tensor] = None,
+                      Tz: Optional[torch.Tensor] = None):
+    """Face transmissibilities (float64 device tensors), allocated when not given."""
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    fx, fy, fz = face_counts(grid)
+    dev = K.device
+    Tx = torch.empty(fx, dtype=torch.float64, device=dev) if Tx is None else Tx
+    Ty = torch.empty(fy, dtype=torch.float64, device=dev) if Ty is None else Ty
+    Tz = torch.empty(fz, dtype=torch.float64, device=dev) if Tz is None else Tz
+    g = _grid(grid)
+    _check(_assemble(ctypes.byref(g), _dev(K, torch.float64, n, "K"), int(dirichlet_mask),
+                     _dev(Tx, torch.float64, fx, "Tx"), _dev(Ty, torch.float64, fy, "Ty"),
+                     _dev(Tz, torch.float64, fz, "Tz"), _stream()), "psl_assemble_tpfa")
+    return Tx, Ty, Tz
+
+
+def psl_build_Z(grid, K: Optional[torch.Tensor], nsub, thr=None, cls: Optional[torch.Tensor] = None,
+                ncls: int = 0, labels: Optional[torch.Tensor] = None):
+    """Subdomain-levelset labels (int32 device tensor) and d."""
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    dev = (K if K is not None else cls).device
+    labels = torch.empty(n, dtype=torch.int32, device=dev) if labels is None else labels
+    g = _grid(grid)
+    ns = (ctypes.c_int32 * 3)(*[int(v) for v in nsub])
+    thr = [] if thr is None else [float(t) for t in thr]
+    th = (ctypes.c_double * max(1, len(thr)))(*thr)
+    d = ctypes.c_int32(0)
+    kp = _dev(K, torch.float64, n, "K") if K is not None else ctypes.c_void_p(0)
+    cp = _dev(cls, torch.int32, n, "cls") if cls is not None else ctypes.c_void_p(0)
+    _check(_build_z(ctypes.byref(g), kp, ns, th, len(thr), cp, int(ncls),
+                    _dev(labels, torch.int32, n, "labels"), ctypes.byref(d), _stream()),
+           "psl_build_Z")
+    return labels, int(d.value)
+
+
+class Context:
+    """Owns a psl_ctx (E, its factor and inverse, work space); freed with the object."""
+
+    def __init__(self, ptr: int, grid, d: int):
+        self._ptr = ctypes.c_void_p(ptr)
+        self.grid = tuple(int(v) for v in grid)
+        self.n = self.grid[0] * self.grid[1] * self.grid[2]
+        self.d = d
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._ptr:
+            raise RuntimeError("context already destroyed")
+        return self._ptr
+
+    def destroy(self):
+        if self._ptr:
+            _destroy(self._ptr)
+            self._ptr = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
+                labels: torch.Tensor, d: int, nsub=None) -> Context:
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    fx, fy, fz = face_counts(grid)
+    g = _grid(grid)
+    out = ctypes.c_void_p(0)
+    ns = (ctypes.c_int32 * 3)(*[int(v) for v in nsub]) if nsub is not None else None
+    _check(_setup_e(ctypes.byref(out), ctypes.byref(g), _dev(Tx, torch.float64, fx, "Tx"),
+                    _dev(Ty, torch.float64, fy, "Ty"), _dev(Tz, torch.float64, fz, "Tz"),
+                    _dev(labels, torch.int32, n, "labels"), int(d),
+                    ns if ns is not None else ctypes.cast(None, _I32P), _stream()),
+           "psl_setup_E")
+    return Context(out.value, grid, int(d))
+
+
+def default_opts() -> psl_solve_opts:
+    o = psl_solve_opts()
+    _default_opts(ctypes.byref(o))
+    return o
+
+
+def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
+              tol: Optional[float] = None, maxit: Optional[int] = None, mode: int = FP64,
+              use_x0: bool = False, max_outer: Optional[int] = None,
+              tau_inner: Optional[float] = None, check_every: Optional[int] = None,
+              reproject: Optional[int] = None, check: bool = False):
+    """Solve A x = b; returns (x, stats dict). Non-zero status raises only if check=True."""
+    o = default_opts()
+    if tol is not None:
+        o.tol = tol
+    if maxit is not None:
+        o.maxit = maxit
+    o.mode = int(mode)
+    o.use_x0 = 1 if use_x0 else 0
+    if max_outer is not None:
+        o.max_outer = max_outer
+    if tau_inner is not None:
+        o.tau_inner = tau_inner
+    if check_every is not None:
+        o.check_every = check_every
+    if reproject is not None:
+        o.reproject = int(reproject)
+    if x is None:
+        if use_x0:
+            raise ValueError("use_x0 needs x")
+        x = torch.empty_like(b)
+    st = psl_solve_stats()
+    rc = _solve(ctx.handle, _dev(b, torch.float64, ctx.n, "b"), _dev(x, torch.float64, ctx.n, "x"),
+                ctypes.byref(o), ctypes.byref(st), _stream())
+    if check:
+        _check(rc, "psl_solve")
+    stats = st.as_dict()
+    stats["status_str"] = psl_status_str(rc)
+    return x, stats
+
+
+def psl_apply_A(ctx: Context, p: torch.Tensor, q: Optional[torch.Tensor] = None) -> torch.Tensor:
+    q = torch.empty_like(p) if q is None else q
+    _check(_apply_a(ctx.handle, _dev(p, torch.float64, ctx.n, "p"),
+                    _dev(q, torch.float64, ctx.n, "q"), _stream()), "psl_apply_A")
+    return q
+
+
+def psl_deflate(ctx: Context, r: torch.Tensor, out: Optional[torch.Tensor] = None,
+                c: Optional[torch.Tensor] = None):
+    """out = P1 r and c = E^-1 Z^T r."""
+    out = torch.empty_like(r) if out is None else out
+    c = torch.empty(ctx.d, dtype=torch.float64, device=r.device) if c is None else c
+    _check(_deflate(ctx.handle, _dev(r, torch.float64, ctx.n, "r"),
+                    _dev(out, torch.float64, ctx.n, "out"), _dev(c, torch.float64, ctx.d, "c"),
+                    _stream()), "psl_deflate")
+    return out, c
+
+
+def psl_get_coarse(ctx: Context, device="cuda"):
+    """(E, E^-1) as d x d float64 device tensors."""
+    d = ctx.d
+    E = torch.empty((d, d), dtype=torch.float64, device=device)
+    Einv = torch.empty((d, d), dtype=torch.float64, device=device)
+    dd = ctypes.c_int32(0)
+    _check(_get_coarse(ctx.handle, _dev(E, torch.float64, d * d, "E"),
+                       _dev(Einv, torch.float64, d * d, "Einv"), ctypes.byref(dd), _stream()),
+           "psl_get_coarse")
+    return E, Einv
+
+
+def psl_destroy(ctx: Context):
+    ctx.destroy()

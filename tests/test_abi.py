@@ -1,0 +1,90 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry point that
+include/psl.h declares; the ctypes structs match the C layout (checked with gcc)."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "psl.h")
+LIB = os.path.join(ROOT, "paper_1510_02148_amd", "libpsl.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(psl_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("psl_build_Z", "psl_setup_E", "psl_solve", "psl_assemble_tpfa", "psl_destroy",
+                 "psl_status_str"):
+        assert must in names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpsl.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_without_gpu(lib):
+    lib.psl_status_str.restype = ctypes.c_char_p
+    assert lib.psl_status_str(0) == b"ok"
+    assert b"positive definite" in lib.psl_status_str(-4)
+    assert lib.psl_status_str(12345) == b"unknown status"
+
+
+def test_binding_struct_layout_matches_c(tmp_path):
+    from paper_1510_02148_amd import psl
+    prog = tmp_path / "sz.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
+        " sizeof(psl_solve_stats), offsetof(psl_solve_opts, tau_inner),"
+        " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_stats, relres_true),"
+        " sizeof(psl_grid));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [ctypes.sizeof(psl.psl_solve_opts), ctypes.sizeof(psl.psl_solve_stats),
+            psl.psl_solve_opts.tau_inner.offset, psl.psl_solve_opts.check_every.offset,
+            psl.psl_solve_stats.relres_true.offset, ctypes.sizeof(psl.psl_grid)]
+    assert got == want
+
+
+def test_default_opts(lib):
+    from paper_1510_02148_amd import psl
+    o = psl.default_opts()
+    assert o.tol == 1e-8 and o.maxit == 10000 and o.mode == psl.FP64 and o.check_every == 16
+
+
+def test_invalid_arguments_rejected_before_any_device_work(lib):
+    from paper_1510_02148_amd import psl
+    # null pointers and bad sizes return PSL_EINVAL without touching the device
+    g = psl.psl_grid(0, 4, 4)
+    rc = psl._assemble(ctypes.byref(g), None, 1, None, None, None, None)
+    assert rc == psl.EINVAL
+    out = ctypes.c_void_p(0)
+    g = psl.psl_grid(4, 4, 4)
+    rc = psl._setup_e(ctypes.byref(out), ctypes.byref(g), None, None, None, None, 3, None, None)
+    assert rc == psl.EINVAL and not out.value
+    d = ctypes.c_int32(0)
+    ns = (ctypes.c_int32 * 3)(9, 1, 1)  # more subdomains than cells along x
+    rc = psl._build_z(ctypes.byref(g), ctypes.c_void_p(16), ns, None, 0, None, 0,
+                      ctypes.c_void_p(16), ctypes.byref(d), None)
+    assert rc == psl.EINVAL
+    assert psl._solve(None, None, None, None, None, None) == psl.EINVAL
