@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Time-to-solution benchmark of the subdomain-levelset deflated PCG path on one MI355X.
+
+One step = the whole hot path for one permeability field already resident in HBM:
+transmissibilities -> subdomain-levelset labels -> E = Z^T A Z with its Cholesky inverse
+-> deflated PCG to ||b - A x|| <= 1e-8 ||b|| (float32 CG inside float64 refinement by
+default; the plain float64 path is timed beside it). Prints one JSON line.
+
+Workload (default): 128 x 128 x 64 cells, 8 horizontal layers of log-normal permeability
+(sigma 1 in ln K) whose means alternate between 1 and 1e-6, 8 x 8 x 4 subdomains x 2
+levelsets (d = 512), p = 0 on the x = 0 face, unit source / sink in opposite corners.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-1e-8 rel. residual (s), iterations, SpMV HBM GB/s vs plain FP64 DPCG")
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c1": "layered2d 64x64, 4x4 subdomains x 2 levelsets",
+    "c2": "layered3d 128x128x64, 8 layers log-normal K (sigma 1), layer means 1 / 1e-6, "
+          "8x8x4 subdomains x 2 levelsets",
+    "c3": "channelized 256x256x128 (GRF corr. length 16, 30% channels), contrast 1e6, "
+          "16x16x8 subdomains x 2 levelsets",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int) -> float:
+    """Bytes one launch must move at minimum (each array touched once), w = word size."""
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    if kernel == "stencil":          # read p, Tx, Ty, Tz, slot; write q
+        return w * n + w * faces + 1 * n + w * n
+    if kernel == "update":           # read q, rhat, xhat, p, 1/diag, slot; write rhat, xhat
+        return 5 * w * n + 1 * n + 2 * w * n + m_faces * (12 + w)
+    if kernel == "direction":        # read rhat, 1/diag, p; write p
+        return 4 * w * n
+    if kernel == "coarse":           # read E^-1 (float64), s, sr; write e, er
+        return 8.0 * d * d + 4 * 8 * d
+    raise KeyError(kernel)
+
+
+def make_problem(name: str, seed: int):
+    import psl_inputs as pi
+    if name == "c3":
+        return pi.config("c3", seed=seed, contrast=1e6)
+    return pi.config(name, seed=seed)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--kernel-reps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain float64 comparison")
+    ap.add_argument("--quick", action="store_true",
+                    help="one step, no comparison legs (for profiler counter runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only: a single-system PSL "
+                          "solve is not sharded across GPUs here (see DESIGN.md, sharding)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.quick:
+        args.steps, args.warmup, args.no_fp64, args.no_cpu_baseline = 1, 0, True, True
+
+    import numpy as np
+    import torch
+
+    from paper_1510_02148_amd import pipeline, psl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = make_problem(args.workload, args.seed)
+    log(f"workload {args.workload} grid={prob.grid} nsub={prob.nsub} n={prob.n}")
+    K = torch.as_tensor(prob.K, dtype=torch.float64, device=dev)
+    b = torch.as_tensor(prob.q, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step(mode):
+        t0 = time.perf_counter()
+        s = pipeline.setup(prob.grid, K, prob.dirichlet_mask, prob.nsub, list(prob.thr))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return s, x, st, t1 - t0, t2 - t1
+
+    def run_leg(mode, steps, warmup, label):
+        for i in range(warmup):
+            s, x, st, _, _ = step(mode)
+            log(f"{label} warmup {i}: status={st['status_str']} iters={st['iters']}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = []
+        for _ in range(steps):
+            s, x, st, ts, tv = step(mode)
+            rec.append((st, ts, tv))
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        st = rec[-1][0]
+        log(f"{label}: {wall * 1e3:.3f} ms/step  status={st['status_str']} iters={st['iters']} "
+            f"outer={st['outer']} relres={st['relres_true']:.2e}")
+        return s, x, rec, wall
+
+    mode = psl.MIXED if args.mode == "mixed" else psl.FP64
+    s, x, rec, wall = run_leg(mode, args.steps, args.warmup, args.mode)
+    st = rec[-1][0]
+    ok = all(r[0]["status"] == 0 and r[0]["relres_true"] <= prob.tol for r in rec)
+    setup_s = float(np.median([r[1] for r in rec]))
+    solve_s = float(np.median([r[2] for r in rec]))
+
+    fp64 = None
+    if not args.no_fp64 and mode != psl.FP64:
+        s64, x64, rec64, wall64 = run_leg(psl.FP64, args.steps, min(args.warmup, 1), "fp64")
+        st64 = rec64[-1][0]
+        fp64 = {"s_per_step": wall64, "setup_s": float(np.median([r[1] for r in rec64])),
+                "solve_s": float(np.median([r[2] for r in rec64])), "iters": st64["iters"],
+                "relres_true": st64["relres_true"], "status": st64["status_str"]}
+        del s64, x64
+
+    # ---- per-kernel durations with events on the stream the kernels run on ----------
+    w = 4 if mode == psl.MIXED else 8
+    d = s.d
+    info = psl.psl_get_info(s.ctx)
+    m_faces = int(info["m_faces"])
+    kernels = {}
+    stream = torch.cuda.current_stream()
+    ids = {"stencil": psl.KERNEL_STENCIL, "coarse": psl.KERNEL_COARSE,
+           "update": psl.KERNEL_UPDATE, "direction": psl.KERNEL_DIRECTION}
+    for name, kid in ids.items():
+        psl.psl_bench_kernel(s.ctx, kid, mode, 3)            # warm
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        psl.psl_bench_kernel(s.ctx, kid, mode, args.kernel_reps)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+        nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w)
+        kernels[name] = {"us": round(us, 3), "alg_bytes": int(nbytes),
+                         "gbs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+    # plain copy of 1 GiB for the achievable-bandwidth reference
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    psl.psl_bench_copy(src, dst)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        psl.psl_bench_copy(src, dst)
+    e1.record(stream)
+    e1.synchronize()
+    copy_us = e0.elapsed_time(e1) * 1e3 / 10
+    copy_gbs = 2 * src.numel() * 4 / (copy_us * 1e-6) / 1e9
+    del src, dst
+    dominant = max(("stencil", "update", "direction", "coarse"), key=lambda k: kernels[k]["us"])
+    kd = kernels[dominant]
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "copy_kernel_gbs": round(copy_gbs, 1)}
+    spmv_gbs = kernels["stencil"]["gbs"]
+
+    # ---- CPU baseline: the oracle on the same workload -------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import psl_oracle as O
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            A, bh = O.assemble(prob.K, prob.grid, prob.dirichlet_mask, prob.q)
+            lab, dd = O.levelset_labels(prob.grid, prob.K, prob.nsub, prob.thr)
+            Z = O.deflation_matrix(lab, dd)
+            res = O.dpcg(A, bh, Z, tol=prob.tol)
+            cpu_s = time.perf_counter() - t0
+        xg = x.cpu().numpy()
+        cpu = {"value": round(cpu_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"one full {args.workload} solve (assembly, labels, E + Cholesky, "
+                         f"DEF1-PCG to 1e-8), {res.iters} iterations, 1 thread",
+               "host_cores_available": len(os.sched_getaffinity(0)),
+               "gpu_vs_oracle_rel_err": float(np.linalg.norm(xg - res.x) / np.linalg.norm(res.x)),
+               "gpu_relres_by_oracle": float(O.relres(A, bh, xg))}
+        log(f"cpu oracle: {cpu_s:.2f} s, {res.iters} iterations")
+
+    dtype = "f32-inner/f64-refine" if mode == psl.MIXED else "f64"
+    out = {
+        "metric": METRIC, "value": round(wall, 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid),
+                   "nsub": list(prob.nsub), "d": d, "tol": prob.tol, "mode": args.mode,
+                   "seed": args.seed},
+        "converged": bool(ok), "iterations": st["iters"], "outer": st["outer"],
+        "relres_true": st["relres_true"], "setup_s": setup_s, "solve_s": solve_s,
+        "spmv_gbs": spmv_gbs, "ctx_info": info, "kernels": kernels, "roofline": roofline,
+        "fp64_plain": fp64,
+        "speedup_vs_fp64": (round(fp64["s_per_step"] / wall, 3) if fp64 else None),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

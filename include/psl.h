@@ -204,6 +204,43 @@ int psl_deflate(psl_ctx* ctx, const double* r, double* out, double* c, void* str
  */
 int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stream);
 
+/* ---- measurement entry points (used by the benchmark and the profiler runs) ------- */
+#define PSL_KERNEL_STENCIL        0  /* q = A p, (p, q), Z^T q        (CG pass 1)          */
+#define PSL_KERNEL_COARSE         1  /* e = E^-1 Z^T q, alpha          (coarse GEMV)        */
+#define PSL_KERNEL_UPDATE         2  /* rhat, xhat update with A Z e   (CG pass 2)          */
+#define PSL_KERNEL_DIRECTION      3  /* p = M^-1 rhat + beta p         (CG pass 3)          */
+#define PSL_KERNEL_OUTER_RESIDUAL 4  /* r = b - A x in float64         (refinement step)    */
+
+/*
+ * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
+ * iteration (Algorithm 1's matrix-vector product, inner products and Galerkin solve, in
+ * the deflated-CG form psl_solve uses) on the context's current work vectors, in the
+ * precision of `mode`, so a caller can time it with events on `stream`. Call after a
+ * psl_solve in the same mode (the vectors then hold a real iterate); the scalars are set
+ * so that no launch exits early. The work vectors are overwritten.
+ * Errors: PSL_EINVAL (bad kernel id, mode or reps < 1), PSL_ENOMEM.
+ */
+int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
+
+/*
+ * psl_bench_copy -- device-to-device streaming copy of `bytes` (multiple of 16, both
+ * pointers 16-byte aligned) with a plain load/store kernel: the reference for achievable
+ * bandwidth and for calibrating hardware byte counters.
+ */
+int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* stream);
+
+/* Sizes of what psl_setup_E built (for byte accounting and diagnostics). */
+typedef struct {
+  int64_t n;            /* cells */
+  int32_t d;            /* deflation vectors */
+  int32_t ntiles;       /* work tiles (one workgroup each) */
+  int64_t m_faces;      /* cut faces stored for A Z (faces between labels + Dirichlet) */
+  int32_t nslot_max;    /* most distinct labels in one tile */
+  int32_t reserved;
+} psl_ctx_info;
+
+int psl_get_info(const psl_ctx* ctx, psl_ctx_info* info);
+
 /* Release everything the context owns. NULL is ignored. */
 void psl_destroy(psl_ctx* ctx);
 

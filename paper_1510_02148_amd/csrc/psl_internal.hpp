@@ -14,6 +14,7 @@ namespace psl {
 constexpr int kBlock = 256;          // threads per workgroup for every cell kernel
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxSlots = PSL_MAX_TILE_LABELS;
+constexpr int kCoarseRows = 8;       // coarse GEMV rows per workgroup (two per wave)
 
 // Work tile: a box of cells inside one subdomain; one workgroup per tile.
 struct Tile {
@@ -39,10 +40,6 @@ struct Scalars {
   int32_t iters;     // inner iterations done in this inner solve
   int32_t status;    // PSL_OK or failure code raised on device
   int32_t maxit;     // remaining iteration budget for this inner solve
-  uint32_t cnt_a;    // last-block counters (reset by the last block)
-  uint32_t cnt_b;
-  uint32_t cnt_c;
-  uint32_t pad;
 };
 
 template <typename R>
@@ -62,6 +59,8 @@ struct psl_ctx {
   int d = 0;
   int ntiles = 0;
   int nslot_max = 0;
+  int tile_max = 0;                   // cells per tile (<= 2048)
+  int cpt = 1;                        // cells per thread = ceil(tile_max / kBlock)
   int nsub[3] = {1, 1, 1};
   // operator data (owned copies)
   double *Tx = nullptr, *Ty = nullptr, *Tz = nullptr;
@@ -74,8 +73,10 @@ struct psl_ctx {
   std::vector<psl::Tile> h_tiles;
   uint8_t* slot = nullptr;            // [n] slot of the cell's label within its tile
   int32_t* tile_lab = nullptr;        // [ntiles*kMaxSlots] label of each slot, -1 unused
-  int32_t* lab_ptr = nullptr;         // [d+1] CSR: partial indices contributing to label
-  int32_t* lab_part = nullptr;        // [ntiles*kMaxSlots] tile*kMaxSlots+slot
+  int32_t* lab_ptr = nullptr;         // [d+1] CSR over the (tile, slot) pairs of each label
+  int32_t* lab_part = nullptr;        // [npart] tile*kMaxSlots+slot, sorted within a label
+  int32_t* slot_pos = nullptr;        // [ntiles*kMaxSlots] position of (tile, slot) in lab_part
+  int npart = 0;                      // lab_ptr[d]
   // cut faces of A Z (faces between labels, and Dirichlet faces), grouped by tile and cell
   int32_t* az_ptr = nullptr;          // [ntiles+1]
   int32_t* az_cell = nullptr;         // [m] local cell index in the tile; bit 31 = first face of its cell
@@ -87,17 +88,17 @@ struct psl_ctx {
   // coarse operator
   double* E = nullptr;                // [d*d] row-major
   double* Einv = nullptr;             // [d*d]
-  int coarse_rows_per_block = 8;
-  int coarse_blocks = 1;
+  int coarse_blocks = 1;              // ceil(d / kCoarseRows) GEMV workgroups
+  int coarse_fused = 1;               // coarse workgroups sum s themselves (small d)
   // work
-  double* zq_part = nullptr;          // [ntiles*kMaxSlots] partials of Z^T q
-  double* zr_part = nullptr;          // [ntiles*kMaxSlots] partials of Z^T rhat
-  double* red_part = nullptr;         // [ntiles*4]
+  double* zq = nullptr;               // [npart] label-major partials of Z^T q (or Z^T r)
+  double* zr = nullptr;               // [npart] label-major partials of Z^T rhat
+  double* red = nullptr;              // [4*ntiles] per-tile scalar partials, quantity-major
+  double* cpart = nullptr;            // [2*coarse_blocks] s^T e and (p, q) partials
   double* s = nullptr;                // [d]
   double* e = nullptr;                // [d]
   double* sr = nullptr;               // [d] Z^T rhat
   double* er = nullptr;               // [d] E^-1 Z^T rhat
-  double* se_part = nullptr;          // [coarse_blocks]
   double* r64 = nullptr;              // [n] FP64 outer residual
   double* t64 = nullptr;              // [n] FP64 scratch
   psl::Scalars* sc = nullptr;

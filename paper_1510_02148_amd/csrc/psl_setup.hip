@@ -386,6 +386,13 @@ __global__ void k_lab_fill(const int32_t* tile_lab, int nparts, const int32_t* p
   part[ptr[l] + pos] = i;
 }
 
+// slot_pos[(tile, slot)] = its index in the label-major list
+__global__ void k_slot_pos(const int32_t* ptr, const int32_t* part, int d, int32_t* slot_pos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ptr[d]) return;
+  slot_pos[part[i]] = i;
+}
+
 __global__ void k_lab_sort(const int32_t* ptr, int32_t* part, int d, int32_t* empty) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= d) return;
@@ -515,35 +522,50 @@ __global__ void __launch_bounds__(kBlock) k_az_fill(GridDev g, const Tile* tiles
 }
 
 // E row l = sum over the cells of label l of their A Z rows: each cut face adds T to
-// E[l][l] and -T to E[l][other]. One workgroup per row; column c is accumulated only by
-// thread c % kBlock, in a fixed scan order (deterministic).
+// E[l][l] and -T to E[l][other]. One workgroup per row. The faces are summed in 64-bit
+// fixed point scaled to the row (2^-60 of an upper bound of the diagonal), so the LDS
+// atomics that let all threads work at once give an order-independent, deterministic row
+// whose absolute error is below 2^-50 of the diagonal.
 constexpr int kEChunk = 4096;
-__global__ void __launch_bounds__(kBlock) k_E_rows(GridDev g, const Tile* tiles,
-                                                   const int32_t* lab_ptr,
+__global__ void __launch_bounds__(kBlock) k_E_rows(const int32_t* lab_ptr,
                                                    const int32_t* lab_part,
                                                    const int32_t* az_ptr,
                                                    const int32_t* az_lab,
                                                    const int32_t* az_oth,
                                                    const double* az_t, double* E, int d) {
-  __shared__ double rowbuf[kEChunk];
+  __shared__ unsigned long long rowbuf[kEChunk];
+  __shared__ double red[kBlock / psl::kWave];
   const int l = blockIdx.x;
+  // pass 1: an upper bound of the diagonal (sum of the row's cut-face T), fixed order
+  double acc[1] = {0.0};
+  for (int pi = lab_ptr[l]; pi < lab_ptr[l + 1]; ++pi) {
+    const int tile = lab_part[pi] / kMaxSlots;
+    for (int k = az_ptr[tile] + threadIdx.x; k < az_ptr[tile + 1]; k += kBlock)
+      if (az_lab[k] == l) acc[0] += az_t[k];
+  }
+  psl::block_sum<1>(acc, red);
+  const double diag_bound = acc[0] > 0.0 ? acc[0] * 1.0000001 : 1.0;
+  int ex;
+  frexp(diag_bound, &ex);                 // diag_bound < 2^ex
+  const double scale = ldexp(1.0, 60 - ex), inv_scale = ldexp(1.0, ex - 60);
   for (int c0 = 0; c0 < d; c0 += kEChunk) {
     const int c1 = min(d, c0 + kEChunk);
-    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) rowbuf[c - c0] = 0.0;
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) rowbuf[c - c0] = 0ull;
     __syncthreads();
-    const bool own_diag = (l >= c0 && l < c1 && (l % kBlock) == threadIdx.x);
     for (int pi = lab_ptr[l]; pi < lab_ptr[l + 1]; ++pi) {
       const int tile = lab_part[pi] / kMaxSlots;
-      for (int k = az_ptr[tile]; k < az_ptr[tile + 1]; ++k) {
+      for (int k = az_ptr[tile] + threadIdx.x; k < az_ptr[tile + 1]; k += kBlock) {
         if (az_lab[k] != l) continue;
-        const double t = az_t[k];
-        if (own_diag) rowbuf[l - c0] += t;
+        const long long v = llrint(az_t[k] * scale);
+        if (l >= c0 && l < c1) atomicAdd(&rowbuf[l - c0], static_cast<unsigned long long>(v));
         const int o = az_oth[k];
-        if (o >= c0 && o < c1 && (o % kBlock) == threadIdx.x) rowbuf[o - c0] -= t;
+        if (o >= c0 && o < c1)
+          atomicAdd(&rowbuf[o - c0], static_cast<unsigned long long>(-v));
       }
     }
     __syncthreads();
-    for (int c = c0 + threadIdx.x; c < c1; c += kBlock) E[int64_t(l) * d + c] = rowbuf[c - c0];
+    for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
+      E[int64_t(l) * d + c] = static_cast<double>(static_cast<long long>(rowbuf[c - c0])) * inv_scale;
     __syncthreads();
   }
 }
@@ -553,30 +575,30 @@ __global__ void __launch_bounds__(kBlock) k_E_rows(GridDev g, const Tile* tiles,
 // ---------------------------------------------------------------------------------------
 constexpr int kNB = 64;
 
-// factor the kb diagonal block in LDS; flags a non-positive pivot
+// Factor the kb diagonal block in LDS (right-looking). Thread t updates row t/4 at the
+// columns congruent to t mod 4; a non-positive pivot raises *bad.
 __global__ void __launch_bounds__(kBlock) k_potrf_diag(double* A, int d, int kb, int32_t* bad) {
   __shared__ double a[kNB][kNB + 1];
+  __shared__ double col[kNB];
   const int nb = min(kNB, d - kb);
   for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
     const int i = t / nb, j = t % nb;
     a[i][j] = A[int64_t(kb + i) * d + kb + j];
   }
   __syncthreads();
+  const int ri = threadIdx.x >> 2, cj = threadIdx.x & 3;
   for (int k = 0; k < nb; ++k) {
-    if (threadIdx.x == 0) {
-      const double p = a[k][k];
-      if (!(p > 0.0) || !(p < INFINITY)) bad[0] = 1;
-      a[k][k] = sqrt(p > 0.0 ? p : 1.0);
-    }
+    const double p = a[k][k];
+    const double piv = sqrt(p > 0.0 ? p : 1.0);
+    if (threadIdx.x == 0 && (!(p > 0.0) || !(p < INFINITY))) bad[0] = 1;
+    if (threadIdx.x < nb && int(threadIdx.x) > k) col[threadIdx.x] = a[threadIdx.x][k] / piv;
     __syncthreads();
-    const double piv = a[k][k];
-    for (int i = k + 1 + threadIdx.x; i < nb; i += kBlock) a[i][k] /= piv;
-    __syncthreads();
-    const int m = nb - k - 1;
-    for (int t = threadIdx.x; t < m * m; t += kBlock) {
-      const int i = k + 1 + t / m, j = k + 1 + t % m;
-      if (j <= i) a[i][j] -= a[i][k] * a[j][k];
+    if (ri < nb && ri > k) {
+      const double ci = col[ri];
+      for (int j = k + 1 + ((cj - (k + 1)) & 3); j <= ri; j += 4) a[ri][j] -= ci * col[j];
     }
+    if (threadIdx.x < nb && int(threadIdx.x) > k) a[threadIdx.x][k] = col[threadIdx.x];
+    if (threadIdx.x == 0) a[k][k] = piv;
     __syncthreads();
   }
   for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
@@ -585,7 +607,28 @@ __global__ void __launch_bounds__(kBlock) k_potrf_diag(double* A, int d, int kb,
   }
 }
 
-// rows below the diagonal block: L[i, kb:kb+nb] = A[i, kb:kb+nb] L_kk^-T (one row per thread)
+// Wave-parallel substitution with the nb x nb lower block l (in LDS): lane j holds x_j.
+// forward (trans = 0): solves l x = x_in; backward (trans = 1): solves l^T x = x_in.
+__device__ inline double wave_trsv(const double (*l)[kNB + 1], int nb, double x, int trans) {
+  const int lane = threadIdx.x & (psl::kWave - 1);
+  if (!trans) {
+    for (int m = 0; m < nb; ++m) {
+      if (lane == m) x /= l[m][m];
+      const double xm = __shfl(x, m, psl::kWave);
+      if (lane > m && lane < nb) x -= l[lane][m] * xm;
+    }
+  } else {
+    for (int m = nb - 1; m >= 0; --m) {
+      if (lane == m) x /= l[m][m];
+      const double xm = __shfl(x, m, psl::kWave);
+      if (lane < m) x -= l[m][lane] * xm;
+    }
+  }
+  return x;
+}
+
+// rows below the diagonal block: L[i, kb:kb+nb] = A[i, kb:kb+nb] L_kk^-T, i.e. solve
+// L_kk y = a^T for every row i; one wave per row.
 __global__ void __launch_bounds__(kBlock) k_trsm_panel(double* A, int d, int kb) {
   __shared__ double l[kNB][kNB + 1];
   const int nb = min(kNB, d - kb);
@@ -594,16 +637,13 @@ __global__ void __launch_bounds__(kBlock) k_trsm_panel(double* A, int d, int kb)
     l[i][j] = A[int64_t(kb + i) * d + kb + j];
   }
   __syncthreads();
-  const int i = kb + nb + blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (psl::kWave - 1);
+  const int i = kb + nb + blockIdx.x * (kBlock / psl::kWave) + threadIdx.x / psl::kWave;
   if (i >= d) return;
-  double x[kNB];
   double* row = A + int64_t(i) * d + kb;
-  for (int j = 0; j < nb; ++j) {
-    double v = row[j];
-    for (int m = 0; m < j; ++m) v -= x[m] * l[j][m];
-    x[j] = v / l[j][j];
-  }
-  for (int j = 0; j < nb; ++j) row[j] = x[j];
+  double x = lane < nb ? row[lane] : 0.0;
+  x = wave_trsv(l, nb, x, 0);
+  if (lane < nb) row[lane] = x;
 }
 
 // C[i][j] -= sum_k A(i,k) B(k,j) for a 64x64 output tile per workgroup, K <= kNB.
@@ -650,8 +690,8 @@ __global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const d
     }
 }
 
-// X[kb:kb+nb, :] = L_kk^-1 X[kb:kb+nb, :] (trans = 0) or L_kk^-T X[...] (trans = 1);
-// one column per thread.
+// X[kb:kb+nb, c] = L_kk^-1 X[kb:kb+nb, c] (trans = 0) or L_kk^-T X[...] (trans = 1);
+// one wave per column c.
 __global__ void __launch_bounds__(kBlock) k_trsm_cols(const double* L, double* X, int d, int kb,
                                                       int trans) {
   __shared__ double l[kNB][kNB + 1];
@@ -661,24 +701,12 @@ __global__ void __launch_bounds__(kBlock) k_trsm_cols(const double* L, double* X
     l[i][j] = L[int64_t(kb + i) * d + kb + j];
   }
   __syncthreads();
-  const int c = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & (psl::kWave - 1);
+  const int c = blockIdx.x * (kBlock / psl::kWave) + threadIdx.x / psl::kWave;
   if (c >= d) return;
-  double x[kNB];
-  for (int j = 0; j < nb; ++j) x[j] = X[int64_t(kb + j) * d + c];
-  if (!trans) {
-    for (int j = 0; j < nb; ++j) {
-      double v = x[j];
-      for (int m = 0; m < j; ++m) v -= l[j][m] * x[m];
-      x[j] = v / l[j][j];
-    }
-  } else {
-    for (int j = nb - 1; j >= 0; --j) {
-      double v = x[j];
-      for (int m = j + 1; m < nb; ++m) v -= l[m][j] * x[m];
-      x[j] = v / l[j][j];
-    }
-  }
-  for (int j = 0; j < nb; ++j) X[int64_t(kb + j) * d + c] = x[j];
+  double x = lane < nb ? X[int64_t(kb + lane) * d + c] : 0.0;
+  x = wave_trsv(l, nb, x, trans);
+  if (lane < nb) X[int64_t(kb + lane) * d + c] = x;
 }
 
 __global__ void k_identity(double* X, int d) {
@@ -695,7 +723,8 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kBlock), 0, st, L, d, kb, bad);
     const int rest = d - kb - nb;
     if (rest > 0) {
-      hipLaunchKernelGGL(k_trsm_panel, dim3(nblocks(rest)), dim3(kBlock), 0, st, L, d, kb);
+      hipLaunchKernelGGL(k_trsm_panel, dim3(nblocks(rest, kBlock / psl::kWave)), dim3(kBlock), 0,
+                         st, L, d, kb);
       const double* P = L + int64_t(kb + nb) * d + kb;   // rest x nb panel
       double* C = L + int64_t(kb + nb) * d + kb + nb;    // trailing block
       dim3 grid(nblocks(rest, 64), nblocks(rest, 64));
@@ -707,7 +736,8 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream
   // forward: L Y = I (Y lower triangular, block row kb has no entries right of kb+nb)
   for (int kb = 0; kb < d; kb += kNB) {
     const int nb = std::min(kNB, d - kb);
-    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d)), dim3(kBlock), 0, st, L, X, d, kb, 0);
+    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d, kBlock / psl::kWave)), dim3(kBlock), 0, st, L,
+                       X, d, kb, 0);
     const int rest = d - kb - nb;
     if (rest > 0) {
       const int ncol = kb + nb;
@@ -720,7 +750,8 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream
   // backward: L^T X = Y
   for (int kb = ((d - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {
     const int nb = std::min(kNB, d - kb);
-    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d)), dim3(kBlock), 0, st, L, X, d, kb, 1);
+    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d, kBlock / psl::kWave)), dim3(kBlock), 0, st, L,
+                       X, d, kb, 1);
     if (kb > 0) {
       dim3 grid(nblocks(d, 64), nblocks(kb, 64));
       hipLaunchKernelGGL((k_gemm_sub<1, 0, 0>), grid, dim3(kBlock), 0, st, X, d,
@@ -795,7 +826,7 @@ extern "C" void psl_destroy(psl_ctx* c) {
   void* ptrs[] = {c->Tx, c->Ty, c->Tz, c->Tx32, c->Ty32, c->Tz32, c->invdiag, c->invdiag32,
                   c->labels, c->tiles, c->slot, c->tile_lab, c->lab_ptr, c->lab_part,
                   c->az_ptr, c->az_cell, c->az_lab, c->az_oth, c->az_t, c->az_t32, c->E, c->Einv,
-                  c->zq_part, c->zr_part, c->red_part, c->s, c->e, c->sr, c->er, c->se_part,
+                  c->zq, c->zr, c->red, c->s, c->e, c->sr, c->er, c->cpart, c->slot_pos,
                   c->r64, c->t64, c->sc,
                   c->v64.xh, c->v64.rh, c->v64.p, c->v64.q, c->v32.xh, c->v32.rh, c->v32.p,
                   c->v32.q};
@@ -912,8 +943,14 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfy)), dim3(kBlock), 0, st, c->Ty, c->Ty32, nfy);
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfz)), dim3(kBlock), 0, st, c->Tz, c->Tz32, nfz);
 
-  // tiles: shrink the tile size until no tile holds more than kMaxSlots labels
-  int tile_max = 2048;
+  // tiles: enough workgroups to fill the chip (>= 8 per CU when the grid allows),
+  // then shrink until no tile holds more than kMaxSlots labels
+  int tile_max = 1024;
+  while (tile_max > 256 && int64_t(n) / tile_max < 2048) tile_max /= 2;
+  if (const char* env = std::getenv("PSL_TILE_MAX")) {
+    const int v = std::atoi(env);
+    if (v >= 64 && v <= 2048) tile_max = v;
+  }
   for (;;) {
     c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
     c->ntiles = int(c->h_tiles.size());
@@ -940,7 +977,13 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
       hipStreamSynchronize(st))
     PSL_FAIL(PSL_EHIP);
   c->nslot_max = 1;
-  for (const Tile& t : c->h_tiles) c->nslot_max = std::max(c->nslot_max, t.nslot);
+  int max_cells = 1;
+  for (const Tile& t : c->h_tiles) {
+    c->nslot_max = std::max(c->nslot_max, t.nslot);
+    max_cells = std::max(max_cells, t.ncell);
+  }
+  c->tile_max = max_cells;
+  c->cpt = (max_cells + kBlock - 1) / kBlock;
 
   // label -> partial lists
   const int nparts = c->ntiles * kMaxSlots;
@@ -958,6 +1001,14 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
                      nparts, c->lab_ptr, cnt, c->lab_part, d);
   hipLaunchKernelGGL(k_lab_sort, dim3(nblocks(d)), dim3(kBlock), 0, st, c->lab_ptr,
                      c->lab_part, d, flags + 2);
+  if (dalloc(&c->slot_pos, nparts)) {
+    (void)hipFree(cnt);
+    PSL_FAIL(PSL_ENOMEM);
+  }
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->slot_pos, 0,
+                     int64_t(nparts));
+  hipLaunchKernelGGL(k_slot_pos, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->lab_ptr,
+                     c->lab_part, d, c->slot_pos);
 
   // interface rows of A Z
   int32_t* tile_cnt = nullptr;
@@ -970,6 +1021,7 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, tile_cnt, c->az_ptr, c->ntiles);
   int32_t m = 0;
   if (hipMemcpyAsync(&m, c->az_ptr + c->ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(&c->npart, c->lab_ptr + d, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
       hipStreamSynchronize(st)) {
     (void)hipFree(cnt);
     (void)hipFree(tile_cnt);
@@ -992,8 +1044,8 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
     (void)hipFree(Lw);
     PSL_FAIL(PSL_ENOMEM);
   }
-  hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, gd, c->tiles, c->lab_ptr,
-                     c->lab_part, c->az_ptr, c->az_lab, c->az_oth, c->az_t, c->E, d);
+  hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, c->lab_ptr, c->lab_part, c->az_ptr,
+                     c->az_lab, c->az_oth, c->az_t, c->E, d);
   if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st)) {
     (void)hipFree(Lw);
     PSL_FAIL(PSL_EHIP);
@@ -1006,11 +1058,13 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
 
   // coarse GEMV layout and solve work space
-  c->coarse_rows_per_block = 8;
-  c->coarse_blocks = (d + c->coarse_rows_per_block - 1) / c->coarse_rows_per_block;
-  if (dalloc(&c->zq_part, nparts) || dalloc(&c->zr_part, nparts) ||
-      dalloc(&c->red_part, int64_t(c->ntiles) * 4) || dalloc(&c->s, d) || dalloc(&c->e, d) ||
-      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->se_part, c->coarse_blocks) ||
+  c->coarse_blocks = (d + psl::kCoarseRows - 1) / psl::kCoarseRows;
+  // coarse workgroups stage all of s (d <= 4096 doubles of LDS) and each re-sums the
+  // label partials; beyond ~4M partial reads a separate reduction kernel is cheaper
+  c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
+  if (dalloc(&c->zq, std::max(1, c->npart)) || dalloc(&c->zr, std::max(1, c->npart)) ||
+      dalloc(&c->red, int64_t(c->ntiles) * 4) || dalloc(&c->s, d) || dalloc(&c->e, d) ||
+      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->cpart, 2 * c->coarse_blocks) ||
       dalloc(&c->r64, n) || dalloc(&c->t64, n) || dalloc(&c->sc, 1))
     PSL_FAIL(PSL_ENOMEM);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(psl::Scalars)) != hipSuccess)
@@ -1032,5 +1086,16 @@ extern "C" int psl_get_coarse(psl_ctx* c, double* E, double* Einv, int32_t* d, v
   if (E) PSL_HIP(hipMemcpyAsync(E, c->E, bytes, hipMemcpyDeviceToDevice, st));
   if (Einv) PSL_HIP(hipMemcpyAsync(Einv, c->Einv, bytes, hipMemcpyDeviceToDevice, st));
   if (d) *d = c->d;
+  return PSL_OK;
+}
+
+extern "C" int psl_get_info(const psl_ctx* c, psl_ctx_info* info) {
+  if (!c || !info) return PSL_EINVAL;
+  info->n = c->n;
+  info->d = c->d;
+  info->ntiles = c->ntiles;
+  info->m_faces = c->m_az;
+  info->nslot_max = c->nslot_max;
+  info->reserved = 0;
   return PSL_OK;
 }

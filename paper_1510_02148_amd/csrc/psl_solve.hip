@@ -1,19 +1,22 @@
 // libpsl solve path: deflated Jacobi-PCG (DEF1 form) on P1 A xhat = P1 b inside a float64
 // refinement loop, plus the stand-alone operator entry points (A p, P1 r).
 //
-// One CG iteration is four launches on the caller's stream:
-//   stencil   q = A p (flux form), partial (p, q) and Z^T q per tile
-//             [last workgroup: s = Z^T q, (p, q) in a fixed order]
-//   coarse    e = E^-1 s (dense float64 GEMV), partial s^T e
-//             [last workgroup: alpha = rho / ((p, q) - s^T e)]
-//   update    rhat = rhat - alpha (q - A Z e) [- A Z E^-1 Z^T rhat when re-projecting],
-//             xhat += alpha p, partial (rhat, M^-1 rhat), ||rhat||^2 (and Z^T rhat)
-//             [last workgroup: beta, rho, convergence / failure flags, iteration count]
+// One CG iteration is five launches on the caller's stream:
+//   stencil         q = A p (flux form); per tile (p, q) and Z^T q partials
+//   coarse          s = Z^T q from the label-major partials, e = E^-1 s (float64 GEMV);
+//                   per workgroup s^T e and (p, q) partials
+//                   (large d: a separate label-reduction kernel produces s first)
+//   update          alpha = rho / ((p, q) - s^T e) (each workgroup, same fixed order);
+//                   rhat = rhat - alpha q + A Z (alpha e - er), xhat += alpha p, where
+//                   er = E^-1 Z^T rhat when re-projecting (else 0); partials of
+//                   (rhat, M^-1 rhat), ||rhat||^2 and Z^T rhat
+//   close           one workgroup: beta, rho, convergence and failure flags, count
+//   direction       p = M^-1 rhat + beta p
 // A Z v is evaluated only on cells with a cut face, in flux form sum T (v_l(i) - v_l(j)).
-//   direction p = M^-1 rhat + beta p
-// Every reduction is a fixed-order tree, so reruns with the same tiling are bit-identical.
+// Partial sums cross workgroups only through kernel boundaries (no in-kernel fences), and
+// every reduction is a fixed-order tree: reruns with the same tiling are bit-identical.
 // A finished solve raises a device flag that makes every later launch return at once, so
-// the host enqueues several iterations between convergence checks.
+// the host enqueues several iterations (a captured graph) between convergence checks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,10 +24,12 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "psl_internal.hpp"
 
 using psl::kBlock;
+using psl::kCoarseRows;
 using psl::kMaxSlots;
 using psl::Scalars;
 using psl::Tile;
@@ -32,8 +37,8 @@ using psl::Tile;
 namespace {
 
 constexpr int kTileMax = 2048;       // cells per tile (LDS correction buffer size)
-constexpr int kCoarseRows = 16;      // GEMV rows per workgroup
-constexpr int kSChunk = 4096;        // s entries staged in LDS per pass
+constexpr int kSChunk = 4096;        // coarse vector entries staged in LDS per pass
+constexpr int kNW = kBlock / psl::kWave;
 
 struct Geo {
   int nx, ny, nz;
@@ -60,132 +65,151 @@ __device__ inline void cell_coords(const Tile& T, int j, float inv_sx, float inv
   iz = T.z0 + lz;
 }
 
-// Last-workgroup election: every block calls this once after publishing its partials
-// (thread 0 wrote them). Returns true in all threads of the last block to arrive, which
-// then sees every other block's partials. The counter is reset by that last block.
-__device__ inline bool last_block(uint32_t* counter) {
-  __shared__ int am_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(counter, 1u);
-    am_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (am_last) {
-    __threadfence();
-    if (threadIdx.x == 0) *counter = 0;
-  }
-  return am_last;
-}
-
-// Fixed-order sum of v[i*stride + off] over i < count by one workgroup.
-__device__ inline double block_reduce_strided(const double* v, int count, int stride, int off,
-                                              double* lds) {
+// Fixed-order sum of v[0..count) by one workgroup (result in every thread).
+__device__ inline double block_reduce(const double* v, int count, double* lds) {
   double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < count; i += kBlock) acc[0] += v[int64_t(i) * stride + off];
+  for (int i = threadIdx.x; i < count; i += kBlock) acc[0] += v[i];
   psl::block_sum<1>(acc, lds);
   return acc[0];
 }
 
-// s[l] = sum of the (tile, slot) partials of label l, in list order.
-__device__ inline void reduce_labels(const double* part, const int32_t* lab_ptr,
-                                     const int32_t* lab_part, double* s, int d) {
-  for (int l = threadIdx.x; l < d; l += kBlock) {
-    double acc = 0.0;
-    for (int i = lab_ptr[l]; i < lab_ptr[l + 1]; ++i) acc += part[lab_part[i]];
-    s[l] = acc;
-  }
+// Sum of the label-major partials of label l (contiguous, list order).
+__device__ inline double label_sum(const double* part, const int32_t* lab_ptr, int l) {
+  const int a = lab_ptr[l], b = lab_ptr[l + 1];
+  double acc = 0.0;
+#pragma unroll 4
+  for (int i = a; i < b; ++i) acc += part[i];
+  return acc;
+}
+
+// Publish the block-reduced per-slot sums acc[0..nslot) to their label-major positions.
+template <int NS>
+__device__ inline void write_slots(const double (&acc)[NS], int nslot, const int32_t* slot_pos,
+                                   int t, double* part) {
+#pragma unroll
+  for (int m = 0; m < NS; ++m)
+    if (int(threadIdx.x) == m && m < nslot) part[slot_pos[t * kMaxSlots + m]] = acc[m];
 }
 
 // ---------------------------------------------------------------------------------------
-// stencil pass. MODE 0: out = A in (inner CG, R = float or double), reductions (in, out)
-// and Z^T out. MODE 1: out = b - A in (float64 outer residual), reductions ||out||^2 and
-// Z^T out.
+// stencil pass. MODE 0: out = A in (inner CG, R = float or double), partials (in, out)
+// and Z^T out. MODE 1: out = b - A in (float64 refinement residual), partials ||out||^2
+// and Z^T out. The scalar partial goes to red[t].
 // ---------------------------------------------------------------------------------------
-template <typename R, int MODE, int NS, int RP>
+template <typename R, int MODE, int NS, int CPT>
 __global__ void __launch_bounds__(kBlock)
     k_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty, const R* __restrict__ Tz,
               const R* __restrict__ in, const double* __restrict__ b, R* __restrict__ out,
-              const uint8_t* __restrict__ slot, double* zq_part, const double* zr_part,
-              double* red_part, const int32_t* lab_ptr, const int32_t* lab_part, double* s,
-              double* sr, int d, Scalars* sc, int check_done) {
-  __shared__ double lds[(NS + 1) * (kBlock / psl::kWave)];
+              const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
+              double* zq, double* red, const Scalars* sc, int check_done) {
+  __shared__ double lds[(NS + 1) * kNW];
   if (check_done && sc->done) return;
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int sxy = nx * ny;
+  // issue every load of the thread's cells first
+  int cc[CPT];
+  int sl[CPT];
+  R pc[CPT], pw[CPT], pe[CPT], ps[CPT], pn[CPT], pb[CPT], pt[CPT];
+  R t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT];
+  double bv[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    cc[k] = -1;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const int c = ix + nx * (iy + ny * iz);
+      const int fx = c + (iy + ny * iz);          // ix + (nx+1)(iy + ny iz)
+      const int fy = c + nx * iz;                 // ix + nx(iy + (ny+1) iz)
+      cc[k] = c;
+      pc[k] = in[c];
+      pw[k] = ix > 0 ? in[c - 1] : R(0);
+      pe[k] = ix < nx - 1 ? in[c + 1] : R(0);
+      ps[k] = iy > 0 ? in[c - nx] : R(0);
+      pn[k] = iy < ny - 1 ? in[c + nx] : R(0);
+      pb[k] = iz > 0 ? in[c - sxy] : R(0);
+      pt[k] = iz < nz - 1 ? in[c + sxy] : R(0);
+      t0[k] = Tx[fx];
+      t1[k] = Tx[fx + 1];
+      t2[k] = Ty[fy];
+      t3[k] = Ty[fy + nx];
+      t4[k] = Tz[c];
+      t5[k] = Tz[c + sxy];
+      sl[k] = slot[c];
+      bv[k] = MODE == 1 ? b[c] : 0.0;
+    }
+  }
   double acc[NS + 1];
 #pragma unroll
   for (int k = 0; k <= NS; ++k) acc[k] = 0.0;
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
-    int ix, iy, iz;
-    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-    const int c = ix + nx * (iy + ny * iz);
-    const int fx = ix + (nx + 1) * (iy + ny * iz);
-    const int fy = ix + nx * (iy + (ny + 1) * iz);
-    const R pc = in[c];
-    const R pw = ix > 0 ? in[c - 1] : R(0);
-    const R pe = ix < nx - 1 ? in[c + 1] : R(0);
-    const R ps = iy > 0 ? in[c - nx] : R(0);
-    const R pn = iy < ny - 1 ? in[c + nx] : R(0);
-    const R pb = iz > 0 ? in[c - sxy] : R(0);
-    const R pt = iz < nz - 1 ? in[c + sxy] : R(0);
-    R ap = Tx[fx] * (pc - pw);
-    ap += Tx[fx + 1] * (pc - pe);
-    ap += Ty[fy] * (pc - ps);
-    ap += Ty[fy + nx] * (pc - pn);
-    ap += Tz[c] * (pc - pb);
-    ap += Tz[c + sxy] * (pc - pt);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (cc[k] < 0) continue;
+    const R p0 = pc[k];
+    R ap = t0[k] * (p0 - pw[k]);
+    ap += t1[k] * (p0 - pe[k]);
+    ap += t2[k] * (p0 - ps[k]);
+    ap += t3[k] * (p0 - pn[k]);
+    ap += t4[k] * (p0 - pb[k]);
+    ap += t5[k] * (p0 - pt[k]);
     double v;
     if (MODE == 0) {
-      out[c] = ap;
+      out[cc[k]] = ap;
       v = double(ap);
-      acc[NS] += double(pc) * v;
+      acc[NS] += double(p0) * v;
     } else {
-      const double r = b[c] - double(ap);
-      out[c] = R(r);
+      const double r = bv[k] - double(ap);
+      out[cc[k]] = R(r);
       v = r;
       acc[NS] += r * r;
     }
-    const int sl = slot[c];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) acc[k] += (sl == k) ? v : 0.0;
+    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? v : 0.0;
   }
   psl::block_sum<NS + 1>(acc, lds);
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < T.nslot; ++k) zq_part[t * kMaxSlots + k] = acc[k];
-    red_part[t * 4 + MODE] = acc[NS];
-  }
-  if (!last_block(&sc->cnt_a)) return;
-  __shared__ double lds2[kBlock / psl::kWave];
-  reduce_labels(zq_part, lab_ptr, lab_part, s, d);
-  if (RP) reduce_labels(zr_part, lab_ptr, lab_part, sr, d);  // Z^T rhat from the update pass
-  const double tot = block_reduce_strided(red_part, g.ntiles, 4, MODE, lds2);
-  if (threadIdx.x == 0) {
-    if (MODE == 0)
-      sc->pq = tot;
-    else
-      sc->rr = tot;
-  }
+  double zs[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) zs[m] = acc[m];
+  write_slots<NS>(zs, T.nslot, slot_pos, t, zq);
+  if (threadIdx.x == 0) red[t] = acc[NS];
+}
+
+// s = Z^T v (and sr = Z^T rhat when RP) from label-major partials, spread over workgroups
+// (used when the coarse kernel cannot stage all of s itself).
+template <int RP>
+__global__ void __launch_bounds__(kBlock)
+    k_reduce_s(const double* zq, const double* zr, const int32_t* lab_ptr, double* s, double* sr,
+               int d, const Scalars* sc, int check_done) {
+  if (check_done && sc->done) return;
+  const int l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= d) return;
+  s[l] = label_sum(zq, lab_ptr, l);
+  if (RP) sr[l] = label_sum(zr, lab_ptr, l);
 }
 
 // ---------------------------------------------------------------------------------------
-// coarse solve e = E^-1 s. MODE 0 (inner): alpha = rho / ((p, q) - s^T e) by the last
-// block, with breakdown / non-finite detection. MODE 1: e only.
+// coarse solve e = E^-1 s (and er = E^-1 sr when RP), kCoarseRows rows per workgroup.
+// FUSED: s is summed here from the label-major partials (d <= kSChunk); otherwise read
+// from global memory. Per workgroup: cpart[g] = sum over its rows of s_r e_r and
+// cpart[G + g] = its slice of the stencil scalar partials red[0..ntiles).
 // ---------------------------------------------------------------------------------------
-template <int MODE, int RP>
+template <int RP, int FUSED>
 __global__ void __launch_bounds__(kBlock)
-    k_coarse(const double* __restrict__ Einv, const double* __restrict__ s,
-             const double* __restrict__ sr, double* e, double* er, double* se_part, int d,
-             Scalars* sc, int check_done) {
-  __shared__ double ss[(RP ? 2 : 1) * kSChunk];
-  __shared__ double lds[kBlock / psl::kWave];
+    k_coarse(const double* __restrict__ Einv, const double* zq, const double* zr,
+             const int32_t* lab_ptr, double* s, double* sr, double* e, double* er,
+             const double* red, int ntiles, double* cpart, int d, const Scalars* sc,
+             int check_done) {
+  __shared__ double ss[kSChunk];
+  __shared__ double ss2[RP ? kSChunk : 1];
+  __shared__ double lds[2 * kNW];
   if (check_done && sc->done) return;
   const int lane = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
-  constexpr int kRowsPerWave = kCoarseRows / (kBlock / psl::kWave);
+  const int G = gridDim.x;
+  constexpr int kRowsPerWave = kCoarseRows / kNW;
   const int row0 = blockIdx.x * kCoarseRows + w * kRowsPerWave;
   double racc[kRowsPerWave], racc2[kRowsPerWave];
 #pragma unroll
@@ -194,8 +218,20 @@ __global__ void __launch_bounds__(kBlock)
     const int c1 = min(d, c0 + kSChunk);
     __syncthreads();
     for (int c = c0 + threadIdx.x; c < c1; c += kBlock) {
-      ss[c - c0] = s[c];
-      if (RP) ss[kSChunk + c - c0] = sr[c];
+      double v, v2 = 0.0;
+      if (FUSED) {
+        v = label_sum(zq, lab_ptr, c);
+        if (RP) v2 = label_sum(zr, lab_ptr, c);
+        if (blockIdx.x == 0) {
+          s[c] = v;
+          if (RP) sr[c] = v2;
+        }
+      } else {
+        v = s[c];
+        if (RP) v2 = sr[c];
+      }
+      ss[c - c0] = v;
+      if (RP) ss2[c - c0] = v2;
     }
     __syncthreads();
 #pragma unroll
@@ -207,41 +243,36 @@ __global__ void __launch_bounds__(kBlock)
         for (int c = c0 + lane; c < c1; c += psl::kWave) {
           const double m = erow[c];
           a += m * ss[c - c0];
-          if (RP) a2 += m * ss[kSChunk + c - c0];
+          if (RP) a2 += m * ss2[c - c0];
         }
         racc[r] += a;
         racc2[r] += a2;
       }
     }
   }
-  double se[1] = {0.0};
+  // s^T e over this workgroup's rows (s of a row from the staged chunk when d fits, else
+  // from global memory, which the fused path never needs)
+  double part[2] = {0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < kRowsPerWave; ++r) {
     const double v = psl::wave_sum(racc[r]);
     const double v2 = RP ? psl::wave_sum(racc2[r]) : 0.0;
     const int row = row0 + r;
-    if (row < d) {
-      if (lane == 0) {
-        e[row] = v;
-        if (RP) er[row] = v2;
-      }
-      se[0] += (lane == 0) ? v * s[row] : 0.0;
+    if (row < d && lane == 0) {
+      e[row] = v;
+      if (RP) er[row] = v2;
+      const double srow = (d <= kSChunk) ? ss[row] : s[row];
+      part[0] += v * srow;
     }
   }
-  psl::block_sum<1>(se, lds);
-  if (threadIdx.x == 0) se_part[blockIdx.x] = se[0];
-  if (!last_block(&sc->cnt_b)) return;
-  const double tot = block_reduce_strided(se_part, gridDim.x, 1, 0, lds);
-  if (MODE == 0 && threadIdx.x == 0) {
-    sc->se = tot;
-    const double pw = sc->pq - tot;
-    if (!(pw > 0.0)) {
-      sc->status = (pw == pw && fabs(pw) < INFINITY) ? PSL_EBREAKDOWN : PSL_ENONFINITE;
-      sc->done = 1;
-      sc->alpha = 0.0;
-    } else {
-      sc->alpha = sc->rho / pw;
-    }
+  // this workgroup's slice of the stencil scalar partials
+  const int ta = int((int64_t(ntiles) * blockIdx.x) / G);
+  const int tb = int((int64_t(ntiles) * (blockIdx.x + 1)) / G);
+  for (int t = ta + threadIdx.x; t < tb; t += kBlock) part[1] += red[t];
+  psl::block_sum<2>(part, lds);
+  if (threadIdx.x == 0) {
+    cpart[blockIdx.x] = part[0];
+    cpart[G + blockIdx.x] = part[1];
   }
 }
 
@@ -274,68 +305,142 @@ __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_p
 }
 
 // ---------------------------------------------------------------------------------------
-// CG update pass: rhat = rhat - alpha q + A Z (alpha e - er) (er = E^-1 Z^T rhat when
-// re-projecting, else 0), i.e. rhat <- P1 rhat - alpha P1 A p; xhat += alpha p;
-// y = M^-1 rhat; reductions (rhat, y), ||rhat||^2 and, when re-projecting, Z^T rhat.
-// The last block closes the iteration.
+// CG update pass. alpha = rho / ((p, q) - s^T e) from the coarse partials (every workgroup
+// reduces them in the same order, so all agree; a breakdown makes all of them return and
+// workgroup 0 records it). Then rhat = rhat - alpha q + A Z (alpha e - er) (i.e.
+// rhat <- P1 rhat - alpha P1 A p), xhat += alpha p, partials of (rhat, M^-1 rhat),
+// ||rhat||^2 (red2, red3) and, when re-projecting, Z^T rhat.
+// alpha_fixed != 0 replaces the computed alpha (kernel timing only).
 // ---------------------------------------------------------------------------------------
-template <typename R, int NS, int RP>
+template <typename R, int NS, int RP, int CPT>
 __global__ void __launch_bounds__(kBlock)
     k_update(Geo g, const R* __restrict__ q, const R* __restrict__ p, R* __restrict__ rh,
              R* __restrict__ xh, const R* __restrict__ invd, const uint8_t* __restrict__ slot,
-             const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
-             const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
-             const double* __restrict__ er, double* zr_part, double* red_part, Scalars* sc) {
+             const int32_t* __restrict__ slot_pos, const int32_t* az_ptr,
+             const int32_t* az_cell, const int32_t* az_lab, const int32_t* az_oth,
+             const R* az_t, const double* __restrict__ e, const double* __restrict__ er,
+             const double* cpart, int G, double* zr, double* red2, double* red3, Scalars* sc,
+             double alpha_fixed) {
   __shared__ double corr[kTileMax];
-  __shared__ double lds[(NS + 2) * (kBlock / psl::kWave)];
+  __shared__ double lds[(NS + 2) * kNW];
   if (sc->done) return;
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
-  const double alpha_d = sc->alpha;
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  // issue the cell loads first so their latency overlaps the reductions below
+  int cc[CPT];
+  int sl[CPT];
+  R qv[CPT], rv[CPT], xv[CPT], pv[CPT], dv[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    cc[k] = -1;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const int c = ix + g.nx * (iy + g.ny * iz);
+      cc[k] = c;
+      qv[k] = q[c];
+      rv[k] = rh[c];
+      xv[k] = xh[c];
+      pv[k] = p[c];
+      dv[k] = invd[c];
+      sl[k] = RP ? int(slot[c]) : 0;
+    }
+  }
+  double alpha_d = alpha_fixed;
+  if (alpha_fixed == 0.0) {
+    double pr[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < G; i += kBlock) {
+      pr[0] += cpart[i];
+      pr[1] += cpart[G + i];
+    }
+    psl::block_sum<2>(pr, lds);
+    const double pw = pr[1] - pr[0];   // (p, q) - s^T e = (p, P1 A p)
+    if (!(pw > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->status = (pw == pw && fabs(pw) < INFINITY) ? PSL_EBREAKDOWN : PSL_ENONFINITE;
+        sc->done = 1;
+        sc->alpha = 0.0;
+      }
+      return;
+    }
+    alpha_d = sc->rho / pw;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->alpha = alpha_d;
+      sc->pq = pr[1];
+      sc->se = pr[0];
+    }
+  }
   tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, alpha_d, RP ? er : nullptr,
                   -1.0, corr);
-  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const R alpha = R(alpha_d);
   double acc[NS + 2];
 #pragma unroll
   for (int k = 0; k < NS + 2; ++k) acc[k] = 0.0;
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
-    int ix, iy, iz;
-    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-    const int c = ix + g.nx * (iy + g.ny * iz);
-    const R r = rh[c] - alpha * q[c] + R(corr[j]);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (cc[k] < 0) continue;
+    const int c = cc[k];
+    const R r = rv[k] - alpha * qv[k] + R(corr[threadIdx.x + k * kBlock]);
     rh[c] = r;
-    xh[c] += alpha * p[c];
+    xh[c] = xv[k] + alpha * pv[k];
     const double rd = double(r);
-    acc[NS] += rd * double(r * invd[c]);
+    acc[NS] += rd * double(r * dv[k]);
     acc[NS + 1] += rd * rd;
     if (RP) {
-      const int sl = slot[c];
 #pragma unroll
-      for (int k = 0; k < NS; ++k) acc[k] += (sl == k) ? rd : 0.0;
+      for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? rd : 0.0;
     }
   }
   psl::block_sum<NS + 2>(acc, lds);
-  if (threadIdx.x == 0) {
-    red_part[t * 4 + 2] = acc[NS];
-    red_part[t * 4 + 3] = acc[NS + 1];
-    if (RP)
-      for (int k = 0; k < T.nslot; ++k) zr_part[t * kMaxSlots + k] = acc[k];
+  if (RP) {
+    double zs[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) zs[m] = acc[m];
+    write_slots<NS>(zs, T.nslot, slot_pos, t, zr);
   }
-  if (!last_block(&sc->cnt_c)) return;
-  const double ry = block_reduce_strided(red_part, g.ntiles, 4, 2, lds);
-  const double rr = block_reduce_strided(red_part, g.ntiles, 4, 3, lds);
   if (threadIdx.x == 0) {
-    sc->iters += 1;
-    sc->rr = rr;
-    if (!(fabs(ry) < INFINITY) || !(rr < INFINITY)) {
+    red2[t] = acc[NS];
+    red3[t] = acc[NS + 1];
+  }
+}
+
+// Close an iteration (INIT = 0) or the inner start (INIT = 1), one workgroup:
+// rho' = (rhat, M^-1 rhat), ||rhat||^2, beta = rho'/rho, convergence and failure flags.
+template <int INIT>
+__global__ void __launch_bounds__(kBlock) k_close(const double* red2, const double* red3,
+                                                  int ntiles, Scalars* sc) {
+  __shared__ double lds[2 * kNW];
+  if (!INIT && sc->done) return;
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < ntiles; i += kBlock) {
+    v[0] += red2[i];
+    v[1] += red3[i];
+  }
+  psl::block_sum<2>(v, lds);
+  if (threadIdx.x != 0) return;
+  const double ry = v[0], rr = v[1];
+  sc->rr = rr;
+  if (INIT) {
+    sc->rho = ry;
+    sc->iters = 0;
+    if (!(rr < INFINITY) || !(fabs(ry) < INFINITY)) {
       sc->status = PSL_ENONFINITE;
       sc->done = 1;
-    } else {
-      sc->beta = ry / sc->rho;
-      sc->rho = ry;
-      if (rr <= sc->goal2 || sc->iters >= sc->maxit) sc->done = 1;
+    } else if (rr <= sc->goal2 || sc->maxit <= 0) {
+      sc->done = 1;
     }
+    return;
+  }
+  sc->iters += 1;
+  if (!(fabs(ry) < INFINITY) || !(rr < INFINITY)) {
+    sc->status = PSL_ENONFINITE;
+    sc->done = 1;
+  } else {
+    sc->beta = ry / sc->rho;
+    sc->rho = ry;
+    if (rr <= sc->goal2 || sc->iters >= sc->maxit) sc->done = 1;
   }
 }
 
@@ -349,15 +454,15 @@ __global__ void k_direction(int n, const R* __restrict__ rh, const R* __restrict
     p[c] = rh[c] * invd[c] + beta * p[c];
 }
 
-// Inner start: rhat = sigma r (cast to R), xhat = 0, p = M^-1 rhat; rho = (rhat, p),
-// ||rhat||^2 (and Z^T rhat partials when re-projecting); done if already below the goal.
+// Inner start: rhat = sigma r (cast to R), xhat = 0, p = M^-1 rhat; partials of
+// (rhat, p), ||rhat||^2 and, when re-projecting, Z^T rhat (k_close<1> finishes).
 template <typename R, int NS, int RP>
 __global__ void __launch_bounds__(kBlock)
     k_inner_init(Geo g, const double* __restrict__ r, R* __restrict__ rh, R* __restrict__ xh,
                  R* __restrict__ p, const R* __restrict__ invd,
-                 const uint8_t* __restrict__ slot, double* zr_part, double* red_part,
-                 Scalars* sc) {
-  __shared__ double lds[(NS + 2) * (kBlock / psl::kWave)];
+                 const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
+                 double* zr, double* red2, double* red3, const Scalars* sc) {
+  __shared__ double lds[(NS + 2) * kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
@@ -380,41 +485,31 @@ __global__ void __launch_bounds__(kBlock)
     if (RP) {
       const int sl = slot[c];
 #pragma unroll
-      for (int k = 0; k < NS; ++k) acc[k] += (sl == k) ? rd : 0.0;
+      for (int m = 0; m < NS; ++m) acc[m] += (sl == m) ? rd : 0.0;
     }
   }
   psl::block_sum<NS + 2>(acc, lds);
-  if (threadIdx.x == 0) {
-    red_part[t * 4 + 2] = acc[NS];
-    red_part[t * 4 + 3] = acc[NS + 1];
-    if (RP)
-      for (int k = 0; k < T.nslot; ++k) zr_part[t * kMaxSlots + k] = acc[k];
+  if (RP) {
+    double zs[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) zs[m] = acc[m];
+    write_slots<NS>(zs, T.nslot, slot_pos, t, zr);
   }
-  if (!last_block(&sc->cnt_c)) return;
-  const double ry = block_reduce_strided(red_part, g.ntiles, 4, 2, lds);
-  const double rr = block_reduce_strided(red_part, g.ntiles, 4, 3, lds);
   if (threadIdx.x == 0) {
-    sc->rho = ry;
-    sc->rr = rr;
-    sc->iters = 0;
-    if (!(rr < INFINITY)) {
-      sc->status = PSL_ENONFINITE;
-      sc->done = 1;
-    } else if (rr <= sc->goal2 || sc->maxit <= 0) {
-      sc->done = 1;
-    }
+    red2[t] = acc[NS];
+    red3[t] = acc[NS + 1];
   }
 }
 
-// Outer deflation: x += Z e (if x != null), rout = rin - A Z e, ||rout||^2 -> sc->rr.
+// Refinement deflation: x += Z e (if x != null), rout = rin - A Z e, partial ||rout||^2.
+// rin and rout may alias (each cell reads rin before writing rout).
 __global__ void __launch_bounds__(kBlock)
     k_outer_deflate(Geo g, double* __restrict__ x, const double* rin, double* rout,
                     const int32_t* __restrict__ labels, const int32_t* az_ptr,
                     const int32_t* az_cell, const int32_t* az_lab, const int32_t* az_oth,
-                    const double* az_t, const double* __restrict__ e, double* red_part,
-                    Scalars* sc) {
+                    const double* az_t, const double* __restrict__ e, double* red) {
   __shared__ double corr[kTileMax];
-  __shared__ double lds[kBlock / psl::kWave];
+  __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, 1.0,
@@ -431,18 +526,15 @@ __global__ void __launch_bounds__(kBlock)
     acc[0] += r * r;
   }
   psl::block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) red_part[t * 4 + 1] = acc[0];
-  if (!last_block(&sc->cnt_c)) return;
-  const double rr = block_reduce_strided(red_part, g.ntiles, 4, 1, lds);
-  if (threadIdx.x == 0) sc->rr = rr;
+  if (threadIdx.x == 0) red[t] = acc[0];
 }
 
-// Z^T v partials only (for psl_deflate), last block -> s.
+// Z^T v partials only (label-major)
 template <int NS>
 __global__ void __launch_bounds__(kBlock)
-    k_zt(Geo g, const double* __restrict__ v, const uint8_t* __restrict__ slot, double* zq_part,
-         const int32_t* lab_ptr, const int32_t* lab_part, double* s, int d, Scalars* sc) {
-  __shared__ double lds[NS * (kBlock / psl::kWave)];
+    k_zt(Geo g, const double* __restrict__ v, const uint8_t* __restrict__ slot,
+         const int32_t* __restrict__ slot_pos, double* zq) {
+  __shared__ double lds[NS * kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
@@ -459,13 +551,35 @@ __global__ void __launch_bounds__(kBlock)
     for (int k = 0; k < NS; ++k) acc[k] += (sl == k) ? val : 0.0;
   }
   psl::block_sum<NS>(acc, lds);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < T.nslot; ++k) zq_part[t * kMaxSlots + k] = acc[k];
-  if (!last_block(&sc->cnt_a)) return;
-  reduce_labels(zq_part, lab_ptr, lab_part, s, d);
+  write_slots<NS>(acc, T.nslot, slot_pos, t, zq);
 }
 
-// x += scale * xhat (float64 accumulation of an inner correction)
+// ||v||^2 partials per tile
+__global__ void __launch_bounds__(kBlock) k_norm2(Geo g, const double* __restrict__ v,
+                                                  double* red) {
+  __shared__ double lds[kNW];
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = g.tiles[t];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  double acc[1] = {0.0};
+  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+    int ix, iy, iz;
+    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+    const double val = v[ix + g.nx * (iy + g.ny * iz)];
+    acc[0] += val * val;
+  }
+  psl::block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) red[t] = acc[0];
+}
+
+// *out = fixed-order sum of v[0..n) (one workgroup)
+__global__ void __launch_bounds__(kBlock) k_sum(const double* v, int n, double* out) {
+  __shared__ double lds[kNW];
+  const double s = block_reduce(v, n, lds);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// x += ||r|| xhat (float64 accumulation of an inner correction)
 template <typename R>
 __global__ void k_accumulate(int n, double* __restrict__ x, const R* __restrict__ xh,
                              const Scalars* sc) {
@@ -484,37 +598,37 @@ __global__ void k_set_inner(Scalars* sc, double goal2, int maxit) {
   sc->status = 0;
 }
 
+// measurement set-up: the iteration kernels run unconditionally (never "converge")
+__global__ void k_bench_prep(Scalars* sc) {
+  sc->done = 0;
+  sc->iters = 0;
+  sc->status = 0;
+  sc->goal2 = -1.0;
+  sc->maxit = 0x7fffffff;
+  sc->alpha = 1e-3;
+  sc->beta = 0.5;
+  sc->rho = 1.0;
+}
+
+// streaming copy used to calibrate byte counters and the achievable bandwidth
+__global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src,
+                                                   uint4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_reset(Scalars* sc) {
   sc->done = 0;
   sc->iters = 0;
   sc->status = 0;
-  sc->cnt_a = sc->cnt_b = sc->cnt_c = 0;
-}
-
-// ||v||^2 -> sc->bnorm2 and finiteness (tiles; used for b and x0)
-__global__ void __launch_bounds__(kBlock)
-    k_norm2(Geo g, const double* __restrict__ v, double* red_part, Scalars* sc, int into_b) {
-  __shared__ double lds[kBlock / psl::kWave];
-  const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
-  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
-  double acc[1] = {0.0};
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
-    int ix, iy, iz;
-    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-    const double val = v[ix + g.nx * (iy + g.ny * iz)];
-    acc[0] += val * val;
-  }
-  psl::block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) red_part[t * 4 + 0] = acc[0];
-  if (!last_block(&sc->cnt_a)) return;
-  const double tot = block_reduce_strided(red_part, g.ntiles, 4, 0, lds);
-  if (threadIdx.x == 0) {
-    if (into_b)
-      sc->bnorm2 = tot;
-    else
-      sc->rr = tot;
-  }
 }
 
 __global__ void k_zero(double* x, int n) {
@@ -531,11 +645,16 @@ inline unsigned elem_grid(int64_t n) {
   return static_cast<unsigned>(std::min<int64_t>((n + kBlock - 1) / kBlock, 256 * 64));
 }
 
+// scalar partial arrays, quantity-major: red + q * ntiles
+inline double* red(psl_ctx* c, int q) { return c->red + int64_t(q) * c->ntiles; }
+
 template <typename R>
 struct Prec;
 template <>
 struct Prec<double> {
-  static const double* face(const psl_ctx* c, int a) { return a == 0 ? c->Tx : (a == 1 ? c->Ty : c->Tz); }
+  static const double* face(const psl_ctx* c, int a) {
+    return a == 0 ? c->Tx : (a == 1 ? c->Ty : c->Tz);
+  }
   static const double* invd(const psl_ctx* c) { return c->invdiag; }
   static const double* azt(const psl_ctx* c) { return c->az_t; }
   static psl::VecSet<double>& vecs(psl_ctx* c) { return c->v64; }
@@ -544,7 +663,9 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
-  static const float* face(const psl_ctx* c, int a) { return a == 0 ? c->Tx32 : (a == 1 ? c->Ty32 : c->Tz32); }
+  static const float* face(const psl_ctx* c, int a) {
+    return a == 0 ? c->Tx32 : (a == 1 ? c->Ty32 : c->Tz32);
+  }
   static const float* invd(const psl_ctx* c) { return c->invdiag32; }
   static const float* azt(const psl_ctx* c) { return c->az_t32; }
   static psl::VecSet<float>& vecs(psl_ctx* c) { return c->v32; }
@@ -563,6 +684,19 @@ int ensure_vecs(psl_ctx* c) {
   return PSL_OK;
 }
 
+// Dispatch on the cells each thread owns (compile-time, so the loads can be hoisted).
+template <template <int> class F, typename... A>
+void with_cpt(int cpt, A&&... args) {
+  if (cpt <= 1)
+    F<1>::run(args...);
+  else if (cpt <= 2)
+    F<2>::run(args...);
+  else if (cpt <= 4)
+    F<4>::run(args...);
+  else
+    F<8>::run(args...);
+}
+
 // Dispatch on the number of label slots per tile (compile-time width of the segmented sums).
 template <template <int> class F, typename... A>
 void with_ns(int ns, A&&... args) {
@@ -578,36 +712,74 @@ void with_ns(int ns, A&&... args) {
     F<16>::run(args...);
 }
 
-template <typename R, int MODE, int RP>
+template <typename R, int MODE, int NS>
+struct StencilC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
+                    hipStream_t st) {
+      hipLaunchKernelGGL((k_stencil<R, MODE, NS, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
+                         in, b, out, c->slot, c->slot_pos, c->zq, red(c, 0), c->sc, check_done);
+    }
+  };
+};
+
+template <typename R, int MODE>
 struct StencilL {
   template <int NS>
   struct F {
     static void run(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
                     hipStream_t st) {
-      hipLaunchKernelGGL((k_stencil<R, MODE, NS, RP>), dim3(c->ntiles), dim3(kBlock), 0, st,
-                         geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
-                         in, b, out, c->slot, c->zq_part, c->zr_part, c->red_part, c->lab_ptr,
-                         c->lab_part, c->s, c->sr, c->d, c->sc, check_done);
+      with_cpt<StencilC<R, MODE, NS>::template F>(c->cpt, c, in, b, out, check_done, st);
     }
   };
 };
 
-template <typename R, int MODE, int RP = 0>
+// stencil pass alone: out = A in (MODE 0) or b - A in (MODE 1); partials in zq / red[0]
+template <typename R, int MODE>
 void launch_stencil(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
                     hipStream_t st) {
-  with_ns<StencilL<R, MODE, RP>::template F>(c->nslot_max, c, in, b, out, check_done, st);
+  with_ns<StencilL<R, MODE>::template F>(c->nslot_max, c, in, b, out, check_done, st);
 }
+
+// s (and sr) from the partials, then e (and er) = E^-1 s; coarse partials in cpart
+template <int RP>
+void launch_coarse(psl_ctx* c, int check_done, hipStream_t st) {
+  if (c->coarse_fused) {
+    hipLaunchKernelGGL((k_coarse<RP, 1>), dim3(c->coarse_blocks), dim3(kBlock), 0, st, c->Einv,
+                       c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, red(c, 0),
+                       c->ntiles, c->cpart, c->d, c->sc, check_done);
+  } else {
+    hipLaunchKernelGGL(k_reduce_s<RP>, dim3((c->d + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                       c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->d, c->sc, check_done);
+    hipLaunchKernelGGL((k_coarse<RP, 0>), dim3(c->coarse_blocks), dim3(kBlock), 0, st, c->Einv,
+                       c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, red(c, 0),
+                       c->ntiles, c->cpart, c->d, c->sc, check_done);
+  }
+}
+
+template <typename R, int RP, int NS>
+struct UpdateC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st, double alpha_fixed) {
+      psl::VecSet<R>& v = Prec<R>::vecs(c);
+      hipLaunchKernelGGL((k_update<R, NS, RP, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), v.q, v.p, v.rh, v.xh, Prec<R>::invd(c), c->slot, c->slot_pos,
+                         c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
+                         c->er, c->cpart, c->coarse_blocks, c->zr, red(c, 2), red(c, 3), c->sc,
+                         alpha_fixed);
+    }
+  };
+};
 
 template <typename R, int RP>
 struct UpdateL {
   template <int NS>
   struct F {
-    static void run(psl_ctx* c, hipStream_t st) {
-      psl::VecSet<R>& v = Prec<R>::vecs(c);
-      hipLaunchKernelGGL((k_update<R, NS, RP>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
-                         v.q, v.p, v.rh, v.xh, Prec<R>::invd(c), c->slot, c->az_ptr, c->az_cell,
-                         c->az_lab, c->az_oth, Prec<R>::azt(c), c->e, c->er, c->zr_part,
-                         c->red_part, c->sc);
+    static void run(psl_ctx* c, hipStream_t st, double alpha_fixed) {
+      with_cpt<UpdateC<R, RP, NS>::template F>(c->cpt, c, st, alpha_fixed);
     }
   };
 };
@@ -620,7 +792,7 @@ struct InitL {
       psl::VecSet<R>& v = Prec<R>::vecs(c);
       hipLaunchKernelGGL((k_inner_init<R, NS, RP>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), c->r64, v.rh, v.xh, v.p, Prec<R>::invd(c), c->slot,
-                         c->zr_part, c->red_part, c->sc);
+                         c->slot_pos, c->zr, red(c, 2), red(c, 3), c->sc);
     }
   };
 };
@@ -629,22 +801,15 @@ template <int NS>
 struct ZtL {
   static void run(psl_ctx* c, const double* r, hipStream_t st) {
     hipLaunchKernelGGL(k_zt<NS>, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), r, c->slot,
-                       c->zq_part, c->lab_ptr, c->lab_part, c->s, c->d, c->sc);
+                       c->slot_pos, c->zq);
   }
 };
-
-template <int MODE, int RP = 0>
-void launch_coarse(psl_ctx* c, int check_done, hipStream_t st) {
-  const int nbk = (c->d + kCoarseRows - 1) / kCoarseRows;
-  hipLaunchKernelGGL((k_coarse<MODE, RP>), dim3(nbk), dim3(kBlock), 0, st, c->Einv, c->s, c->sr,
-                     c->e, c->er, c->se_part, c->d, c->sc, check_done);
-}
 
 void launch_outer_deflate(psl_ctx* c, double* x, const double* rin, double* rout,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_outer_deflate, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), x, rin,
                      rout, c->labels, c->az_ptr, c->az_cell, c->az_lab, c->az_oth, c->az_t,
-                     c->e, c->red_part, c->sc);
+                     c->e, red(c, 1));
 }
 
 // r = b - A x ; then twice: x += Z E^-1 Z^T r, r = P1 r  (||r||^2 -> sc->rr).
@@ -655,20 +820,23 @@ void launch_outer_deflate(psl_ctx* c, double* x, const double* rin, double* rout
 // already tiny Z^T r).
 void enqueue_outer_step(psl_ctx* c, const double* b, double* x, hipStream_t st) {
   launch_stencil<double, 1>(c, x, b, c->r64, 0, st);
-  launch_coarse<1>(c, 0, st);
+  launch_coarse<0>(c, 0, st);
   launch_outer_deflate(c, x, c->r64, c->r64, st);
   with_ns<ZtL>(c->nslot_max, c, c->r64, st);
-  launch_coarse<1>(c, 0, st);
+  launch_coarse<0>(c, 0, st);
   launch_outer_deflate(c, x, c->r64, c->r64, st);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->rr);
 }
 
-// one CG iteration (four launches)
+// one CG iteration
 template <typename R, int RP>
 void enqueue_iteration(psl_ctx* c, hipStream_t st) {
   psl::VecSet<R>& v = Prec<R>::vecs(c);
-  launch_stencil<R, 0, RP>(c, v.p, nullptr, v.q, 1, st);
-  launch_coarse<0, RP>(c, 1, st);
-  with_ns<UpdateL<R, RP>::template F>(c->nslot_max, c, st);
+  launch_stencil<R, 0>(c, v.p, nullptr, v.q, 1, st);
+  launch_coarse<RP>(c, 1, st);
+  with_ns<UpdateL<R, RP>::template F>(c->nslot_max, c, st, 0.0);
+  hipLaunchKernelGGL(k_close<0>, dim3(1), dim3(kBlock), 0, st, red(c, 2), red(c, 3), c->ntiles,
+                     c->sc);
   hipLaunchKernelGGL(k_direction<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n),
                      v.rh, Prec<R>::invd(c), v.p, c->sc);
 }
@@ -726,7 +894,7 @@ int read_scalars(psl_ctx* c, hipStream_t st) {
 
 constexpr int kStallWindow = 512;   // inner iterations without halving ||rhat|| -> stop
 
-// Inner deflated PCG on the current outer residual (c->r64, ||r||^2 in sc->rr); adds
+// Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
 template <typename R>
 int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, int rp,
@@ -739,6 +907,8 @@ int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, 
     with_ns<InitL<R, 1>::template F>(c->nslot_max, c, st);
   else
     with_ns<InitL<R, 0>::template F>(c->nslot_max, c, st);
+  hipLaunchKernelGGL(k_close<1>, dim3(1), dim3(kBlock), 0, st, red(c, 2), red(c, 3), c->ntiles,
+                     c->sc);
   double best = INFINITY;
   int best_it = 0;
   *stalled = 0;
@@ -778,7 +948,6 @@ int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, 
 extern "C" int psl_apply_A(psl_ctx* c, const double* p, double* q, void* stream) {
   if (!c || !p || !q || p == q) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, c->sc);
   launch_stencil<double, 0>(c, p, nullptr, q, 0, st);
   PSL_HIP(hipGetLastError());
   return PSL_OK;
@@ -788,9 +957,8 @@ extern "C" int psl_deflate(psl_ctx* c, const double* r, double* out, double* cve
                            void* stream) {
   if (!c || !r || !out) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, c->sc);
   with_ns<ZtL>(c->nslot_max, c, r, st);
-  launch_coarse<1>(c, 0, st);
+  launch_coarse<0>(c, 0, st);
   // out may alias r: each cell reads r before writing out
   launch_outer_deflate(c, nullptr, r, out, st);
   if (cvec)
@@ -824,11 +992,13 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   };
   int rc;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, c->sc);
-  hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), b, c->red_part,
-                     c->sc, 1);
-  if (o.use_x0)
-    hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), x, c->red_part,
-                       c->sc, 0);
+  hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), b, red(c, 1));
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles,
+                     &c->sc->bnorm2);
+  if (o.use_x0) {
+    hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), x, red(c, 1));
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->rr);
+  }
   if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
   const double bnorm = std::sqrt(c->h_sc->bnorm2);
   stats.bnorm = bnorm;
@@ -893,7 +1063,8 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
     }
     if (rc != PSL_OK) return finish(rc);
     if (verbose)
-      std::fprintf(stderr, "libpsl:   inner %d iterations, status %d, stalled %d, ||rhat||/||rhat0|| = %.3e\n",
+      std::fprintf(stderr,
+                   "libpsl:   inner %d iterations, status %d, stalled %d, ||rhat||/||rhat0|| = %.3e\n",
                    it, ist, stalled, std::sqrt(c->h_sc->rr));
     total_iters += it;
     stats.iters = total_iters;
@@ -907,8 +1078,68 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   }
   // fresh float64 residual of the returned x
   launch_stencil<double, 1>(c, x, b, c->t64, 0, st);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
   if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
   stats.relres_true = std::sqrt(c->h_sc->rr) / bnorm;
   stats.iters = total_iters;
   return finish(status);
+}
+
+extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t reps,
+                                void* stream) {
+  if (!c || reps < 1 || (mode != PSL_FP64 && mode != PSL_MIXED) || kernel < 0 ||
+      kernel > PSL_KERNEL_OUTER_RESIDUAL)
+    return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = mode == PSL_MIXED ? ensure_vecs<float>(c) : ensure_vecs<double>(c);
+  if (rc != PSL_OK) return rc;
+  hipLaunchKernelGGL(k_bench_prep, dim3(1), dim3(1), 0, st, c->sc);
+  for (int i = 0; i < reps; ++i) {
+    switch (kernel) {
+      case PSL_KERNEL_STENCIL:
+        if (mode == PSL_MIXED)
+          launch_stencil<float, 0>(c, c->v32.p, nullptr, c->v32.q, 1, st);
+        else
+          launch_stencil<double, 0>(c, c->v64.p, nullptr, c->v64.q, 1, st);
+        break;
+      case PSL_KERNEL_COARSE:
+        if (mode == PSL_MIXED)
+          launch_coarse<1>(c, 1, st);
+        else
+          launch_coarse<0>(c, 1, st);
+        break;
+      case PSL_KERNEL_UPDATE:
+        if (mode == PSL_MIXED)
+          with_ns<UpdateL<float, 1>::template F>(c->nslot_max, c, st, 1e-3);
+        else
+          with_ns<UpdateL<double, 0>::template F>(c->nslot_max, c, st, 1e-3);
+        break;
+      case PSL_KERNEL_DIRECTION:
+        if (mode == PSL_MIXED)
+          hipLaunchKernelGGL(k_direction<float>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                             int(c->n), c->v32.rh, c->invdiag32, c->v32.p, c->sc);
+        else
+          hipLaunchKernelGGL(k_direction<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                             int(c->n), c->v64.rh, c->invdiag, c->v64.p, c->sc);
+        break;
+      default:
+        launch_stencil<double, 1>(c, c->r64, c->r64, c->t64, 0, st);
+        break;
+    }
+  }
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
+extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* stream) {
+  if (!src || !dst || bytes <= 0 || (bytes % 16) != 0 ||
+      (reinterpret_cast<uintptr_t>(src) % 16) || (reinterpret_cast<uintptr_t>(dst) % 16))
+    return PSL_EINVAL;
+  const int64_t n16 = bytes / 16;
+  const unsigned grid =
+      static_cast<unsigned>(std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16));
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
 }

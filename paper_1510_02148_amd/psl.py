@@ -45,6 +45,12 @@ class psl_solve_opts(ctypes.Structure):
                 ("reproject", ctypes.c_int32)]
 
 
+class psl_ctx_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("m_faces", ctypes.c_int64), ("nslot_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class psl_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("fell_back", ctypes.c_int32), ("relres_true", ctypes.c_double),
@@ -79,12 +85,16 @@ _apply_a = _sig("psl_apply_A", ctypes.c_int, [_P, _P, _P, _P])
 _deflate = _sig("psl_deflate", ctypes.c_int, [_P, _P, _P, _P, _P])
 _get_coarse = _sig("psl_get_coarse", ctypes.c_int, [_P, _P, _P, _I32P, _P])
 _destroy = _sig("psl_destroy", None, [_P])
+_get_info = _sig("psl_get_info", ctypes.c_int, [_P, ctypes.POINTER(psl_ctx_info)])
+_bench_kernel = _sig("psl_bench_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P])
+_bench_copy = _sig("psl_bench_copy", ctypes.c_int, [_P, _P, ctypes.c_int64, _P])
 _status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
 _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
 
 EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_setup_E", "psl_solve", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
-            "psl_default_opts")
+            "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info")
+KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL = range(5)
 
 
 class PslError(RuntimeError):
@@ -273,6 +283,25 @@ def psl_get_coarse(ctx: Context, device="cuda"):
                        _dev(Einv, torch.float64, d * d, "Einv"), ctypes.byref(dd), _stream()),
            "psl_get_coarse")
     return E, Einv
+
+
+def psl_get_info(ctx: Context) -> dict:
+    info = psl_ctx_info()
+    _check(_get_info(ctx.handle, ctypes.byref(info)), "psl_get_info")
+    return {k: getattr(info, k) for k, _ in info._fields_ if k != "reserved"}
+
+
+def psl_bench_kernel(ctx: Context, kernel: int, mode: int, reps: int):
+    _check(_bench_kernel(ctx.handle, int(kernel), int(mode), int(reps), _stream()),
+           "psl_bench_kernel")
+
+
+def psl_bench_copy(src: torch.Tensor, dst: torch.Tensor):
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("psl_bench_copy: src and dst must be device tensors of equal size")
+    _check(_bench_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                       nbytes, _stream()), "psl_bench_copy")
 
 
 def psl_destroy(ctx: Context):
