@@ -205,11 +205,11 @@ int psl_deflate(psl_ctx* ctx, const double* r, double* out, double* c, void* str
 int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stream);
 
 /* ---- measurement entry points (used by the benchmark and the profiler runs) ------- */
-#define PSL_KERNEL_STENCIL        0  /* q = A p, (p, q), Z^T q        (CG pass 1)          */
-#define PSL_KERNEL_COARSE         1  /* e = E^-1 Z^T q, alpha          (coarse GEMV)        */
-#define PSL_KERNEL_UPDATE         2  /* rhat, xhat update with A Z e   (CG pass 2)          */
-#define PSL_KERNEL_DIRECTION      3  /* p = M^-1 rhat + beta p         (CG pass 3)          */
-#define PSL_KERNEL_OUTER_RESIDUAL 4  /* r = b - A x in float64         (refinement step)    */
+#define PSL_KERNEL_STENCIL        0  /* v = A M^-1 r and the CG inner products (pass 1) */
+#define PSL_KERNEL_COARSE         1  /* e = E^-1 Z^T v (coarse GEMV) and scalar slices    */
+#define PSL_KERNEL_UPDATE         2  /* p, q, x, r updates with A Z e   (pass 2)          */
+#define PSL_KERNEL_DIRECTION      3  /* reserved (the direction update is part of pass 2) */
+#define PSL_KERNEL_OUTER_RESIDUAL 4  /* r = b - A x in float64          (refinement step) */
 
 /*
  * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
@@ -218,7 +218,7 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
  * precision of `mode`, so a caller can time it with events on `stream`. Call after a
  * psl_solve in the same mode (the vectors then hold a real iterate); the scalars are set
  * so that no launch exits early. The work vectors are overwritten.
- * Errors: PSL_EINVAL (bad kernel id, mode or reps < 1), PSL_ENOMEM.
+ * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1), PSL_ENOMEM.
  */
 int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
 

@@ -24,30 +24,33 @@ struct Tile {
   int32_t nslot;        // distinct labels in the tile
 };
 
-// Device-resident scalars of one solve; read and written only by kernels.
+// Device-resident scalars of one solve; read and written only by kernels. Quantities
+// carried from one CG iteration to the next are double-buffered by iteration parity, so a
+// kernel reads slot (i+1)&1 while its workgroup 0 writes slot i&1.
 struct Scalars {
-  double rho;        // (rhat, M^-1 rhat)
-  double alpha;
-  double beta;
-  double pq;         // (p, A p)
-  double se;         // s^T e
-  double rr;         // ||rhat||^2
-  double goal2;      // inner stop: ||rhat||^2 <= goal2
-  double rnorm;      // FP64 outer residual norm
-  double sigma;      // inner scale: rhat0 = sigma * r
+  double gamma[2];   // (r, M^-1 r)
+  double alpha[2];   // step length
+  double rr;         // ||r||^2 at the last check
+  double goal2;      // inner stop: ||r||^2 <= goal2
+  double rnorm;      // float64 refinement residual norm
+  double sigma;      // inner scale: r0 = sigma * r
   double bnorm2;
+  double delta;      // (p, P1 A p) of the last step (diagnostic)
+  int32_t cnt[2];    // iterations done
   int32_t done;      // inner loop finished (converged or failed)
   int32_t iters;     // inner iterations done in this inner solve
   int32_t status;    // PSL_OK or failure code raised on device
-  int32_t maxit;     // remaining iteration budget for this inner solve
+  int32_t maxit;     // iteration budget for this inner solve
 };
 
 template <typename R>
 struct VecSet {       // inner CG vectors in precision R
-  R* xh = nullptr;
-  R* rh = nullptr;
-  R* p = nullptr;
-  R* q = nullptr;
+  R* xh = nullptr;      // iterate of the deflated system
+  R* rh = nullptr;      // residual
+  R* p = nullptr;       // search direction
+  R* q = nullptr;       // P1 A p, by recurrence
+  R* v = nullptr;       // A M^-1 r
+  R* u = nullptr;       // M^-1 r
 };
 
 }  // namespace psl
@@ -94,7 +97,7 @@ struct psl_ctx {
   double* zq = nullptr;               // [npart] label-major partials of Z^T q (or Z^T r)
   double* zr = nullptr;               // [npart] label-major partials of Z^T rhat
   double* red = nullptr;              // [4*ntiles] per-tile scalar partials, quantity-major
-  double* cpart = nullptr;            // [2*coarse_blocks] s^T e and (p, q) partials
+  double* cpart = nullptr;            // [4*coarse_blocks] s^T e and slices of the CG partials
   double* s = nullptr;                // [d]
   double* e = nullptr;                // [d]
   double* sr = nullptr;               // [d] Z^T rhat
@@ -109,6 +112,7 @@ struct psl_ctx {
   hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
   hipStream_t graph_stream64 = nullptr, graph_stream32 = nullptr;
   int graph_chunk64 = 0, graph_chunk32 = 0;
+  int last_iters64[8] = {0}, last_iters32[8] = {0};  // inner iterations per refinement step
 };
 
 #define PSL_HIP(call)                                                              \
@@ -154,6 +158,19 @@ __device__ inline void block_sum(double (&v)[NV], double* lds) {
     v[k] = acc;
   }
   __syncthreads();
+}
+
+// Element load/store with a 32-bit element index: the byte offset is formed in 32 bits
+// and added to the (wave-uniform) base, which lets the compiler use the scalar-base plus
+// 32-bit vector-offset addressing form instead of 64-bit vector address arithmetic.
+// Valid for arrays below 4 GiB.
+template <typename T>
+__device__ inline T ld(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + i * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ inline void st(T* base, uint32_t i, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + i * uint32_t(sizeof(T))) = v;
 }
 
 // j / d for 0 <= j < 2^22, 1 <= d <= 2^11, via a float reciprocal with exact fix-up.

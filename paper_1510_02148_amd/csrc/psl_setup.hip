@@ -828,8 +828,8 @@ extern "C" void psl_destroy(psl_ctx* c) {
                   c->az_ptr, c->az_cell, c->az_lab, c->az_oth, c->az_t, c->az_t32, c->E, c->Einv,
                   c->zq, c->zr, c->red, c->s, c->e, c->sr, c->er, c->cpart, c->slot_pos,
                   c->r64, c->t64, c->sc,
-                  c->v64.xh, c->v64.rh, c->v64.p, c->v64.q, c->v32.xh, c->v32.rh, c->v32.p,
-                  c->v32.q};
+                  c->v64.xh, c->v64.rh, c->v64.p, c->v64.q, c->v64.v, c->v64.u, c->v32.xh,
+                  c->v32.rh, c->v32.p, c->v32.q, c->v32.v, c->v32.u};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -1064,7 +1064,7 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
   if (dalloc(&c->zq, std::max(1, c->npart)) || dalloc(&c->zr, std::max(1, c->npart)) ||
       dalloc(&c->red, int64_t(c->ntiles) * 4) || dalloc(&c->s, d) || dalloc(&c->e, d) ||
-      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->cpart, 2 * c->coarse_blocks) ||
+      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->cpart, 4 * c->coarse_blocks) ||
       dalloc(&c->r64, n) || dalloc(&c->t64, n) || dalloc(&c->sc, 1))
     PSL_FAIL(PSL_ENOMEM);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(psl::Scalars)) != hipSuccess)

@@ -1,17 +1,21 @@
 // libpsl solve path: deflated Jacobi-PCG (DEF1 form) on P1 A xhat = P1 b inside a float64
 // refinement loop, plus the stand-alone operator entry points (A p, P1 r).
 //
-// One CG iteration is five launches on the caller's stream:
-//   stencil         q = A p (flux form); per tile (p, q) and Z^T q partials
-//   coarse          s = Z^T q from the label-major partials, e = E^-1 s (float64 GEMV);
-//                   per workgroup s^T e and (p, q) partials
-//                   (large d: a separate label-reduction kernel produces s first)
-//   update          alpha = rho / ((p, q) - s^T e) (each workgroup, same fixed order);
-//                   rhat = rhat - alpha q + A Z (alpha e - er), xhat += alpha p, where
-//                   er = E^-1 Z^T rhat when re-projecting (else 0); partials of
-//                   (rhat, M^-1 rhat), ||rhat||^2 and Z^T rhat
-//   close           one workgroup: beta, rho, convergence and failure flags, count
-//   direction       p = M^-1 rhat + beta p
+// The CG runs in its single-reduction form (the recurrences of Chronopoulos and Gear):
+// with u = M^-1 r, v = A u, w = P1 v = v - A Z E^-1 Z^T v,
+//   gamma = (r, u), delta = (w, u) = (v, u) - s^T e  (s = Z^T v, e = E^-1 s),
+//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev),
+//   p = u + beta p, q = w + beta q (= P1 A p), x += alpha p, r -= alpha q,
+// which produces the same iterates as the two-reduction loop in exact arithmetic but needs
+// one pass over the grid for all its inner products. One iteration is three launches:
+//   stencil   v = A M^-1 r (flux form); per tile Z^T v, (v, u), (r, u), (r, r) partials
+//             (and Z^T r when re-projecting)
+//   coarse    s = Z^T v from the label-major partials, e = E^-1 s (float64 GEMV; er =
+//             E^-1 Z^T r as a second right-hand side); per workgroup s^T e and slices of
+//             the scalar partials (large d: a label-reduction kernel produces s first)
+//   update    alpha, beta from the coarse partials (every workgroup in the same fixed
+//             order), convergence / failure test, then the vector updates with
+//             A Z e (and A Z er: r <- P1 r - alpha q when re-projecting)
 // A Z v is evaluated only on cells with a cut face, in flux form sum T (v_l(i) - v_l(j)).
 // Partial sums cross workgroups only through kernel boundaries (no in-kernel fences), and
 // every reduction is a fixed-order tree: reruns with the same tiling are bit-identical.
@@ -39,6 +43,7 @@ namespace {
 constexpr int kTileMax = 2048;       // cells per tile (LDS correction buffer size)
 constexpr int kSChunk = 4096;        // coarse vector entries staged in LDS per pass
 constexpr int kNW = kBlock / psl::kWave;
+constexpr int kCgQ = 3;              // scalar partials of the CG stencil pass: (v,u), (r,u), (r,r)
 
 struct Geo {
   int nx, ny, nz;
@@ -92,18 +97,16 @@ __device__ inline void write_slots(const double (&acc)[NS], int nslot, const int
 }
 
 // ---------------------------------------------------------------------------------------
-// stencil pass. MODE 0: out = A in (inner CG, R = float or double), partials (in, out)
-// and Z^T out. MODE 1: out = b - A in (float64 refinement residual), partials ||out||^2
-// and Z^T out. The scalar partial goes to red[t].
+// plain stencil pass. MODE 0: out = A in; MODE 1: out = b - A in (float64 refinement
+// residual). Partials per tile: Z^T out (zq) and (in, out) resp. ||out||^2 (red[t]).
 // ---------------------------------------------------------------------------------------
 template <typename R, int MODE, int NS, int CPT>
 __global__ void __launch_bounds__(kBlock)
     k_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty, const R* __restrict__ Tz,
               const R* __restrict__ in, const double* __restrict__ b, R* __restrict__ out,
               const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
-              double* zq, double* red, const Scalars* sc, int check_done) {
+              double* zq, double* red) {
   __shared__ double lds[(NS + 1) * kNW];
-  if (check_done && sc->done) return;
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
@@ -178,7 +181,103 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) red[t] = acc[NS];
 }
 
-// s = Z^T v (and sr = Z^T rhat when RP) from label-major partials, spread over workgroups
+// ---------------------------------------------------------------------------------------
+// CG stencil pass: v = A u with u = M^-1 r (kept by the update pass). Partials per tile:
+// Z^T v (zq), (v, u), (r, u), (r, r) (red[q * ntiles + t]) and, when re-projecting, Z^T r
+// (zr).
+// ---------------------------------------------------------------------------------------
+template <typename R, int NS, int RP, int CPT>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
+                 const R* __restrict__ Tz, const R* __restrict__ r, const R* __restrict__ u,
+                 R* __restrict__ v, const uint8_t* __restrict__ slot,
+                 const int32_t* __restrict__ slot_pos, double* zq, double* zr, double* red,
+                 const Scalars* sc) {
+  using psl::ld;
+  constexpr int NA = NS + 3 + (RP ? NS : 0);
+  __shared__ double lds[NA * kNW];
+  if (sc->done) return;
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = g.tiles[t];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int sxy = nx * ny;
+  int cc[CPT];
+  int sl[CPT];
+  R rc[CPT], uc[CPT], uw[CPT], ue[CPT], us[CPT], un[CPT], ub[CPT], ut[CPT];
+  R t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    cc[k] = -1;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const uint32_t c = ix + nx * (iy + ny * iz);
+      const uint32_t fx = c + (iy + ny * iz);
+      const uint32_t fy = c + nx * iz;
+      cc[k] = int(c);
+      rc[k] = ld(r, c);
+      uc[k] = ld(u, c);
+      uw[k] = ix > 0 ? ld(u, c - 1) : R(0);
+      ue[k] = ix < nx - 1 ? ld(u, c + 1) : R(0);
+      us[k] = iy > 0 ? ld(u, c - nx) : R(0);
+      un[k] = iy < ny - 1 ? ld(u, c + nx) : R(0);
+      ub[k] = iz > 0 ? ld(u, c - sxy) : R(0);
+      ut[k] = iz < nz - 1 ? ld(u, c + sxy) : R(0);
+      t0[k] = ld(Tx, fx);
+      t1[k] = ld(Tx, fx + 1);
+      t2[k] = ld(Ty, fy);
+      t3[k] = ld(Ty, fy + nx);
+      t4[k] = ld(Tz, c);
+      t5[k] = ld(Tz, c + sxy);
+      sl[k] = ld(slot, c);
+    }
+  }
+  double acc[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (cc[k] < 0) continue;
+    const R u0 = uc[k];
+    R av = t0[k] * (u0 - uw[k]);
+    av += t1[k] * (u0 - ue[k]);
+    av += t2[k] * (u0 - us[k]);
+    av += t3[k] * (u0 - un[k]);
+    av += t4[k] * (u0 - ub[k]);
+    av += t5[k] * (u0 - ut[k]);
+    psl::st(v, uint32_t(cc[k]), av);
+    const double vd = double(av);
+    acc[NS] += double(av * u0);
+    acc[NS + 1] += double(rc[k] * u0);
+    acc[NS + 2] += double(rc[k] * rc[k]);
+#pragma unroll
+    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? vd : 0.0;
+    if (RP) {
+      const double rd = double(rc[k]);
+#pragma unroll
+      for (int m = 0; m < NS; ++m) acc[NS + 3 + m] += (sl[k] == m) ? rd : 0.0;
+    }
+  }
+  psl::block_sum<NA>(acc, lds);
+  double zs[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) zs[m] = acc[m];
+  write_slots<NS>(zs, T.nslot, slot_pos, t, zq);
+  if (RP) {
+#pragma unroll
+    for (int m = 0; m < NS; ++m) zs[m] = acc[NS + 3 + m];
+    write_slots<NS>(zs, T.nslot, slot_pos, t, zr);
+  }
+  if (threadIdx.x == 0) {
+    red[t] = acc[NS];
+    red[g.ntiles + t] = acc[NS + 1];
+    red[2 * g.ntiles + t] = acc[NS + 2];
+  }
+}
+
+// s = Z^T v (and sr = Z^T r when RP) from label-major partials, spread over workgroups
 // (used when the coarse kernel cannot stage all of s itself).
 template <int RP>
 __global__ void __launch_bounds__(kBlock)
@@ -194,10 +293,10 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------------------
 // coarse solve e = E^-1 s (and er = E^-1 sr when RP), kCoarseRows rows per workgroup.
 // FUSED: s is summed here from the label-major partials (d <= kSChunk); otherwise read
-// from global memory. Per workgroup: cpart[g] = sum over its rows of s_r e_r and
-// cpart[G + g] = its slice of the stencil scalar partials red[0..ntiles).
+// from global memory. Per workgroup g of G: cpart[g] = sum over its rows of s_r e_r and,
+// for q < NQ, cpart[(1 + q) G + g] = its slice of the tile partials red[q * ntiles + .].
 // ---------------------------------------------------------------------------------------
-template <int RP, int FUSED>
+template <int RP, int FUSED, int NQ>
 __global__ void __launch_bounds__(kBlock)
     k_coarse(const double* __restrict__ Einv, const double* zq, const double* zr,
              const int32_t* lab_ptr, double* s, double* sr, double* e, double* er,
@@ -205,7 +304,7 @@ __global__ void __launch_bounds__(kBlock)
              int check_done) {
   __shared__ double ss[kSChunk];
   __shared__ double ss2[RP ? kSChunk : 1];
-  __shared__ double lds[2 * kNW];
+  __shared__ double lds[(1 + NQ) * kNW];
   if (check_done && sc->done) return;
   const int lane = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
   const int G = gridDim.x;
@@ -240,6 +339,7 @@ __global__ void __launch_bounds__(kBlock)
       if (row < d) {
         const double* erow = Einv + int64_t(row) * d;
         double a = 0.0, a2 = 0.0;
+#pragma unroll 8
         for (int c = c0 + lane; c < c1; c += psl::kWave) {
           const double m = erow[c];
           a += m * ss[c - c0];
@@ -250,9 +350,9 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
   }
-  // s^T e over this workgroup's rows (s of a row from the staged chunk when d fits, else
-  // from global memory, which the fused path never needs)
-  double part[2] = {0.0, 0.0};
+  double part[1 + NQ];
+#pragma unroll
+  for (int q = 0; q <= NQ; ++q) part[q] = 0.0;
 #pragma unroll
   for (int r = 0; r < kRowsPerWave; ++r) {
     const double v = psl::wave_sum(racc[r]);
@@ -265,72 +365,86 @@ __global__ void __launch_bounds__(kBlock)
       part[0] += v * srow;
     }
   }
-  // this workgroup's slice of the stencil scalar partials
   const int ta = int((int64_t(ntiles) * blockIdx.x) / G);
   const int tb = int((int64_t(ntiles) * (blockIdx.x + 1)) / G);
-  for (int t = ta + threadIdx.x; t < tb; t += kBlock) part[1] += red[t];
-  psl::block_sum<2>(part, lds);
-  if (threadIdx.x == 0) {
-    cpart[blockIdx.x] = part[0];
-    cpart[G + blockIdx.x] = part[1];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    for (int t = ta + threadIdx.x; t < tb; t += kBlock) part[1 + q] += red[q * ntiles + t];
+  psl::block_sum<1 + NQ>(part, lds);
+  if (threadIdx.x <= NQ) {
+    double val = part[0];
+#pragma unroll
+    for (int q = 1; q <= NQ; ++q)
+      if (int(threadIdx.x) == q) val = part[q];
+    cpart[threadIdx.x * G + blockIdx.x] = val;
   }
 }
 
-// Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other),
-// v = ca * e + cb * e2 (e2 may be null), v_other = 0 across an outer face; 0 elsewhere.
-template <typename CT>
+// Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other)
+// (v_other = 0 across an outer face; 0 on cells without a cut face). Two coarse vectors
+// at once: corr1 from e1, corr2 from e2 (skipped when e2 is null).
+template <typename CT, typename ST>
 __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_ptr,
                                        const int32_t* az_cell, const int32_t* az_lab,
-                                       const int32_t* az_oth, const CT* az_t, const double* e,
-                                       double ca, const double* e2, double cb, double* corr) {
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) corr[j] = 0.0;
+                                       const int32_t* az_oth, const CT* az_t, const double* e1,
+                                       const double* e2, ST* corr1, ST* corr2) {
+  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+    corr1[j] = ST(0);
+    if (e2) corr2[j] = ST(0);
+  }
   __syncthreads();
   const int a = az_ptr[t], b = az_ptr[t + 1];
   for (int k = a + threadIdx.x; k < b; k += kBlock) {
     const int32_t cw = az_cell[k];
     if (cw >= 0) continue;  // not the first face of its cell
     const int ls = az_lab[k];
-    const double vs = ca * e[ls] + (e2 ? cb * e2[ls] : 0.0);
-    double acc = 0.0;
+    const double vs1 = e1[ls];
+    const double vs2 = e2 ? e2[ls] : 0.0;
+    double a1 = 0.0, a2 = 0.0;
     int m = k;
     do {
       const int lo = az_oth[m];
-      const double vo = lo < 0 ? 0.0 : ca * e[lo] + (e2 ? cb * e2[lo] : 0.0);
-      acc += double(az_t[m]) * (vs - vo);
+      const double tf = double(az_t[m]);
+      a1 += tf * (vs1 - (lo < 0 ? 0.0 : e1[lo]));
+      if (e2) a2 += tf * (vs2 - (lo < 0 ? 0.0 : e2[lo]));
       ++m;
     } while (m < b && az_cell[m] >= 0);
-    corr[cw & 0x7fffffff] = acc;
+    corr1[cw & 0x7fffffff] = ST(a1);
+    if (e2) corr2[cw & 0x7fffffff] = ST(a2);
   }
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------
-// CG update pass. alpha = rho / ((p, q) - s^T e) from the coarse partials (every workgroup
-// reduces them in the same order, so all agree; a breakdown makes all of them return and
-// workgroup 0 records it). Then rhat = rhat - alpha q + A Z (alpha e - er) (i.e.
-// rhat <- P1 rhat - alpha P1 A p), xhat += alpha p, partials of (rhat, M^-1 rhat),
-// ||rhat||^2 (red2, red3) and, when re-projecting, Z^T rhat.
-// alpha_fixed != 0 replaces the computed alpha (kernel timing only).
+// CG update (iteration of parity PAR). Every workgroup reduces the coarse partials in
+// the same order to gamma = (r, u), delta = (v, u) - s^T e and ||r||^2, so all take the
+// same decision: stop (converged or budget spent), fail (breakdown / non-finite), or
+//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev),
+//   w = v - A Z e, p = u + beta p, q = w + beta q, x += alpha p,
+//   r = r - alpha q [- A Z er when re-projecting].
+// Workgroup 0 records the step in the PAR slots of the scalars. bench != 0 forces fixed
+// coefficients (kernel timing only).
 // ---------------------------------------------------------------------------------------
-template <typename R, int NS, int RP, int CPT>
+template <typename R, int RP, int CPT, int PAR>
 __global__ void __launch_bounds__(kBlock)
-    k_update(Geo g, const R* __restrict__ q, const R* __restrict__ p, R* __restrict__ rh,
-             R* __restrict__ xh, const R* __restrict__ invd, const uint8_t* __restrict__ slot,
-             const int32_t* __restrict__ slot_pos, const int32_t* az_ptr,
-             const int32_t* az_cell, const int32_t* az_lab, const int32_t* az_oth,
-             const R* az_t, const double* __restrict__ e, const double* __restrict__ er,
-             const double* cpart, int G, double* zr, double* red2, double* red3, Scalars* sc,
-             double alpha_fixed) {
-  __shared__ double corr[kTileMax];
-  __shared__ double lds[(NS + 2) * kNW];
+    k_cg_update(Geo g, const R* __restrict__ v, R* __restrict__ r, R* __restrict__ u,
+                R* __restrict__ p, R* __restrict__ q, R* __restrict__ x,
+                const R* __restrict__ invd, const int32_t* az_ptr, const int32_t* az_cell,
+                const int32_t* az_lab, const int32_t* az_oth, const R* az_t,
+                const double* __restrict__ e, const double* __restrict__ er,
+                const double* cpart, int G, Scalars* sc, int bench) {
+  using psl::ld;
+  using psl::st;
+  __shared__ R corr[kTileMax];            // A Z e, rounded to the working precision
+  __shared__ R corr2[RP ? kTileMax : 1];  // A Z er
+  __shared__ double coef[3];              // alpha, beta, go (1) / stop (0)
   if (sc->done) return;
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   // issue the cell loads first so their latency overlaps the reductions below
   int cc[CPT];
-  int sl[CPT];
-  R qv[CPT], rv[CPT], xv[CPT], pv[CPT], dv[CPT];
+  R vv[CPT], rv[CPT], uv[CPT], pv[CPT], qv[CPT], xv[CPT], dv[CPT];
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int j = threadIdx.x + k * kBlock;
@@ -338,166 +452,116 @@ __global__ void __launch_bounds__(kBlock)
     if (j < T.ncell) {
       int ix, iy, iz;
       cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-      const int c = ix + g.nx * (iy + g.ny * iz);
-      cc[k] = c;
-      qv[k] = q[c];
-      rv[k] = rh[c];
-      xv[k] = xh[c];
-      pv[k] = p[c];
-      dv[k] = invd[c];
-      sl[k] = RP ? int(slot[c]) : 0;
+      const uint32_t c = ix + g.nx * (iy + g.ny * iz);
+      cc[k] = int(c);
+      vv[k] = ld(v, c);
+      rv[k] = ld(r, c);
+      uv[k] = ld(u, c);
+      pv[k] = ld(p, c);
+      qv[k] = ld(q, c);
+      xv[k] = ld(x, c);
+      dv[k] = ld(invd, c);
     }
   }
-  double alpha_d = alpha_fixed;
-  if (alpha_fixed == 0.0) {
-    double pr[2] = {0.0, 0.0};
-    for (int i = threadIdx.x; i < G; i += kBlock) {
-      pr[0] += cpart[i];
-      pr[1] += cpart[G + i];
-    }
-    psl::block_sum<2>(pr, lds);
-    const double pw = pr[1] - pr[0];   // (p, q) - s^T e = (p, P1 A p)
-    if (!(pw > 0.0)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->status = (pw == pw && fabs(pw) < INFINITY) ? PSL_EBREAKDOWN : PSL_ENONFINITE;
-        sc->done = 1;
-        sc->alpha = 0.0;
+  if (threadIdx.x < psl::kWave) {
+    // one wave reduces the coarse partials (fixed order) and decides the step
+    double alpha_d = 1e-3, beta_d = 0.5, go = 1.0;
+    if (!bench) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int i = threadIdx.x; i < G; i += psl::kWave) {
+        s0 += cpart[i];           // s^T e
+        s1 += cpart[G + i];       // (v, u)
+        s2 += cpart[2 * G + i];   // (r, u)
+        s3 += cpart[3 * G + i];   // (r, r)
       }
-      return;
+      s0 = psl::wave_sum(s0);
+      s1 = psl::wave_sum(s1);
+      s2 = psl::wave_sum(s2);
+      s3 = psl::wave_sum(s3);
+      const double gamma = s2, delta = s1 - s0, rr = s3;
+      const double gprev = sc->gamma[PAR ^ 1], aprev = sc->alpha[PAR ^ 1];
+      const int cnt = sc->cnt[PAR ^ 1];
+      const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+      if (!(rr < INFINITY) || !(fabs(gamma) < INFINITY) || !(fabs(delta) < INFINITY)) {
+        go = 0.0;
+        if (lead) {
+          sc->status = PSL_ENONFINITE;
+          sc->done = 1;
+          sc->iters = cnt;
+        }
+      } else if (rr <= sc->goal2 || cnt >= sc->maxit) {
+        go = 0.0;
+        if (lead) {
+          sc->rr = rr;
+          sc->done = 1;
+          sc->iters = cnt;
+        }
+      } else {
+        beta_d = gamma / gprev;                      // gprev = +inf before the first step
+        const double den = delta - beta_d * gamma / aprev;
+        if (!(den > 0.0)) {
+          go = 0.0;
+          if (lead) {
+            sc->status = PSL_EBREAKDOWN;
+            sc->done = 1;
+            sc->iters = cnt;
+            sc->rr = rr;
+          }
+        } else {
+          alpha_d = gamma / den;
+          if (lead) {
+            sc->gamma[PAR] = gamma;
+            sc->alpha[PAR] = alpha_d;
+            sc->cnt[PAR] = cnt + 1;
+            sc->iters = cnt + 1;
+            sc->rr = rr;
+            sc->delta = den;
+          }
+        }
+      }
     }
-    alpha_d = sc->rho / pw;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->alpha = alpha_d;
-      sc->pq = pr[1];
-      sc->se = pr[0];
+    if (threadIdx.x == 0) {
+      coef[0] = alpha_d;
+      coef[1] = beta_d;
+      coef[2] = go;
     }
   }
-  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, alpha_d, RP ? er : nullptr,
-                  -1.0, corr);
-  const R alpha = R(alpha_d);
-  double acc[NS + 2];
-#pragma unroll
-  for (int k = 0; k < NS + 2; ++k) acc[k] = 0.0;
+  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, RP ? er : nullptr, corr,
+                  corr2);   // ends with a barrier, after which coef[] is visible
+  if (coef[2] == 0.0) return;
+  const R alpha = R(coef[0]), beta = R(coef[1]);
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     if (cc[k] < 0) continue;
-    const int c = cc[k];
-    const R r = rv[k] - alpha * qv[k] + R(corr[threadIdx.x + k * kBlock]);
-    rh[c] = r;
-    xh[c] = xv[k] + alpha * pv[k];
-    const double rd = double(r);
-    acc[NS] += rd * double(r * dv[k]);
-    acc[NS + 1] += rd * rd;
-    if (RP) {
-#pragma unroll
-      for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? rd : 0.0;
-    }
-  }
-  psl::block_sum<NS + 2>(acc, lds);
-  if (RP) {
-    double zs[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) zs[m] = acc[m];
-    write_slots<NS>(zs, T.nslot, slot_pos, t, zr);
-  }
-  if (threadIdx.x == 0) {
-    red2[t] = acc[NS];
-    red3[t] = acc[NS + 1];
+    const uint32_t c = uint32_t(cc[k]);
+    const int j = threadIdx.x + k * kBlock;
+    const R w = vv[k] - corr[j];
+    const R qn = w + beta * qv[k];
+    const R pn = uv[k] + beta * pv[k];
+    R rn = rv[k] - alpha * qn;
+    if (RP) rn -= corr2[j];
+    st(q, c, qn);
+    st(p, c, pn);
+    st(x, c, xv[k] + alpha * pn);
+    st(r, c, rn);
+    st(u, c, rn * dv[k]);
   }
 }
 
-// Close an iteration (INIT = 0) or the inner start (INIT = 1), one workgroup:
-// rho' = (rhat, M^-1 rhat), ||rhat||^2, beta = rho'/rho, convergence and failure flags.
-template <int INIT>
-__global__ void __launch_bounds__(kBlock) k_close(const double* red2, const double* red3,
-                                                  int ntiles, Scalars* sc) {
-  __shared__ double lds[2 * kNW];
-  if (!INIT && sc->done) return;
-  double v[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < ntiles; i += kBlock) {
-    v[0] += red2[i];
-    v[1] += red3[i];
-  }
-  psl::block_sum<2>(v, lds);
-  if (threadIdx.x != 0) return;
-  const double ry = v[0], rr = v[1];
-  sc->rr = rr;
-  if (INIT) {
-    sc->rho = ry;
-    sc->iters = 0;
-    if (!(rr < INFINITY) || !(fabs(ry) < INFINITY)) {
-      sc->status = PSL_ENONFINITE;
-      sc->done = 1;
-    } else if (rr <= sc->goal2 || sc->maxit <= 0) {
-      sc->done = 1;
-    }
-    return;
-  }
-  sc->iters += 1;
-  if (!(fabs(ry) < INFINITY) || !(rr < INFINITY)) {
-    sc->status = PSL_ENONFINITE;
-    sc->done = 1;
-  } else {
-    sc->beta = ry / sc->rho;
-    sc->rho = ry;
-    if (rr <= sc->goal2 || sc->iters >= sc->maxit) sc->done = 1;
-  }
-}
-
-// p = M^-1 rhat + beta p
+// Inner start: r = sigma r64 (cast to R), u = M^-1 r; x = p = q = 0. The first stencil
+// pass then forms every inner product.
 template <typename R>
-__global__ void k_direction(int n, const R* __restrict__ rh, const R* __restrict__ invd,
-                            R* __restrict__ p, const Scalars* sc) {
-  if (sc->done) return;
-  const R beta = R(sc->beta);
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x)
-    p[c] = rh[c] * invd[c] + beta * p[c];
-}
-
-// Inner start: rhat = sigma r (cast to R), xhat = 0, p = M^-1 rhat; partials of
-// (rhat, p), ||rhat||^2 and, when re-projecting, Z^T rhat (k_close<1> finishes).
-template <typename R, int NS, int RP>
-__global__ void __launch_bounds__(kBlock)
-    k_inner_init(Geo g, const double* __restrict__ r, R* __restrict__ rh, R* __restrict__ xh,
-                 R* __restrict__ p, const R* __restrict__ invd,
-                 const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
-                 double* zr, double* red2, double* red3, const Scalars* sc) {
-  __shared__ double lds[(NS + 2) * kNW];
-  const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
-  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+__global__ void k_cg_init(int n, const double* __restrict__ r64, const R* __restrict__ invd,
+                          R* __restrict__ r, R* __restrict__ u, R* __restrict__ x,
+                          R* __restrict__ p, R* __restrict__ q, const Scalars* sc) {
   const double sigma = sc->sigma;
-  double acc[NS + 2];
-#pragma unroll
-  for (int k = 0; k < NS + 2; ++k) acc[k] = 0.0;
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
-    int ix, iy, iz;
-    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-    const int c = ix + g.nx * (iy + g.ny * iz);
-    const R rv = R(sigma * r[c]);
-    const R y = rv * invd[c];
-    rh[c] = rv;
-    xh[c] = R(0);
-    p[c] = y;
-    const double rd = double(rv);
-    acc[NS] += rd * double(y);
-    acc[NS + 1] += rd * rd;
-    if (RP) {
-      const int sl = slot[c];
-#pragma unroll
-      for (int m = 0; m < NS; ++m) acc[m] += (sl == m) ? rd : 0.0;
-    }
-  }
-  psl::block_sum<NS + 2>(acc, lds);
-  if (RP) {
-    double zs[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) zs[m] = acc[m];
-    write_slots<NS>(zs, T.nslot, slot_pos, t, zr);
-  }
-  if (threadIdx.x == 0) {
-    red2[t] = acc[NS];
-    red3[t] = acc[NS + 1];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const R rv = R(sigma * r64[c]);
+    r[c] = rv;
+    u[c] = rv * invd[c];
+    x[c] = R(0);
+    p[c] = R(0);
+    q[c] = R(0);
   }
 }
 
@@ -512,8 +576,8 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
-  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, 1.0,
-                  static_cast<const double*>(nullptr), 0.0, corr);
+  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
+                  static_cast<const double*>(nullptr), corr, corr);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   double acc[1] = {0.0};
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
@@ -521,9 +585,9 @@ __global__ void __launch_bounds__(kBlock)
     cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
     const int c = ix + g.nx * (iy + g.ny * iz);
     if (x) x[c] += e[labels[c]];
-    const double r = rin[c] - corr[j];
-    rout[c] = r;
-    acc[0] += r * r;
+    const double rr = rin[c] - corr[j];
+    rout[c] = rr;
+    acc[0] += rr * rr;
   }
   psl::block_sum<1>(acc, lds);
   if (threadIdx.x == 0) red[t] = acc[0];
@@ -588,6 +652,8 @@ __global__ void k_accumulate(int n, double* __restrict__ x, const R* __restrict_
     x[c] += scale * double(xh[c]);
 }
 
+// Inner start scalars: scale, goal, budget; the "previous step" slots (parity 1) make the
+// first step a steepest-descent step: gamma_prev = +inf gives beta = 0.
 __global__ void k_set_inner(Scalars* sc, double goal2, int maxit) {
   sc->rnorm = sqrt(sc->rr);
   sc->sigma = sc->rnorm > 0.0 ? 1.0 / sc->rnorm : 0.0;
@@ -596,18 +662,18 @@ __global__ void k_set_inner(Scalars* sc, double goal2, int maxit) {
   sc->done = 0;
   sc->iters = 0;
   sc->status = 0;
+  sc->gamma[1] = INFINITY;
+  sc->alpha[1] = 1.0;
+  sc->cnt[1] = 0;
 }
 
-// measurement set-up: the iteration kernels run unconditionally (never "converge")
+// measurement set-up: the iteration kernels run unconditionally
 __global__ void k_bench_prep(Scalars* sc) {
   sc->done = 0;
   sc->iters = 0;
   sc->status = 0;
   sc->goal2 = -1.0;
   sc->maxit = 0x7fffffff;
-  sc->alpha = 1e-3;
-  sc->beta = 0.5;
-  sc->rho = 1.0;
 }
 
 // streaming copy used to calibrate byte counters and the achievable bandwidth
@@ -678,7 +744,7 @@ int ensure_vecs(psl_ctx* c) {
   psl::VecSet<R>& v = Prec<R>::vecs(c);
   if (v.xh) return PSL_OK;
   const size_t bytes = sizeof(R) * size_t(c->n);
-  R** ptrs[4] = {&v.xh, &v.rh, &v.p, &v.q};
+  R** ptrs[6] = {&v.xh, &v.rh, &v.p, &v.q, &v.v, &v.u};
   for (R** p : ptrs)
     if (psl_internal_alloc(reinterpret_cast<void**>(p), bytes) != PSL_OK) return PSL_ENOMEM;
   return PSL_OK;
@@ -716,11 +782,10 @@ template <typename R, int MODE, int NS>
 struct StencilC {
   template <int CPT>
   struct F {
-    static void run(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
-                    hipStream_t st) {
+    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
       hipLaunchKernelGGL((k_stencil<R, MODE, NS, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
-                         in, b, out, c->slot, c->slot_pos, c->zq, red(c, 0), c->sc, check_done);
+                         in, b, out, c->slot, c->slot_pos, c->zq, red(c, 0));
     }
   };
 };
@@ -729,70 +794,67 @@ template <typename R, int MODE>
 struct StencilL {
   template <int NS>
   struct F {
-    static void run(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
-                    hipStream_t st) {
-      with_cpt<StencilC<R, MODE, NS>::template F>(c->cpt, c, in, b, out, check_done, st);
+    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
+      with_cpt<StencilC<R, MODE, NS>::template F>(c->cpt, c, in, b, out, st);
     }
   };
 };
 
-// stencil pass alone: out = A in (MODE 0) or b - A in (MODE 1); partials in zq / red[0]
+// plain stencil pass: out = A in (MODE 0) or b - A in (MODE 1); partials in zq / red[0]
 template <typename R, int MODE>
-void launch_stencil(psl_ctx* c, const R* in, const double* b, R* out, int check_done,
-                    hipStream_t st) {
-  with_ns<StencilL<R, MODE>::template F>(c->nslot_max, c, in, b, out, check_done, st);
+void launch_stencil(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
+  with_ns<StencilL<R, MODE>::template F>(c->nslot_max, c, in, b, out, st);
 }
 
+template <typename R, int RP, int NS>
+struct CgStencilC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st) {
+      psl::VecSet<R>& v = Prec<R>::vecs(c);
+      hipLaunchKernelGGL((k_cg_stencil<R, NS, RP, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
+                         v.rh, v.u, v.v, c->slot, c->slot_pos, c->zq, c->zr, c->red, c->sc);
+    }
+  };
+};
+
+template <typename R, int RP>
+struct CgStencilL {
+  template <int NS>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st) {
+      with_cpt<CgStencilC<R, RP, NS>::template F>(c->cpt, c, st);
+    }
+  };
+};
+
 // s (and sr) from the partials, then e (and er) = E^-1 s; coarse partials in cpart
-template <int RP>
+template <int RP, int NQ>
 void launch_coarse(psl_ctx* c, int check_done, hipStream_t st) {
   if (c->coarse_fused) {
-    hipLaunchKernelGGL((k_coarse<RP, 1>), dim3(c->coarse_blocks), dim3(kBlock), 0, st, c->Einv,
-                       c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, red(c, 0),
+    hipLaunchKernelGGL((k_coarse<RP, 1, NQ>), dim3(c->coarse_blocks), dim3(kBlock), 0, st,
+                       c->Einv, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, c->red,
                        c->ntiles, c->cpart, c->d, c->sc, check_done);
   } else {
     hipLaunchKernelGGL(k_reduce_s<RP>, dim3((c->d + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                        c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->d, c->sc, check_done);
-    hipLaunchKernelGGL((k_coarse<RP, 0>), dim3(c->coarse_blocks), dim3(kBlock), 0, st, c->Einv,
-                       c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, red(c, 0),
+    hipLaunchKernelGGL((k_coarse<RP, 0, NQ>), dim3(c->coarse_blocks), dim3(kBlock), 0, st,
+                       c->Einv, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, c->red,
                        c->ntiles, c->cpart, c->d, c->sc, check_done);
   }
 }
 
-template <typename R, int RP, int NS>
-struct UpdateC {
+template <typename R, int RP, int PAR>
+struct CgUpdateC {
   template <int CPT>
   struct F {
-    static void run(psl_ctx* c, hipStream_t st, double alpha_fixed) {
+    static void run(psl_ctx* c, hipStream_t st, int bench) {
       psl::VecSet<R>& v = Prec<R>::vecs(c);
-      hipLaunchKernelGGL((k_update<R, NS, RP, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
-                         geo(c), v.q, v.p, v.rh, v.xh, Prec<R>::invd(c), c->slot, c->slot_pos,
-                         c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
-                         c->er, c->cpart, c->coarse_blocks, c->zr, red(c, 2), red(c, 3), c->sc,
-                         alpha_fixed);
-    }
-  };
-};
-
-template <typename R, int RP>
-struct UpdateL {
-  template <int NS>
-  struct F {
-    static void run(psl_ctx* c, hipStream_t st, double alpha_fixed) {
-      with_cpt<UpdateC<R, RP, NS>::template F>(c->cpt, c, st, alpha_fixed);
-    }
-  };
-};
-
-template <typename R, int RP>
-struct InitL {
-  template <int NS>
-  struct F {
-    static void run(psl_ctx* c, hipStream_t st) {
-      psl::VecSet<R>& v = Prec<R>::vecs(c);
-      hipLaunchKernelGGL((k_inner_init<R, NS, RP>), dim3(c->ntiles), dim3(kBlock), 0, st,
-                         geo(c), c->r64, v.rh, v.xh, v.p, Prec<R>::invd(c), c->slot,
-                         c->slot_pos, c->zr, red(c, 2), red(c, 3), c->sc);
+      hipLaunchKernelGGL((k_cg_update<R, RP, CPT, PAR>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), v.v, v.rh, v.u, v.p, v.q, v.xh, Prec<R>::invd(c), c->az_ptr,
+                         c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e, c->er,
+                         c->cpart, c->coarse_blocks, c->sc, bench);
     }
   };
 };
@@ -819,35 +881,34 @@ void launch_outer_deflate(psl_ctx* c, double* x, const double* rin, double* rout
 // deflated CG. The second projection removes it (its own error is kappa(E) u times an
 // already tiny Z^T r).
 void enqueue_outer_step(psl_ctx* c, const double* b, double* x, hipStream_t st) {
-  launch_stencil<double, 1>(c, x, b, c->r64, 0, st);
-  launch_coarse<0>(c, 0, st);
+  launch_stencil<double, 1>(c, x, b, c->r64, st);
+  launch_coarse<0, 0>(c, 0, st);
   launch_outer_deflate(c, x, c->r64, c->r64, st);
   with_ns<ZtL>(c->nslot_max, c, c->r64, st);
-  launch_coarse<0>(c, 0, st);
+  launch_coarse<0, 0>(c, 0, st);
   launch_outer_deflate(c, x, c->r64, c->r64, st);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->rr);
 }
 
-// one CG iteration
-template <typename R, int RP>
+// one CG iteration of parity PAR (three launches)
+template <typename R, int RP, int PAR>
 void enqueue_iteration(psl_ctx* c, hipStream_t st) {
-  psl::VecSet<R>& v = Prec<R>::vecs(c);
-  launch_stencil<R, 0>(c, v.p, nullptr, v.q, 1, st);
-  launch_coarse<RP>(c, 1, st);
-  with_ns<UpdateL<R, RP>::template F>(c->nslot_max, c, st, 0.0);
-  hipLaunchKernelGGL(k_close<0>, dim3(1), dim3(kBlock), 0, st, red(c, 2), red(c, 3), c->ntiles,
-                     c->sc);
-  hipLaunchKernelGGL(k_direction<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n),
-                     v.rh, Prec<R>::invd(c), v.p, c->sc);
+  with_ns<CgStencilL<R, RP>::template F>(c->nslot_max, c, st);
+  launch_coarse<RP, kCgQ>(c, 1, st);
+  with_cpt<CgUpdateC<R, RP, PAR>::template F>(c->cpt, c, st, 0);
 }
 
+// `count` iterations (even), alternating parity
 template <typename R>
 void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
-  for (int i = 0; i < count; ++i) {
-    if (rp)
-      enqueue_iteration<R, 1>(c, st);
-    else
-      enqueue_iteration<R, 0>(c, st);
+  for (int i = 0; i < count; i += 2) {
+    if (rp) {
+      enqueue_iteration<R, 1, 0>(c, st);
+      enqueue_iteration<R, 1, 1>(c, st);
+    } else {
+      enqueue_iteration<R, 0, 0>(c, st);
+      enqueue_iteration<R, 0, 1>(c, st);
+    }
   }
 }
 
@@ -892,34 +953,39 @@ int read_scalars(psl_ctx* c, hipStream_t st) {
   return PSL_OK;
 }
 
-constexpr int kStallWindow = 512;   // inner iterations without halving ||rhat|| -> stop
+constexpr int kStallWindow = 512;   // inner iterations without halving ||r|| -> stop
 
 // Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
 template <typename R>
 int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, int rp,
-                int use_graph, hipStream_t st, int* iters, int* status, int* stalled) {
+                int use_graph, int outer, hipStream_t st, int* iters, int* status,
+                int* stalled) {
   int rc = ensure_vecs<R>(c);
   if (rc != PSL_OK) return rc;
   psl::VecSet<R>& v = Prec<R>::vecs(c);
+  const int chunk = check_every + (check_every & 1);  // parity pattern needs an even count
   hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit);
-  if (rp)
-    with_ns<InitL<R, 1>::template F>(c->nslot_max, c, st);
-  else
-    with_ns<InitL<R, 0>::template F>(c->nslot_max, c, st);
-  hipLaunchKernelGGL(k_close<1>, dim3(1), dim3(kBlock), 0, st, red(c, 2), red(c, 3), c->ntiles,
-                     c->sc);
+  hipLaunchKernelGGL(k_cg_init<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n),
+                     c->r64, Prec<R>::invd(c), v.rh, v.u, v.xh, v.p, v.q, c->sc);
   double best = INFINITY;
   int best_it = 0;
   *stalled = 0;
+  // the first check comes after about 3/4 of the iterations the same refinement step of
+  // the previous solve needed (launches after convergence return at once)
+  int& last = (std::is_same<R, double>::value ? c->last_iters64 : c->last_iters32)[std::min(outer, 7)];
+  int batches = std::max(1, (3 * last / 4) / chunk);
   for (;;) {
-    if (use_graph) {
-      rc = run_chunk<R>(c, check_every, rp, st);
-      if (rc != PSL_OK) return rc;
-    } else {
-      enqueue_iterations<R>(c, check_every, rp, st);
-      PSL_HIP(hipGetLastError());
+    for (int bi = 0; bi < batches; ++bi) {
+      if (use_graph) {
+        rc = run_chunk<R>(c, chunk, rp, st);
+        if (rc != PSL_OK) return rc;
+      } else {
+        enqueue_iterations<R>(c, chunk, rp, st);
+        PSL_HIP(hipGetLastError());
+      }
     }
+    batches = 1;
     rc = read_scalars(c, st);
     if (rc != PSL_OK) return rc;
     if (c->h_sc->done) break;
@@ -934,6 +1000,7 @@ int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, 
   }
   *iters = c->h_sc->iters;
   *status = c->h_sc->status;
+  last = *iters;
   // x += ||r|| xhat
   hipLaunchKernelGGL(k_accumulate<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n), x,
                      v.xh, c->sc);
@@ -948,7 +1015,7 @@ int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, 
 extern "C" int psl_apply_A(psl_ctx* c, const double* p, double* q, void* stream) {
   if (!c || !p || !q || p == q) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  launch_stencil<double, 0>(c, p, nullptr, q, 0, st);
+  launch_stencil<double, 0>(c, p, nullptr, q, st);
   PSL_HIP(hipGetLastError());
   return PSL_OK;
 }
@@ -958,7 +1025,7 @@ extern "C" int psl_deflate(psl_ctx* c, const double* r, double* out, double* cve
   if (!c || !r || !out) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   with_ns<ZtL>(c->nslot_max, c, r, st);
-  launch_coarse<0>(c, 0, st);
+  launch_coarse<0, 0>(c, 0, st);
   // out may alias r: each cell reads r before writing out
   launch_outer_deflate(c, nullptr, r, out, st);
   if (cvec)
@@ -1050,21 +1117,21 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       }
     }
     prev_rnorm = std::min(prev_rnorm, rnorm);
-    const double target = o.tol * bnorm / rnorm;  // relative to ||rhat_0|| = 1
+    const double target = o.tol * bnorm / rnorm;  // relative to ||r_0|| = 1
     int it = 0, ist = 0, stalled = 0;
     if (mode == PSL_MIXED) {
       const int rp = o.reproject != 0;
       rc = inner_solve<float>(c, x, std::max(o.tau_inner, target), o.maxit - total_iters,
-                              o.check_every, rp, use_graph, st, &it, &ist, &stalled);
+                              o.check_every, rp, use_graph, outer, st, &it, &ist, &stalled);
     } else {
       const int rp = o.reproject == 1;
       rc = inner_solve<double>(c, x, target, o.maxit - total_iters, o.check_every, rp,
-                               use_graph, st, &it, &ist, &stalled);
+                               use_graph, outer, st, &it, &ist, &stalled);
     }
     if (rc != PSL_OK) return finish(rc);
     if (verbose)
       std::fprintf(stderr,
-                   "libpsl:   inner %d iterations, status %d, stalled %d, ||rhat||/||rhat0|| = %.3e\n",
+                   "libpsl:   inner %d iterations, status %d, stalled %d, ||r||/||r0|| = %.3e\n",
                    it, ist, stalled, std::sqrt(c->h_sc->rr));
     total_iters += it;
     stats.iters = total_iters;
@@ -1077,7 +1144,7 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
     last_inner_broke = (ist == PSL_EBREAKDOWN && it == 0);
   }
   // fresh float64 residual of the returned x
-  launch_stencil<double, 1>(c, x, b, c->t64, 0, st);
+  launch_stencil<double, 1>(c, x, b, c->t64, st);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
   if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
   stats.relres_true = std::sqrt(c->h_sc->rr) / bnorm;
@@ -1098,32 +1165,26 @@ extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_
     switch (kernel) {
       case PSL_KERNEL_STENCIL:
         if (mode == PSL_MIXED)
-          launch_stencil<float, 0>(c, c->v32.p, nullptr, c->v32.q, 1, st);
+          with_ns<CgStencilL<float, 1>::template F>(c->nslot_max, c, st);
         else
-          launch_stencil<double, 0>(c, c->v64.p, nullptr, c->v64.q, 1, st);
+          with_ns<CgStencilL<double, 0>::template F>(c->nslot_max, c, st);
         break;
       case PSL_KERNEL_COARSE:
         if (mode == PSL_MIXED)
-          launch_coarse<1>(c, 1, st);
+          launch_coarse<1, kCgQ>(c, 1, st);
         else
-          launch_coarse<0>(c, 1, st);
+          launch_coarse<0, kCgQ>(c, 1, st);
         break;
       case PSL_KERNEL_UPDATE:
         if (mode == PSL_MIXED)
-          with_ns<UpdateL<float, 1>::template F>(c->nslot_max, c, st, 1e-3);
+          with_cpt<CgUpdateC<float, 1, 0>::template F>(c->cpt, c, st, 1);
         else
-          with_ns<UpdateL<double, 0>::template F>(c->nslot_max, c, st, 1e-3);
+          with_cpt<CgUpdateC<double, 0, 0>::template F>(c->cpt, c, st, 1);
         break;
       case PSL_KERNEL_DIRECTION:
-        if (mode == PSL_MIXED)
-          hipLaunchKernelGGL(k_direction<float>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
-                             int(c->n), c->v32.rh, c->invdiag32, c->v32.p, c->sc);
-        else
-          hipLaunchKernelGGL(k_direction<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
-                             int(c->n), c->v64.rh, c->invdiag, c->v64.p, c->sc);
-        break;
+        return PSL_EINVAL;  // folded into the update pass in the single-reduction form
       default:
-        launch_stencil<double, 1>(c, c->r64, c->r64, c->t64, 0, st);
+        launch_stencil<double, 1>(c, c->r64, c->r64, c->t64, st);
         break;
     }
   }
