@@ -39,18 +39,54 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int) -> float:
-    """Bytes one launch must move at minimum (each array touched once), w = word size."""
+def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool) -> float:
+    """Bytes one launch must move at minimum (each array touched once), w = word size.
+
+    two=True: the two-reduction loop (float32 path); False: the single-reduction loop.
+    """
     nx, ny, nz = grid
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
-    if kernel == "stencil":          # read r, u = M^-1 r, Tx, Ty, Tz, slot; write v = A u
-        return 2 * w * n + w * faces + 1 * n + w * n
-    if kernel == "update":           # read v, r, u, p, q, x, 1/diag; write q, p, x, r, u;
-        return 12 * w * n + m_faces * (12 + w)   # + the cut faces of A Z (cell, labels, T)
-    if kernel == "coarse":           # read E^-1 (float64), s, sr; write e, er
+    if kernel == "stencil":
+        if two:   # read u, p_prev, Tx, Ty, Tz, slot; write p, q = A p
+            return 4 * w * n + w * faces + 1 * n
+        return 2 * w * n + w * faces + 1 * n + w * n   # read r, u, T, slot; write v = A u
+    if kernel == "update":
+        if two:   # read q, r, p, x, 1/diag; write r, x, u; + the cut faces of A Z
+            return 8 * w * n + m_faces * (12 + w)
+        return 12 * w * n + m_faces * (12 + w)   # read v, r, u, p, q, x, 1/diag; write 5
+    if kernel == "coarse":           # read E^-1 (float64), s; write e
         return 8.0 * d * d + 4 * 8 * d
     raise KeyError(kernel)
+
+
+def counter_traffic(kernel: str, workload: str, mode: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary
+    (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration), or None when no
+    summary covers this kernel, workload and mode or the kernel source changed since."""
+    import glob
+    import hashlib
+    src_path = os.path.join(ROOT, "paper_1510_02148_amd", "csrc", "psl_solve.hip")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.md"))):
+        fields = {}
+        for line in open(path):
+            k, sep, v = line.strip().partition(": ")
+            if sep:
+                fields[k] = v.strip()
+        if (fields.get("bench_kernel"), fields.get("workload"), fields.get("mode")) != \
+                (kernel, workload, mode):
+            continue
+        src = open(src_path).read()
+        i = src.find(fields.get("source_marker", "\0"))
+        if i < 0:
+            return None
+        body = src[i - 4:src.index("\n}\n", i)]
+        if hashlib.sha256(body.encode()).hexdigest() != fields.get("kernel_source_sha256"):
+            return None
+        kib = 1024.0
+        return (float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_factor"]) +
+                float(fields["write_kib_per_dispatch"]) * float(fields["write_factor"])) * kib
+    return None
 
 
 def make_problem(name: str, seed: int):
@@ -159,7 +195,7 @@ def main():
         e1.record(stream)
         e1.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
-        nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w)
+        nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w, mode == psl.MIXED)
         kernels[name] = {"us": round(us, 3), "alg_bytes": int(nbytes),
                          "gbs": round(nbytes / (us * 1e-6) / 1e9, 1)}
     # plain copy of 1 GiB for the achievable-bandwidth reference
@@ -178,8 +214,12 @@ def main():
     del src, dst
     dominant = max(kernels, key=lambda k: kernels[k]["us"])
     kd = kernels[dominant]
+    traffic = counter_traffic(dominant, args.workload, args.mode)
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": (round(traffic) if traffic is not None else None),
+                "traffic_over_algorithmic": (round(traffic / kd["alg_bytes"], 3)
+                                             if traffic is not None else None),
                 "copy_kernel_gbs": round(copy_gbs, 1)}
     spmv_gbs = kernels["stencil"]["gbs"]
 

@@ -78,13 +78,18 @@ typedef struct {
   int32_t mode;         /* PSL_FP64 or PSL_MIXED */
   int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
   int32_t max_outer;    /* cap on refinement steps (default 30) */
-  double  tau_inner;    /* PSL_MIXED: residual reduction asked of each float32 inner solve
-                           (default 1e-4); PSL_FP64 ignores it */
+  double  tau_inner;    /* PSL_MIXED: reduction of the float32 CG residual after which it
+                           is replaced by the float64 residual (default 0.1); PSL_FP64
+                           ignores it */
   int32_t check_every;  /* CG iterations enqueued between host convergence checks
                            (default 16; iterations after convergence are skipped on device) */
-  int32_t reproject;    /* re-apply P1 to the CG residual every iteration, fused into the
-                           update pass (keeps Z^T rhat = 0 under rounding): 1 on, 0 off,
-                           -1 (default) on for float32 CG and off for float64 CG */
+  int32_t reproject;    /* PSL_FP64: re-apply P1 to the CG residual every iteration, fused
+                           into the update pass (keeps Z^T rhat = 0 under rounding): 1 on,
+                           0 or -1 (default) off. PSL_MIXED ignores it (its residual is
+                           replaced by the projected float64 residual instead) */
+  double  mixed_floor;  /* PSL_MIXED: once ||b - A x|| <= mixed_floor ||b||, float64 CG
+                           continues along the float32 search direction (default 1e-4;
+                           0 keeps float32 until it stalls) */
 } psl_solve_opts;
 
 typedef struct {
@@ -165,8 +170,14 @@ int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double
  * preconditioned CG on the deflated system P1 A xhat = P1 b (eqs. "deflops", "defsys";
  * E built from A itself, Remark 3.1) and the projection back x = Z E^-1 Z^T b + P2 xhat
  * (eq. "projectback"), inside a float64 refinement loop: r = b - A x;
- * x += Z E^-1 Z^T r; r = P1 r; stop if ||r|| <= tol ||b||; else CG on the scaled r
- * (float32 in PSL_MIXED, float64 in PSL_FP64) and x += ||r|| xhat.
+ * x += Z E^-1 Z^T r; r = P1 r; stop if ||r|| <= tol ||b||; else CG on the scaled r and
+ * x += ||r|| xhat.
+ * PSL_FP64: float64 CG (single-reduction recurrences) straight to the tolerance.
+ * PSL_MIXED: float32 CG (two-reduction loop) whose recursive residual is replaced by the
+ * projected float64 residual each time it has dropped by tau_inner, keeping the search
+ * direction; below mixed_floor, or once the float64 residual stops following the float32
+ * one (float32's attainable accuracy), float64 CG takes over (stats.fell_back = 1), along
+ * the float32 direction when the last float32 run ended normally.
  *   ctx   context from psl_setup_E.
  *   b     dev[n] float64 right-hand side (not modified).
  *   x     dev[n] float64: start vector on entry if o->use_x0, solution on exit.
@@ -175,7 +186,7 @@ int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double
  * An inner CG that stops improving (rounding floor: (p, P1 A p) <= 0, or no halving of
  * ||rhat|| over 512 iterations) returns to the refinement loop, which restarts it from
  * the new float64 residual; in PSL_MIXED a refinement step that does not halve the
- * float64 residual switches the remaining steps to float64 CG (stats.fell_back = 1).
+ * float64 residual also switches the remaining steps to float64 CG.
  * Returns PSL_OK when ||b - A x|| <= tol ||b|| was reached; otherwise PSL_EMAXIT
  * (iteration or refinement cap; x is the projected last iterate), PSL_ESTAGNATION
  * (float64 refinement stopped reducing the residual), PSL_EBREAKDOWN (breakdown on the

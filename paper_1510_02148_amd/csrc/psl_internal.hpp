@@ -28,8 +28,8 @@ struct Tile {
 // carried from one CG iteration to the next are double-buffered by iteration parity, so a
 // kernel reads slot (i+1)&1 while its workgroup 0 writes slot i&1.
 struct Scalars {
-  double gamma[2];   // (r, M^-1 r)
-  double alpha[2];   // step length
+  double gamma[2];   // (r, M^-1 r); in the two-reduction form rho = (r, M^-1 r)
+  double alpha[2];   // step length (single-reduction form)
   double rr;         // ||r||^2 at the last check
   double goal2;      // inner stop: ||r||^2 <= goal2
   double rnorm;      // float64 refinement residual norm
@@ -41,6 +41,7 @@ struct Scalars {
   int32_t iters;     // inner iterations done in this inner solve
   int32_t status;    // PSL_OK or failure code raised on device
   int32_t maxit;     // iteration budget for this inner solve
+  int32_t stop_par;  // parity of the launch that ended the last two-reduction inner solve
 };
 
 template <typename R>
@@ -51,6 +52,14 @@ struct VecSet {       // inner CG vectors in precision R
   R* q = nullptr;       // P1 A p, by recurrence
   R* v = nullptr;       // A M^-1 r
   R* u = nullptr;       // M^-1 r
+  R* p2 = nullptr;      // second search-direction buffer (two-reduction form)
+};
+
+constexpr int kGraphSlots = 4;      // captured iteration chunks kept per precision
+
+struct GraphSlot {
+  int key = -1;                      // chunk, CG form and re-projection it was captured for
+  hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace psl
@@ -98,6 +107,8 @@ struct psl_ctx {
   double* zr = nullptr;               // [npart] label-major partials of Z^T rhat
   double* red = nullptr;              // [4*ntiles] per-tile scalar partials, quantity-major
   double* cpart = nullptr;            // [4*coarse_blocks] s^T e and slices of the CG partials
+  double* upart = nullptr;            // [2*upd_blocks] (r, M^-1 r), (r, r) per update workgroup
+  int upd_blocks = 1;                 // workgroups of the two-reduction update pass
   double* s = nullptr;                // [d]
   double* e = nullptr;                // [d]
   double* sr = nullptr;               // [d] Z^T rhat
@@ -108,10 +119,13 @@ struct psl_ctx {
   psl::Scalars* h_sc = nullptr;       // pinned host mirror
   psl::VecSet<double> v64;
   psl::VecSet<float> v32;
-  // captured iteration chunks, one per precision
-  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-  hipStream_t graph_stream64 = nullptr, graph_stream32 = nullptr;
-  int graph_chunk64 = 0, graph_chunk32 = 0;
+  // captured iteration chunks per precision
+  psl::GraphSlot graphs64[psl::kGraphSlots], graphs32[psl::kGraphSlots];
+  // device memory arena: every buffer of the context is carved from a few large blocks,
+  // released together by psl_destroy
+  std::vector<void*> blocks;
+  char* arena = nullptr;
+  size_t arena_left = 0;
   int last_iters64[8] = {0}, last_iters32[8] = {0};  // inner iterations per refinement step
 };
 
@@ -183,5 +197,16 @@ __device__ inline int div_small(int j, int d, float inv) {
 
 }  // namespace psl
 
-// host-side helpers implemented in psl_setup.hip
+// host-side helpers implemented in psl_setup.hip: device memory from the stream-ordered
+// pool, ordered on psl_alloc_stream (set by each entry point to the caller's stream)
+extern thread_local hipStream_t psl_alloc_stream;
 int psl_internal_alloc(void** p, size_t bytes);
+void psl_internal_free(void* p);
+// bytes from the context's arena (256-byte aligned); a new block when the current one is
+// exhausted (at least `reserve` bytes)
+int psl_ctx_alloc(psl_ctx* c, void** p, size_t bytes, size_t reserve = size_t(32) << 20);
+// pinned host blocks (<= 1024 bytes), recycled across contexts
+void* psl_internal_pinned_get(size_t bytes);
+void psl_internal_pinned_put(void* p);
+// per-device non-blocking stream used only to capture graphs (created once, kept)
+hipStream_t psl_internal_capture_stream();

@@ -2,6 +2,8 @@
 // the interface rows of A Z, E = Z^T A Z and its float64 Cholesky factor and inverse.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -40,20 +42,97 @@ extern "C" void psl_default_opts(psl_solve_opts* o) {
   o->mode = PSL_FP64;
   o->use_x0 = 0;
   o->max_outer = 30;
-  o->tau_inner = 1e-4;
+  o->tau_inner = 0.1;
   o->check_every = 16;
   o->reproject = -1;
+  o->mixed_floor = 1e-4;
+}
+
+// Device memory comes from the device's stream-ordered pool, which keeps freed blocks
+// (release threshold raised once per device), so building and destroying contexts
+// repeatedly does not go back to the driver. Blocks are ordered on the stream of the
+// entry point that asks for them; psl_destroy waits for the device before freeing.
+thread_local hipStream_t psl_alloc_stream = nullptr;
+
+static void keep_pool_memory() {
+  static bool done[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done[dev] = true;
 }
 
 int psl_internal_alloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 256;
-  if (hipMalloc(p, bytes) != hipSuccess) {
+  keep_pool_memory();
+  if (hipMallocAsync(p, bytes, psl_alloc_stream) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
     return PSL_ENOMEM;
   }
   return PSL_OK;
+}
+
+void psl_internal_free(void* p) {
+  if (p) (void)hipFreeAsync(p, psl_alloc_stream);
+}
+
+hipStream_t psl_internal_capture_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+int psl_ctx_alloc(psl_ctx* c, void** p, size_t bytes, size_t reserve) {
+  *p = nullptr;
+  bytes = (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+  if (bytes > c->arena_left) {
+    void* blk = nullptr;
+    const size_t sz = std::max(bytes, reserve);
+    if (psl_internal_alloc(&blk, sz) != PSL_OK) return PSL_ENOMEM;
+    c->blocks.push_back(blk);
+    c->arena = static_cast<char*>(blk);
+    c->arena_left = sz;
+  }
+  *p = c->arena;
+  c->arena += bytes;
+  c->arena_left -= bytes;
+  return PSL_OK;
+}
+
+// Pinned host mirrors of the solve scalars are recycled process-wide: pinning and
+// unpinning host memory costs milliseconds, a context's whole set-up a few.
+static std::mutex g_pinned_mu;
+static std::vector<void*> g_pinned_free;
+
+void* psl_internal_pinned_get(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      void* p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes < 1024 ? 1024 : bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void psl_internal_pinned_put(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free.push_back(p);
 }
 
 static bool grid_ok(const psl_grid* g) {
@@ -203,6 +282,7 @@ __global__ void __launch_bounds__(1024) k_scan_small(const int32_t* in, int32_t*
 extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
                            const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
                            int32_t* labels, int32_t* d, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (!grid_ok(g) || !nsub || !labels || !d) return PSL_EINVAL;
   if (!cls && !K) return PSL_EINVAL;
   const int nx = g->nx, ny = g->ny, nz = g->nz;
@@ -233,9 +313,9 @@ extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsu
   if (rc == PSL_OK) rc = psl_internal_alloc((void**)&rank, sizeof(int32_t) * (nkeys + 1));
   if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bad, sizeof(int32_t));
   if (rc != PSL_OK) {
-    (void)hipFree(present);
-    (void)hipFree(rank);
-    (void)hipFree(bad);
+    psl_internal_free(present);
+    psl_internal_free(rank);
+    psl_internal_free(bad);
     return rc;
   }
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nkeys)), dim3(kBlock), 0, st, present, 0,
@@ -250,9 +330,9 @@ extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsu
   hipError_t e1 = hipMemcpyAsync(&h[0], rank + nkeys, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipMemcpyAsync(&h[1], bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   hipError_t e3 = hipStreamSynchronize(st);
-  (void)hipFree(present);
-  (void)hipFree(rank);
-  (void)hipFree(bad);
+  psl_internal_free(present);
+  psl_internal_free(rank);
+  psl_internal_free(bad);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return PSL_EHIP;
   if (h[1]) return PSL_EINVAL;  // a manual class outside [0, ncls)
   *d = h[0];
@@ -819,20 +899,13 @@ extern "C" void psl_destroy(psl_ctx* c) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(c->dev);
   (void)hipDeviceSynchronize();
-  if (c->graph64) (void)hipGraphExecDestroy(c->graph64);
-  if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
-  if (c->graph_stream64) (void)hipStreamDestroy(c->graph_stream64);
-  if (c->graph_stream32) (void)hipStreamDestroy(c->graph_stream32);
-  void* ptrs[] = {c->Tx, c->Ty, c->Tz, c->Tx32, c->Ty32, c->Tz32, c->invdiag, c->invdiag32,
-                  c->labels, c->tiles, c->slot, c->tile_lab, c->lab_ptr, c->lab_part,
-                  c->az_ptr, c->az_cell, c->az_lab, c->az_oth, c->az_t, c->az_t32, c->E, c->Einv,
-                  c->zq, c->zr, c->red, c->s, c->e, c->sr, c->er, c->cpart, c->slot_pos,
-                  c->r64, c->t64, c->sc,
-                  c->v64.xh, c->v64.rh, c->v64.p, c->v64.q, c->v64.v, c->v64.u, c->v32.xh,
-                  c->v32.rh, c->v32.p, c->v32.q, c->v32.v, c->v32.u};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (c->h_sc) (void)hipHostFree(c->h_sc);
+  psl_alloc_stream = nullptr;   // the caller's stream may be gone; the device is idle
+  for (int i = 0; i < psl::kGraphSlots; ++i) {
+    if (c->graphs64[i].exec) (void)hipGraphExecDestroy(c->graphs64[i].exec);
+    if (c->graphs32[i].exec) (void)hipGraphExecDestroy(c->graphs32[i].exec);
+  }
+  for (void* blk : c->blocks) psl_internal_free(blk);
+  psl_internal_pinned_put(c->h_sc);
   (void)hipSetDevice(cur);
   delete c;
 }
@@ -857,13 +930,14 @@ extern "C" void psl_destroy(psl_ctx* c) {
   } while (0)
 
 template <typename T>
-static int dalloc(T** p, int64_t count) {
-  return psl_internal_alloc(reinterpret_cast<void**>(p), sizeof(T) * size_t(count));
+static int dalloc(psl_ctx* c, T** p, int64_t count) {
+  return psl_ctx_alloc(c, reinterpret_cast<void**>(p), sizeof(T) * size_t(count));
 }
 
 extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
                            const double* Ty, const double* Tz, const int32_t* labels,
                            int32_t d, const int32_t nsub[3], void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (!out) return PSL_EINVAL;
   *out = nullptr;
   if (!grid_ok(g) || !Tx || !Ty || !Tz || !labels || d < 1) return PSL_EINVAL;
@@ -896,20 +970,29 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
                 nfz = int64_t(nx) * ny * (nz + 1);
   GridDev gd{nx, ny, nz};
 
-  PSL_TRY(dalloc(&c->Tx, nfx));
-  PSL_TRY(dalloc(&c->Ty, nfy));
-  PSL_TRY(dalloc(&c->Tz, nfz));
-  PSL_TRY(dalloc(&c->Tx32, nfx));
-  PSL_TRY(dalloc(&c->Ty32, nfy));
-  PSL_TRY(dalloc(&c->Tz32, nfz));
-  PSL_TRY(dalloc(&c->invdiag, n));
-  PSL_TRY(dalloc(&c->invdiag32, n));
-  PSL_TRY(dalloc(&c->labels, n));
-  PSL_TRY(dalloc(&c->slot, n));
+  // one block for what the context and both solve precisions need (further blocks only
+  // if the tiling or the cut faces outgrow the estimate)
+  {
+    const size_t nn = size_t(n), nf = size_t(nfx + nfy + nfz);
+    const size_t est = nf * 12 + nn * (8 + 4 + 4 + 1 + 16) + nn * (7 * 8 + 7 * 4) +
+                       size_t(d) * d * 8 * 3 + nn * 3 * 28 / 4 + (size_t(16) << 20);
+    void* first = nullptr;
+    PSL_TRY(psl_ctx_alloc(c, &first, 256, est));
+  }
+  PSL_TRY(dalloc(c, &c->Tx, nfx));
+  PSL_TRY(dalloc(c, &c->Ty, nfy));
+  PSL_TRY(dalloc(c, &c->Tz, nfz));
+  PSL_TRY(dalloc(c, &c->Tx32, nfx));
+  PSL_TRY(dalloc(c, &c->Ty32, nfy));
+  PSL_TRY(dalloc(c, &c->Tz32, nfz));
+  PSL_TRY(dalloc(c, &c->invdiag, n));
+  PSL_TRY(dalloc(c, &c->invdiag32, n));
+  PSL_TRY(dalloc(c, &c->labels, n));
+  PSL_TRY(dalloc(c, &c->slot, n));
   int32_t* flags = nullptr;  // 0 diag, 1 tile overflow, 2 empty column, 3 label range, 4 E pivot
-  PSL_TRY(dalloc(&flags, 8));
+  PSL_TRY(dalloc(c, &flags, 8));
   auto free_flags = [&]() {
-    if (flags) (void)hipFree(flags);
+    
     flags = nullptr;
   };
   int32_t hflags[8] = {0};
@@ -954,11 +1037,11 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   for (;;) {
     c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
     c->ntiles = int(c->h_tiles.size());
-    if (c->tiles) (void)hipFree(c->tiles);
-    if (c->tile_lab) (void)hipFree(c->tile_lab);
+    
+    
     c->tiles = nullptr;
     c->tile_lab = nullptr;
-    if (dalloc(&c->tiles, c->ntiles) || dalloc(&c->tile_lab, int64_t(c->ntiles) * kMaxSlots))
+    if (dalloc(c, &c->tiles, c->ntiles) || dalloc(c, &c->tile_lab, int64_t(c->ntiles) * kMaxSlots))
       PSL_FAIL(PSL_ENOMEM);
     if (hipMemcpyAsync(c->tiles, c->h_tiles.data(), sizeof(Tile) * c->ntiles,
                        hipMemcpyHostToDevice, st))
@@ -988,7 +1071,7 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   // label -> partial lists
   const int nparts = c->ntiles * kMaxSlots;
   int32_t* cnt = nullptr;
-  if (dalloc(&cnt, d + 1) || dalloc(&c->lab_ptr, d + 1) || dalloc(&c->lab_part, nparts))
+  if (dalloc(c, &cnt, d + 1) || dalloc(c, &c->lab_ptr, d + 1) || dalloc(c, &c->lab_part, nparts))
     PSL_FAIL(PSL_ENOMEM);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(d + 1)), dim3(kBlock), 0, st, cnt, 0,
                      int64_t(d + 1));
@@ -1001,8 +1084,8 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
                      nparts, c->lab_ptr, cnt, c->lab_part, d);
   hipLaunchKernelGGL(k_lab_sort, dim3(nblocks(d)), dim3(kBlock), 0, st, c->lab_ptr,
                      c->lab_part, d, flags + 2);
-  if (dalloc(&c->slot_pos, nparts)) {
-    (void)hipFree(cnt);
+  if (dalloc(c, &c->slot_pos, nparts)) {
+    
     PSL_FAIL(PSL_ENOMEM);
   }
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->slot_pos, 0,
@@ -1012,8 +1095,8 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
 
   // interface rows of A Z
   int32_t* tile_cnt = nullptr;
-  if (dalloc(&tile_cnt, c->ntiles + 1) || dalloc(&c->az_ptr, c->ntiles + 1)) {
-    (void)hipFree(cnt);
+  if (dalloc(c, &tile_cnt, c->ntiles + 1) || dalloc(c, &c->az_ptr, c->ntiles + 1)) {
+    
     PSL_FAIL(PSL_ENOMEM);
   }
   hipLaunchKernelGGL(k_az_count, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
@@ -1023,15 +1106,15 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   if (hipMemcpyAsync(&m, c->az_ptr + c->ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
       hipMemcpyAsync(&c->npart, c->lab_ptr + d, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
       hipStreamSynchronize(st)) {
-    (void)hipFree(cnt);
-    (void)hipFree(tile_cnt);
+    
+    
     PSL_FAIL(PSL_EHIP);
   }
-  (void)hipFree(cnt);
-  (void)hipFree(tile_cnt);
+  
+  
   c->m_az = m;
-  if (dalloc(&c->az_cell, m) || dalloc(&c->az_lab, m) || dalloc(&c->az_oth, m) ||
-      dalloc(&c->az_t, m) || dalloc(&c->az_t32, m))
+  if (dalloc(c, &c->az_cell, m) || dalloc(c, &c->az_lab, m) || dalloc(c, &c->az_oth, m) ||
+      dalloc(c, &c->az_t, m) || dalloc(c, &c->az_t32, m))
     PSL_FAIL(PSL_ENOMEM);
   hipLaunchKernelGGL(k_az_fill, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
                      c->Ty, c->Tz, c->labels, c->az_ptr, c->az_cell, c->az_lab, c->az_oth,
@@ -1040,19 +1123,19 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   // E = Z^T A Z, then Cholesky and inverse
   const int64_t dd = int64_t(d) * d;
   double* Lw = nullptr;
-  if (dalloc(&c->E, dd) || dalloc(&c->Einv, dd) || dalloc(&Lw, dd)) {
-    (void)hipFree(Lw);
+  if (dalloc(c, &c->E, dd) || dalloc(c, &c->Einv, dd) || dalloc(c, &Lw, dd)) {
+    
     PSL_FAIL(PSL_ENOMEM);
   }
   hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, c->lab_ptr, c->lab_part, c->az_ptr,
                      c->az_lab, c->az_oth, c->az_t, c->E, d);
   if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st)) {
-    (void)hipFree(Lw);
+    
     PSL_FAIL(PSL_EHIP);
   }
   int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, st);
   if (rc == PSL_OK) rc = read_flags();
-  (void)hipFree(Lw);
+  
   if (rc != PSL_OK) PSL_FAIL(rc);
   if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range
   if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
@@ -1062,13 +1145,14 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   // coarse workgroups stage all of s (d <= 4096 doubles of LDS) and each re-sums the
   // label partials; beyond ~4M partial reads a separate reduction kernel is cheaper
   c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
-  if (dalloc(&c->zq, std::max(1, c->npart)) || dalloc(&c->zr, std::max(1, c->npart)) ||
-      dalloc(&c->red, int64_t(c->ntiles) * 4) || dalloc(&c->s, d) || dalloc(&c->e, d) ||
-      dalloc(&c->sr, d) || dalloc(&c->er, d) || dalloc(&c->cpart, 4 * c->coarse_blocks) ||
-      dalloc(&c->r64, n) || dalloc(&c->t64, n) || dalloc(&c->sc, 1))
+  if (dalloc(c, &c->zq, std::max(1, c->npart)) || dalloc(c, &c->zr, std::max(1, c->npart)) ||
+      dalloc(c, &c->red, int64_t(c->ntiles) * 4) || dalloc(c, &c->s, d) || dalloc(c, &c->e, d) ||
+      dalloc(c, &c->sr, d) || dalloc(c, &c->er, d) || dalloc(c, &c->cpart, 4 * c->coarse_blocks) ||
+      dalloc(c, &c->r64, n) || dalloc(c, &c->t64, n) || dalloc(c, &c->sc, 1))
     PSL_FAIL(PSL_ENOMEM);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_sc), sizeof(psl::Scalars)) != hipSuccess)
-    PSL_FAIL(PSL_ENOMEM);
+  static_assert(sizeof(psl::Scalars) <= 1024, "pinned mirror slot size");
+  c->h_sc = static_cast<psl::Scalars*>(psl_internal_pinned_get(sizeof(psl::Scalars)));
+  if (!c->h_sc) PSL_FAIL(PSL_ENOMEM);
   std::memset(c->h_sc, 0, sizeof(psl::Scalars));
   if (hipMemcpyAsync(c->sc, c->h_sc, sizeof(psl::Scalars), hipMemcpyHostToDevice, st) ||
       hipStreamSynchronize(st))

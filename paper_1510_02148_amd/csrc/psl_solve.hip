@@ -1,7 +1,7 @@
 // libpsl solve path: deflated Jacobi-PCG (DEF1 form) on P1 A xhat = P1 b inside a float64
 // refinement loop, plus the stand-alone operator entry points (A p, P1 r).
 //
-// The CG runs in its single-reduction form (the recurrences of Chronopoulos and Gear):
+// Float64 CG runs in its single-reduction form (the recurrences of Chronopoulos and Gear):
 // with u = M^-1 r, v = A u, w = P1 v = v - A Z E^-1 Z^T v,
 //   gamma = (r, u), delta = (w, u) = (v, u) - s^T e  (s = Z^T v, e = E^-1 s),
 //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev),
@@ -16,6 +16,8 @@
 //   update    alpha, beta from the coarse partials (every workgroup in the same fixed
 //             order), convergence / failure test, then the vector updates with
 //             A Z e (and A Z er: r <- P1 r - alpha q when re-projecting)
+// Float32 CG runs the two-reduction loop (sd_* kernels below) with its residual replaced
+// by the projected float64 residual at each refinement step and its direction kept.
 // A Z v is evaluated only on cells with a cut face, in flux form sum T (v_l(i) - v_l(j)).
 // Partial sums cross workgroups only through kernel boundaries (no in-kernel fences), and
 // every reduction is a fixed-order tree: reruns with the same tiling are bit-identical.
@@ -548,6 +550,309 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Two-reduction form: the standard DEF1 PCG loop, used with float64 residual replacement
+// (the recursive residual is replaced by the projected float64 residual every time it
+// has dropped by a set factor, while the search direction is kept). Its step length is
+// an inner product of the current vectors, so a replaced residual does not disturb it;
+// the single-reduction step length leans on orthogonality to the previous residual,
+// which a replacement breaks. Three launches per iteration:
+//   sd_stencil  rho = (r, M^-1 r) and ||r||^2 from the update partials (every workgroup,
+//               same fixed order), convergence test, beta = rho / rho_prev,
+//               p = u + beta p_prev (parity double-buffered; halo values recomputed from
+//               u and p_prev), q = A p; per tile Z^T q, (p, q)
+//   coarse      s = Z^T q, e = E^-1 s; slices of s^T e and (p, q)
+//   sd_update   alpha = rho / ((p, q) - s^T e), w = q - A Z e, x += alpha p,
+//               r -= alpha w, u = M^-1 r; per-workgroup (r, u), (r, r) over a capped grid
+//               so that the next stencil pass reduces few partials
+// ---------------------------------------------------------------------------------------
+template <typename R>
+__device__ inline R axpy(R a, R x, R y) {   // a x + y, contracted the same way everywhere
+  return fma(a, x, y);
+}
+
+template <typename R, int NS, int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_sd_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
+                 const R* __restrict__ Tz, const R* __restrict__ u,
+                 const R* __restrict__ pprev, R* __restrict__ p, R* __restrict__ q,
+                 const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
+                 double* zq, double* red, const double* upart, int GU, Scalars* sc,
+                 int bench) {
+  using psl::ld;
+  using psl::st;
+  __shared__ double lds[(NS + 1) * kNW];
+  __shared__ double lds2[2 * kNW];
+  if (sc->done) return;
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = g.tiles[t];
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int sxy = nx * ny;
+  int cc[CPT];
+  int sl[CPT];
+  R uc[CPT], uw[CPT], ue[CPT], us[CPT], un[CPT], ub[CPT], ut[CPT];
+  R pc[CPT], pw[CPT], pe[CPT], ps[CPT], pn[CPT], pb[CPT], pt[CPT];
+  R t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    cc[k] = -1;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const uint32_t c = ix + nx * (iy + ny * iz);
+      const uint32_t fx = c + (iy + ny * iz);
+      const uint32_t fy = c + nx * iz;
+      cc[k] = int(c);
+      uc[k] = ld(u, c);
+      pc[k] = ld(pprev, c);
+      const bool hw = ix > 0, he = ix < nx - 1, hs = iy > 0, hn = iy < ny - 1, hb = iz > 0,
+                 ht = iz < nz - 1;
+      uw[k] = hw ? ld(u, c - 1) : R(0);
+      pw[k] = hw ? ld(pprev, c - 1) : R(0);
+      ue[k] = he ? ld(u, c + 1) : R(0);
+      pe[k] = he ? ld(pprev, c + 1) : R(0);
+      us[k] = hs ? ld(u, c - nx) : R(0);
+      ps[k] = hs ? ld(pprev, c - nx) : R(0);
+      un[k] = hn ? ld(u, c + nx) : R(0);
+      pn[k] = hn ? ld(pprev, c + nx) : R(0);
+      ub[k] = hb ? ld(u, c - sxy) : R(0);
+      pb[k] = hb ? ld(pprev, c - sxy) : R(0);
+      ut[k] = ht ? ld(u, c + sxy) : R(0);
+      pt[k] = ht ? ld(pprev, c + sxy) : R(0);
+      t0[k] = ld(Tx, fx);
+      t1[k] = ld(Tx, fx + 1);
+      t2[k] = ld(Ty, fy);
+      t3[k] = ld(Ty, fy + nx);
+      t4[k] = ld(Tz, c);
+      t5[k] = ld(Tz, c + sxy);
+      sl[k] = ld(slot, c);
+    }
+  }
+  // rho and ||r||^2 of the current residual, summed from the update partials
+  double rs[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < GU; i += kBlock) {
+    rs[0] += upart[i];
+    rs[1] += upart[GU + i];
+  }
+  psl::block_sum<2>(rs, lds2);
+  double beta_d = 0.5;
+  if (!bench) {
+    const double rho = rs[0], rr = rs[1];
+    const int cnt = sc->cnt[PAR ^ 1];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(rr < INFINITY) || !(fabs(rho) < INFINITY)) {
+      if (lead) {
+        sc->status = PSL_ENONFINITE;
+        sc->iters = cnt;
+        sc->stop_par = PAR;
+        sc->done = 1;
+      }
+      return;
+    }
+    if (rr <= sc->goal2 || cnt >= sc->maxit) {
+      if (lead) {
+        sc->rr = rr;
+        sc->iters = cnt;
+        sc->stop_par = PAR;
+        sc->done = 1;
+      }
+      return;
+    }
+    beta_d = rho / sc->gamma[PAR ^ 1];   // +inf before the first step of a fresh start
+    if (lead) {
+      sc->gamma[PAR] = rho;
+      sc->cnt[PAR] = cnt + 1;
+      sc->iters = cnt + 1;
+      sc->rr = rr;
+    }
+  }
+  const R beta = R(beta_d);
+  double acc[NS + 1];
+#pragma unroll
+  for (int k = 0; k <= NS; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (cc[k] < 0) continue;
+    const R p0 = axpy(beta, pc[k], uc[k]);
+    R ap = t0[k] * (p0 - axpy(beta, pw[k], uw[k]));
+    ap += t1[k] * (p0 - axpy(beta, pe[k], ue[k]));
+    ap += t2[k] * (p0 - axpy(beta, ps[k], us[k]));
+    ap += t3[k] * (p0 - axpy(beta, pn[k], un[k]));
+    ap += t4[k] * (p0 - axpy(beta, pb[k], ub[k]));
+    ap += t5[k] * (p0 - axpy(beta, pt[k], ut[k]));
+    st(p, uint32_t(cc[k]), p0);
+    st(q, uint32_t(cc[k]), ap);
+    const double qd = double(ap);
+    acc[NS] += double(p0) * qd;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? qd : 0.0;
+  }
+  psl::block_sum<NS + 1>(acc, lds);
+  double zs[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) zs[m] = acc[m];
+  write_slots<NS>(zs, T.nslot, slot_pos, t, zq);
+  if (threadIdx.x == 0) red[t] = acc[NS];
+}
+
+template <typename R, int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_sd_update(Geo g, const R* __restrict__ q, R* __restrict__ r, R* __restrict__ u,
+                const R* __restrict__ p, R* __restrict__ x, const R* __restrict__ invd,
+                const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
+                const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
+                const double* cpart, int G, double* upart, Scalars* sc, int bench) {
+  using psl::ld;
+  using psl::st;
+  __shared__ R corr[kTileMax];   // A Z e, rounded to the working precision
+  __shared__ double coef[2];     // alpha, go (1) / stop (0)
+  __shared__ double lds[2 * kNW];
+  if (sc->done) return;
+  double acc[2] = {0.0, 0.0};
+  bool first = true;
+  for (int tb = blockIdx.x; tb < g.ntiles; tb += gridDim.x) {
+    const int t = tile_of_block(tb, g.ntiles);
+    const Tile T = g.tiles[t];
+    const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+    int cc[CPT];
+    R qv[CPT], rv[CPT], pv[CPT], xv[CPT], dv[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int j = threadIdx.x + k * kBlock;
+      cc[k] = -1;
+      if (j < T.ncell) {
+        int ix, iy, iz;
+        cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+        const uint32_t c = ix + g.nx * (iy + g.ny * iz);
+        cc[k] = int(c);
+        qv[k] = ld(q, c);
+        rv[k] = ld(r, c);
+        pv[k] = ld(p, c);
+        xv[k] = ld(x, c);
+        dv[k] = ld(invd, c);
+      }
+    }
+    if (first && threadIdx.x < psl::kWave) {
+      // one wave reduces the coarse partials (fixed order) and takes the step decision
+      double alpha_d = 1e-3, go = 1.0;
+      if (!bench) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = threadIdx.x; i < G; i += psl::kWave) {
+          s0 += cpart[i];       // s^T e
+          s1 += cpart[G + i];   // (p, q)
+        }
+        s0 = psl::wave_sum(s0);
+        s1 = psl::wave_sum(s1);
+        const double den = s1 - s0;   // (p, P1 A p)
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (!(fabs(den) < INFINITY) || !(den > 0.0)) {
+          go = 0.0;
+          if (lead) {
+            sc->status = (fabs(den) < INFINITY) ? PSL_EBREAKDOWN : PSL_ENONFINITE;
+            sc->iters = sc->cnt[PAR] - 1;
+            sc->stop_par = -1;
+            sc->done = 1;
+          }
+        } else {
+          alpha_d = sc->gamma[PAR] / den;
+          if (lead) sc->delta = den;
+        }
+      }
+      if (threadIdx.x == 0) {
+        coef[0] = alpha_d;
+        coef[1] = go;
+      }
+    }
+    tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
+                    static_cast<const double*>(nullptr), corr, corr);  // ends with a barrier
+    if (coef[1] == 0.0) return;
+    const R alpha = R(coef[0]);
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (cc[k] < 0) continue;
+      const uint32_t c = uint32_t(cc[k]);
+      const int j = threadIdx.x + k * kBlock;
+      const R w = qv[k] - corr[j];
+      const R rn = rv[k] - alpha * w;
+      const R un = rn * dv[k];
+      st(x, c, axpy(alpha, pv[k], xv[k]));
+      st(r, c, rn);
+      st(u, c, un);
+      acc[0] += double(rn) * double(un);
+      acc[1] += double(rn) * double(rn);
+    }
+    first = false;
+    __syncthreads();   // corr is rewritten for the next tile
+  }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    upart[blockIdx.x] = acc[0];
+    upart[gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// Two-reduction start (fresh) or restart after a residual replacement (keep): r = sigma
+// r64, u = M^-1 r, x = 0 and the (r, u), (r, r) partials in the update layout. A fresh start
+// clears the previous direction; a kept direction is moved to the buffer the next parity-0
+// stencil pass reads when the last pass that ran had parity 1.
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+    k_sd_init(Geo g, const double* __restrict__ r64, const R* __restrict__ invd,
+              R* __restrict__ r, R* __restrict__ u, R* __restrict__ x, const R* __restrict__ p0,
+              R* __restrict__ p1, double* upart, const Scalars* sc, int fresh) {
+  __shared__ double lds[2 * kNW];
+  const double sigma = sc->sigma;
+  const bool move_p = !fresh && sc->stop_par == 1;
+  double acc[2] = {0.0, 0.0};
+  for (int tb = blockIdx.x; tb < g.ntiles; tb += gridDim.x) {
+    const int t = tile_of_block(tb, g.ntiles);
+    const Tile T = g.tiles[t];
+    const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+    for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const int c = ix + g.nx * (iy + g.ny * iz);
+      const R rv = R(sigma * r64[c]);
+      const R uv = rv * invd[c];
+      r[c] = rv;
+      u[c] = uv;
+      x[c] = R(0);
+      if (fresh)
+        p1[c] = R(0);
+      else if (move_p)
+        p1[c] = p0[c];
+      acc[0] += double(rv) * double(uv);
+      acc[1] += double(rv) * double(rv);
+    }
+  }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    upart[blockIdx.x] = acc[0];
+    upart[gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// Two-reduction inner start scalars. fresh: the scale comes from the current float64
+// residual and rho_prev = +inf (first step along u); otherwise the scale, the direction
+// and its rho are kept (rho moved to the slot the parity-0 pass reads).
+__global__ void k_sd_set(Scalars* sc, double goal2, int maxit, int fresh) {
+  if (fresh) {
+    sc->rnorm = sqrt(sc->rr);
+    sc->sigma = sc->rnorm > 0.0 ? 1.0 / sc->rnorm : 0.0;
+    sc->gamma[1] = INFINITY;
+  } else if (sc->stop_par == 1) {
+    sc->gamma[1] = sc->gamma[0];
+  }
+  sc->cnt[1] = 0;
+  sc->goal2 = goal2;
+  sc->maxit = maxit;
+  sc->done = 0;
+  sc->iters = 0;
+  sc->status = 0;
+}
+
 // Inner start: r = sigma r64 (cast to R), u = M^-1 r; x = p = q = 0. The first stencil
 // pass then forms every inner product.
 template <typename R>
@@ -691,6 +996,16 @@ __global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
+// float32 -> float64 copy of both search-direction buffers (precision handover that
+// keeps the Krylov direction)
+__global__ void k_widen2(int n, const float* __restrict__ a, const float* __restrict__ b,
+                         double* __restrict__ a64, double* __restrict__ b64) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    a64[c] = double(a[c]);
+    b64[c] = double(b[c]);
+  }
+}
+
 __global__ void k_reset(Scalars* sc) {
   sc->done = 0;
   sc->iters = 0;
@@ -724,8 +1039,7 @@ struct Prec<double> {
   static const double* invd(const psl_ctx* c) { return c->invdiag; }
   static const double* azt(const psl_ctx* c) { return c->az_t; }
   static psl::VecSet<double>& vecs(psl_ctx* c) { return c->v64; }
-  static hipGraphExec_t& graph(psl_ctx* c) { return c->graph64; }
-  static int& graph_key(psl_ctx* c) { return c->graph_chunk64; }
+  static psl::GraphSlot* graphs(psl_ctx* c) { return c->graphs64; }
 };
 template <>
 struct Prec<float> {
@@ -735,8 +1049,7 @@ struct Prec<float> {
   static const float* invd(const psl_ctx* c) { return c->invdiag32; }
   static const float* azt(const psl_ctx* c) { return c->az_t32; }
   static psl::VecSet<float>& vecs(psl_ctx* c) { return c->v32; }
-  static hipGraphExec_t& graph(psl_ctx* c) { return c->graph32; }
-  static int& graph_key(psl_ctx* c) { return c->graph_chunk32; }
+  static psl::GraphSlot* graphs(psl_ctx* c) { return c->graphs32; }
 };
 
 template <typename R>
@@ -746,7 +1059,7 @@ int ensure_vecs(psl_ctx* c) {
   const size_t bytes = sizeof(R) * size_t(c->n);
   R** ptrs[6] = {&v.xh, &v.rh, &v.p, &v.q, &v.v, &v.u};
   for (R** p : ptrs)
-    if (psl_internal_alloc(reinterpret_cast<void**>(p), bytes) != PSL_OK) return PSL_ENOMEM;
+    if (psl_ctx_alloc(c, reinterpret_cast<void**>(p), bytes) != PSL_OK) return PSL_ENOMEM;
   return PSL_OK;
 }
 
@@ -867,6 +1180,63 @@ struct ZtL {
   }
 };
 
+template <typename R, int PAR, int NS>
+struct SdStencilC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st, int bench) {
+      psl::VecSet<R>& v = Prec<R>::vecs(c);
+      hipLaunchKernelGGL((k_sd_stencil<R, NS, CPT, PAR>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
+                         v.u, PAR ? v.p : v.p2, PAR ? v.p2 : v.p, v.q, c->slot, c->slot_pos,
+                         c->zq, c->red, c->upart, c->upd_blocks, c->sc, bench);
+    }
+  };
+};
+
+template <typename R, int PAR>
+struct SdStencilL {
+  template <int NS>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st, int bench) {
+      with_cpt<SdStencilC<R, PAR, NS>::template F>(c->cpt, c, st, bench);
+    }
+  };
+};
+
+template <typename R, int PAR>
+struct SdUpdateC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, hipStream_t st, int bench) {
+      psl::VecSet<R>& v = Prec<R>::vecs(c);
+      hipLaunchKernelGGL((k_sd_update<R, CPT, PAR>), dim3(c->upd_blocks), dim3(kBlock), 0, st,
+                         geo(c), v.q, v.rh, v.u, PAR ? v.p2 : v.p, v.xh, Prec<R>::invd(c),
+                         c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
+                         c->cpart, c->coarse_blocks, c->upart, c->sc, bench);
+    }
+  };
+};
+
+// buffers of the two-reduction form: the search direction is double-buffered by parity
+// (parity 0 writes p, parity 1 writes p2)
+constexpr int kUpdMaxBlocks = 1024;
+
+template <typename R>
+int ensure_sd(psl_ctx* c) {
+  int rc = ensure_vecs<R>(c);
+  if (rc != PSL_OK) return rc;
+  psl::VecSet<R>& v = Prec<R>::vecs(c);
+  if (!v.p2 && psl_ctx_alloc(c, reinterpret_cast<void**>(&v.p2), sizeof(R) * size_t(c->n)) != PSL_OK)
+    return PSL_ENOMEM;
+  if (!c->upart) {
+    c->upd_blocks = std::min(c->ntiles, kUpdMaxBlocks);
+    if (psl_ctx_alloc(c, reinterpret_cast<void**>(&c->upart), sizeof(double) * 2 * c->upd_blocks) != PSL_OK)
+      return PSL_ENOMEM;
+  }
+  return PSL_OK;
+}
+
 void launch_outer_deflate(psl_ctx* c, double* x, const double* rin, double* rout,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_outer_deflate, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), x, rin,
@@ -912,38 +1282,70 @@ void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
   }
 }
 
-// Capture `chunk` iterations into a graph once per (precision, chunk, re-projection);
+// one two-reduction iteration of parity PAR (three launches)
+template <typename R, int PAR>
+void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
+  with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, 0);
+  launch_coarse<0, 1>(c, 1, st);
+  with_cpt<SdUpdateC<R, PAR>::template F>(c->cpt, c, st, 0);
+}
+
+template <typename R>
+void enqueue_sd_iterations(psl_ctx* c, int count, hipStream_t st) {
+  for (int i = 0; i < count; i += 2) {
+    enqueue_sd_iteration<R, 0>(c, st);
+    enqueue_sd_iteration<R, 1>(c, st);
+  }
+}
+
+// CG forms
+constexpr int kFormSingle = 0;   // single-reduction recurrences
+constexpr int kFormTwo = 1;      // two-reduction loop with residual replacement
+
+template <typename R>
+void enqueue_form(psl_ctx* c, int form, int chunk, int rp, hipStream_t st) {
+  if (form == kFormTwo)
+    enqueue_sd_iterations<R>(c, chunk, st);
+  else
+    enqueue_iterations<R>(c, chunk, rp, st);
+}
+
+// Capture `chunk` iterations into a graph once per (precision, form, chunk, re-projection);
 // replay it afterwards.
 template <typename R>
-int run_chunk(psl_ctx* c, int chunk, int rp, hipStream_t st) {
-  hipGraphExec_t& ge = Prec<R>::graph(c);
-  int& key = Prec<R>::graph_key(c);
-  const int want = chunk * 2 + (rp ? 1 : 0);
-  if (!ge || key != want) {
-    if (ge) {
-      (void)hipGraphExecDestroy(ge);
-      ge = nullptr;
+int run_chunk(psl_ctx* c, int form, int chunk, int rp, hipStream_t st) {
+  psl::GraphSlot* slots = Prec<R>::graphs(c);
+  const int want = chunk * 4 + form * 2 + (rp ? 1 : 0);
+  psl::GraphSlot* use = nullptr;
+  for (int i = 0; i < psl::kGraphSlots && !use; ++i)
+    if (slots[i].exec && slots[i].key == want) use = &slots[i];
+  if (!use) {
+    use = &slots[0];
+    for (int i = 0; i < psl::kGraphSlots; ++i)
+      if (!slots[i].exec) {
+        use = &slots[i];
+        break;
+      }
+    if (use->exec) {
+      (void)hipGraphExecDestroy(use->exec);
+      use->exec = nullptr;
     }
-    hipStream_t cap;
-    PSL_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t cap = psl_internal_capture_stream();
+    if (!cap) return PSL_EHIP;
     hipGraph_t graph;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      (void)hipStreamDestroy(cap);
-      return PSL_EHIP;
-    }
-    enqueue_iterations<R>(c, chunk, rp, cap);
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PSL_EHIP;
+    enqueue_form<R>(c, form, chunk, rp, cap);
     hipError_t e1 = hipStreamEndCapture(cap, &graph);
-    (void)hipStreamDestroy(cap);
     if (e1 != hipSuccess) return PSL_EHIP;
-    hipError_t e2 = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    hipError_t e2 = hipGraphInstantiate(&use->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) {
-      ge = nullptr;
+      use->exec = nullptr;
       return PSL_EHIP;
     }
-    key = want;
+    use->key = want;
   }
-  PSL_HIP(hipGraphLaunch(ge, st));
+  PSL_HIP(hipGraphLaunch(use->exec, st));
   return PSL_OK;
 }
 
@@ -958,16 +1360,22 @@ constexpr int kStallWindow = 512;   // inner iterations without halving ||r|| ->
 // Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
 template <typename R>
-int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, int rp,
-                int use_graph, int outer, hipStream_t st, int* iters, int* status,
-                int* stalled) {
-  int rc = ensure_vecs<R>(c);
+int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int maxit,
+                int check_every, int rp, int use_graph, int outer, hipStream_t st, int* iters,
+                int* status, int* stalled) {
+  int rc = form == kFormTwo ? ensure_sd<R>(c) : ensure_vecs<R>(c);
   if (rc != PSL_OK) return rc;
   psl::VecSet<R>& v = Prec<R>::vecs(c);
   const int chunk = check_every + (check_every & 1);  // parity pattern needs an even count
-  hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit);
-  hipLaunchKernelGGL(k_cg_init<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n),
-                     c->r64, Prec<R>::invd(c), v.rh, v.u, v.xh, v.p, v.q, c->sc);
+  if (form == kFormTwo) {
+    hipLaunchKernelGGL(k_sd_set, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit, fresh);
+    hipLaunchKernelGGL(k_sd_init<R>, dim3(c->upd_blocks), dim3(kBlock), 0, st, geo(c), c->r64,
+                       Prec<R>::invd(c), v.rh, v.u, v.xh, v.p, v.p2, c->upart, c->sc, fresh);
+  } else {
+    hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit);
+    hipLaunchKernelGGL(k_cg_init<R>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, int(c->n),
+                       c->r64, Prec<R>::invd(c), v.rh, v.u, v.xh, v.p, v.q, c->sc);
+  }
   double best = INFINITY;
   int best_it = 0;
   *stalled = 0;
@@ -978,10 +1386,10 @@ int inner_solve(psl_ctx* c, double* x, double goal, int maxit, int check_every, 
   for (;;) {
     for (int bi = 0; bi < batches; ++bi) {
       if (use_graph) {
-        rc = run_chunk<R>(c, chunk, rp, st);
+        rc = run_chunk<R>(c, form, chunk, rp, st);
         if (rc != PSL_OK) return rc;
       } else {
-        enqueue_iterations<R>(c, chunk, rp, st);
+        enqueue_form<R>(c, form, chunk, rp, st);
         PSL_HIP(hipGetLastError());
       }
     }
@@ -1036,6 +1444,7 @@ extern "C" int psl_deflate(psl_ctx* c, const double* r, double* out, double* cve
 
 extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve_opts* o_in,
                          psl_solve_stats* st_out, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   if (!c || !b || !x) return PSL_EINVAL;
   psl_solve_opts o;
@@ -1044,7 +1453,7 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   if (!(o.tol > 0.0) || o.maxit < 0 || o.max_outer < 1 ||
       (o.mode != PSL_FP64 && o.mode != PSL_MIXED) || o.check_every < 1 ||
       o.check_every > 4096 || !(o.tau_inner > 0.0 && o.tau_inner < 1.0) || o.reproject < -1 ||
-      o.reproject > 1)
+      o.reproject > 1 || !(o.mixed_floor >= 0.0 && o.mixed_floor < 1.0))
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int n = int(c->n);
@@ -1086,6 +1495,16 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   int status = PSL_EMAXIT;
   double prev_rnorm = INFINITY;
   int last_inner_broke = 0;
+  // float32 CG keeps its search direction across refinement steps (residual replacement)
+  // as long as each of its runs ended by reaching its goal; `scale` is the residual norm
+  // its vectors are measured in
+  int keep_direction = 0;
+  double scale = 1.0;
+  double inner_reached = 0.0;   // recursive float32 residual norm the last run ended at
+  int widen_direction = 0;      // next float64 run continues the float32 direction
+  int last_fresh64 = 0;         // the last inner run was a fresh float64 run that did not stall
+  const int form64 = kFormSingle;   // float64: single-reduction recurrences
+  const int form32 = kFormTwo;      // float32: two-reduction loop with residual replacement
   for (int outer = 0;; ++outer) {
     // projects the previous inner correction and forms x* for the next inner solve
     enqueue_outer_step(c, b, x, st);
@@ -1107,11 +1526,22 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       status = PSL_EMAXIT;
       break;
     }
-    if (outer > 0 && rnorm > 0.5 * prev_rnorm) {
+    // float32 has reached its attainable accuracy once the float64 residual no longer
+    // follows the recursive one (it lags by more than half again)
+    const bool detached = mode == PSL_MIXED && keep_direction && rnorm > 1.5 * inner_reached;
+    const bool floor = mode == PSL_MIXED && rnorm <= o.mixed_floor * bnorm;
+    if ((outer > 0 && (rnorm > 0.5 * prev_rnorm || detached)) || floor) {
       if (mode == PSL_MIXED) {
         mode = PSL_FP64;  // float32 CG stopped reducing the float64 residual
         stats.fell_back = 1;
-      } else if (rnorm > 0.9 * prev_rnorm) {
+        // a float32 run that ended normally hands its search direction on: float64 CG
+        // continues from it rather than restarting (a restart late in the solve loses the
+        // Krylov space it took most of the iterations to build)
+        widen_direction = keep_direction && !(outer > 0 && rnorm > 0.5 * prev_rnorm);
+        keep_direction = 0;
+      } else if (rnorm > 0.9 * prev_rnorm && last_fresh64) {
+        // only a fresh float64 run that made no progress ends the solve; after a
+        // continued or stalled run the next one starts fresh
         status = last_inner_broke ? PSL_EBREAKDOWN : PSL_ESTAGNATION;
         break;
       }
@@ -1121,12 +1551,28 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
     int it = 0, ist = 0, stalled = 0;
     if (mode == PSL_MIXED) {
       const int rp = o.reproject != 0;
-      rc = inner_solve<float>(c, x, std::max(o.tau_inner, target), o.maxit - total_iters,
-                              o.check_every, rp, use_graph, outer, st, &it, &ist, &stalled);
+      const int fresh = !(keep_direction && form32 == kFormTwo);
+      if (fresh) scale = rnorm;
+      // goal of this run relative to `scale`: a reduction by tau_inner, or the tolerance
+      const double goal = std::max(o.tau_inner * rnorm, o.tol * bnorm) / scale;
+      rc = inner_solve<float>(c, x, form32, fresh, goal, o.maxit - total_iters, o.check_every,
+                              rp, use_graph, outer, st, &it, &ist, &stalled);
+      keep_direction = (rc == PSL_OK && ist == PSL_OK && !stalled);
+      inner_reached = std::sqrt(c->h_sc->rr) * scale;
+    } else if (widen_direction) {
+      widen_direction = 0;
+      rc = ensure_sd<double>(c);
+      if (rc != PSL_OK) return finish(rc);
+      hipLaunchKernelGGL(k_widen2, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->v32.p,
+                         c->v32.p2, c->v64.p, c->v64.p2);
+      rc = inner_solve<double>(c, x, kFormTwo, 0, o.tol * bnorm / scale, o.maxit - total_iters,
+                               o.check_every, 0, use_graph, outer, st, &it, &ist, &stalled);
+      last_fresh64 = 0;
     } else {
       const int rp = o.reproject == 1;
-      rc = inner_solve<double>(c, x, target, o.maxit - total_iters, o.check_every, rp,
-                               use_graph, outer, st, &it, &ist, &stalled);
+      rc = inner_solve<double>(c, x, form64, 1, target, o.maxit - total_iters, o.check_every,
+                               rp, use_graph, outer, st, &it, &ist, &stalled);
+      last_fresh64 = !stalled;
     }
     if (rc != PSL_OK) return finish(rc);
     if (verbose)
@@ -1154,30 +1600,31 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
 
 extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t reps,
                                 void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (!c || reps < 1 || (mode != PSL_FP64 && mode != PSL_MIXED) || kernel < 0 ||
       kernel > PSL_KERNEL_OUTER_RESIDUAL)
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int rc = mode == PSL_MIXED ? ensure_vecs<float>(c) : ensure_vecs<double>(c);
+  int rc = mode == PSL_MIXED ? ensure_sd<float>(c) : ensure_vecs<double>(c);
   if (rc != PSL_OK) return rc;
   hipLaunchKernelGGL(k_bench_prep, dim3(1), dim3(1), 0, st, c->sc);
   for (int i = 0; i < reps; ++i) {
     switch (kernel) {
       case PSL_KERNEL_STENCIL:
         if (mode == PSL_MIXED)
-          with_ns<CgStencilL<float, 1>::template F>(c->nslot_max, c, st);
+          with_ns<SdStencilL<float, 0>::template F>(c->nslot_max, c, st, 1);
         else
           with_ns<CgStencilL<double, 0>::template F>(c->nslot_max, c, st);
         break;
       case PSL_KERNEL_COARSE:
         if (mode == PSL_MIXED)
-          launch_coarse<1, kCgQ>(c, 1, st);
+          launch_coarse<0, 1>(c, 1, st);
         else
           launch_coarse<0, kCgQ>(c, 1, st);
         break;
       case PSL_KERNEL_UPDATE:
         if (mode == PSL_MIXED)
-          with_cpt<CgUpdateC<float, 1, 0>::template F>(c->cpt, c, st, 1);
+          with_cpt<SdUpdateC<float, 0>::template F>(c->cpt, c, st, 1);
         else
           with_cpt<CgUpdateC<double, 0, 0>::template F>(c->cpt, c, st, 1);
         break;

@@ -42,7 +42,7 @@ class psl_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("max_outer", ctypes.c_int32),
                 ("tau_inner", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("reproject", ctypes.c_int32)]
+                ("reproject", ctypes.c_int32), ("mixed_floor", ctypes.c_double)]
 
 
 class psl_ctx_info(ctypes.Structure):
@@ -224,7 +224,8 @@ def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *
               tol: Optional[float] = None, maxit: Optional[int] = None, mode: int = FP64,
               use_x0: bool = False, max_outer: Optional[int] = None,
               tau_inner: Optional[float] = None, check_every: Optional[int] = None,
-              reproject: Optional[int] = None, check: bool = False):
+              reproject: Optional[int] = None, mixed_floor: Optional[float] = None,
+              check: bool = False):
     """Solve A x = b; returns (x, stats dict). Non-zero status raises only if check=True."""
     o = default_opts()
     if tol is not None:
@@ -241,6 +242,8 @@ def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *
         o.check_every = check_every
     if reproject is not None:
         o.reproject = int(reproject)
+    if mixed_floor is not None:
+        o.mixed_floor = float(mixed_floor)
     if x is None:
         if use_x0:
             raise ValueError("use_x0 needs x")

@@ -51,10 +51,10 @@ def test_binding_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
         " sizeof(psl_solve_stats), offsetof(psl_solve_opts, tau_inner),"
-        " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_stats, relres_true),"
-        " sizeof(psl_grid));return 0;}\n")
+        " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_opts, mixed_floor),"
+        " offsetof(psl_solve_stats, relres_true), sizeof(psl_grid));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -62,7 +62,8 @@ def test_binding_struct_layout_matches_c(tmp_path):
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(psl.psl_solve_opts), ctypes.sizeof(psl.psl_solve_stats),
             psl.psl_solve_opts.tau_inner.offset, psl.psl_solve_opts.check_every.offset,
-            psl.psl_solve_stats.relres_true.offset, ctypes.sizeof(psl.psl_grid)]
+            psl.psl_solve_opts.mixed_floor.offset, psl.psl_solve_stats.relres_true.offset,
+            ctypes.sizeof(psl.psl_grid)]
     assert got == want
 
 
@@ -70,6 +71,7 @@ def test_default_opts(lib):
     from paper_1510_02148_amd import psl
     o = psl.default_opts()
     assert o.tol == 1e-8 and o.maxit == 10000 and o.mode == psl.FP64 and o.check_every == 16
+    assert o.tau_inner == 0.1 and o.reproject == -1 and o.mixed_floor == 1e-4
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):
