@@ -32,6 +32,8 @@ WORKLOADS = {
           "8x8x4 subdomains x 2 levelsets",
     "c3": "channelized 256x256x128 (GRF corr. length 16, 30% channels), contrast 1e6, "
           "16x16x8 subdomains x 2 levelsets",
+    "c4": "batch of 64 layered cubes, side U{32..96} (seed-drawn), contrast log-uniform "
+          "1e4..1e6, 4x4x4 subdomains x 2 levelsets, well columns; solved together",
 }
 
 
@@ -96,6 +98,122 @@ def make_problem(name: str, seed: int):
     return pi.config(name, seed=seed)
 
 
+def run_batched(args):
+    """64 uneven systems solved together (psl_solve_batched, float64 CG): one step =
+    set-up of every system (tuned tile sizes) + the batched solve to 1e-8 each."""
+    import numpy as np
+    import torch
+
+    import psl_inputs as pi
+    from paper_1510_02148_amd import autotune, pipeline, psl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    probs = pi.batch(nsys=64, seed=args.seed)
+    ntot = sum(p.n for p in probs)
+    log(f"workload c4: 64 systems, sides {min(p.grid[0] for p in probs)}.."
+        f"{max(p.grid[0] for p in probs)}, {ntot} cells")
+    Ks = [torch.as_tensor(p.K, dtype=torch.float64, device="cuda") for p in probs]
+    bs = [torch.as_tensor(p.q, dtype=torch.float64, device="cuda") for p in probs]
+    table = autotune.load_table()
+    tiles = autotune.tiles_for([p.grid for p in probs], table)
+    if any(t is None for t in tiles):
+        log("no tuned tile sizes for this GPU: tuning (outside the timed region)")
+        table = autotune.tune(probs, log=log)
+        tiles = autotune.tiles_for([p.grid for p in probs], table)
+    torch.cuda.synchronize()
+
+    def setup_all(tl):
+        return [pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), tile_cells=t)
+                for p, K, t in zip(probs, Ks, tl)]
+
+    def step(tl):
+        t0 = time.perf_counter()
+        setups = setup_all(tl)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xs, stats, rc = psl.psl_solve_batched([s.ctx for s in setups], bs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return setups, xs, stats, rc, t1 - t0, t2 - t1
+
+    def leg(tl, label):
+        for _ in range(args.warmup):
+            step(tl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = [step(tl) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        setups, xs, stats, rc = rec[-1][:4]
+        log(f"{label}: {wall * 1e3:.2f} ms/step, setup {np.median([r[4] for r in rec]) * 1e3:.1f}"
+            f" ms, solve {np.median([r[5] for r in rec]) * 1e3:.1f} ms, status {rc}")
+        return rec, wall
+
+    rec, wall = leg(tiles, "batched, tuned tiles")
+    setups, xs, stats, rc = rec[-1][:4]
+    solve_s = float(np.median([r[5] for r in rec]))
+    setup_s = float(np.median([r[4] for r in rec]))
+    ok = rc == 0 and all(st["relres_true"] <= 1e-8 for st in stats)
+    # the same systems solved one after another by psl_solve
+    torch.cuda.synchronize()
+    seq = []
+    for _ in range(max(1, args.steps // 2)):
+        t0 = time.perf_counter()
+        for s, b in zip(setups, bs):
+            psl.psl_solve(s.ctx, b, mode=psl.FP64)
+        torch.cuda.synchronize()
+        seq.append(time.perf_counter() - t0)
+    seq_s = float(np.median(seq))
+    log(f"sequential psl_solve: {seq_s * 1e3:.1f} ms")
+    _, wall_def = leg([None] * len(probs), "batched, library-default tiles")
+    # effective bandwidth of the whole batched solve (stencil + coarse + update per iteration)
+    total_bytes = 0.0
+    for p, s, st in zip(probs, setups, stats):
+        info = psl.psl_get_info(s.ctx)
+        per_it = sum(algorithmic_bytes(k, p.grid, s.d, int(info["m_faces"]), 8, False)
+                     for k in ("stencil", "coarse", "update"))
+        total_bytes += st["iters"] * per_it
+    gbs = total_bytes / solve_s / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import psl_oracle as O
+        sample = sorted(range(len(probs)), key=lambda i: probs[i].n)[::16][:3]
+        ns = sum(probs[i].n for i in sample)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for i in sample:
+                p = probs[i]
+                A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+                lab, dd = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+                O.dpcg(A, bh, O.deflation_matrix(lab, dd), tol=p.tol)
+            t_s = time.perf_counter() - t0
+        cpu = {"value": round(t_s * ntot / ns, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"systems {sample} ({ns} of {ntot} cells) solved whole by the oracle "
+                         f"in {t_s:.2f} s on 1 thread, scaled by cells to the batch"}
+        log(f"cpu oracle sample: {t_s:.2f} s for {ns} cells")
+    out = {
+        "metric": METRIC, "value": round(wall, 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"], "systems": len(probs), "cells": ntot,
+                   "tol": 1e-8, "mode": "fp64", "seed": args.seed},
+        "converged": bool(ok), "iterations_max": max(st["iters"] for st in stats),
+        "iterations_mean": round(float(np.mean([st["iters"] for st in stats])), 1),
+        "setup_s": setup_s, "solve_s": solve_s, "sequential_solve_s": seq_s,
+        "speedup_vs_sequential": round(seq_s / solve_s, 3),
+        "default_tiles_s_per_step": round(wall_def, 6),
+        "tiles": {str(k): v["tile_cells"] for k, v in sorted(table.items())},
+        "roofline": {"bound": "hbm", "kernel": "batched CG (stencil + coarse + update)",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +237,8 @@ def main():
         sys.exit(2)
     if args.quick:
         args.steps, args.warmup, args.no_fp64, args.no_cpu_baseline = 1, 0, True, True
+    if args.workload == "c4":
+        return run_batched(args)
 
     import numpy as np
     import torch

@@ -165,6 +165,27 @@ int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double
                 const double* Tz, const int32_t* labels, int32_t d, const int32_t nsub[3],
                 void* stream);
 
+/* Options of psl_setup_E_ex. */
+typedef struct {
+  int32_t tile_cells;   /* cells per work tile, 64..2048 (one workgroup each; tiles never
+                           straddle a subdomain); 0 = the library's choice (1024, halved
+                           down to 256 while the grid would give fewer than 2048 tiles) */
+  int32_t reserved[7];  /* must be 0 */
+} psl_setup_opts;
+
+/* Fill `o` with the defaults (all zero). */
+void psl_default_setup_opts(psl_setup_opts* o);
+
+/*
+ * psl_setup_E_ex -- psl_setup_E with options (NULL = defaults; psl_setup_E passes NULL).
+ * The tile size trades workgroup count against per-workgroup work; the tile autotuner
+ * (paper_1510_02148_amd/autotune.py) picks it per shape class by timing solves.
+ * Errors: as psl_setup_E, and PSL_EINVAL for tile_cells outside 64..2048 (0 allowed).
+ */
+int psl_setup_E_ex(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double* Ty,
+                   const double* Tz, const int32_t* labels, int32_t d, const int32_t nsub[3],
+                   const psl_setup_opts* o, void* stream);
+
 /*
  * psl_solve -- solve A x = b (eq. "coupledsys", reservoir block) with Jacobi-
  * preconditioned CG on the deflated system P1 A xhat = P1 b (eqs. "deflops", "defsys";
@@ -194,6 +215,29 @@ int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double
  */
 int psl_solve(psl_ctx* ctx, const double* b, double* x, const psl_solve_opts* o,
               psl_solve_stats* st, void* stream);
+
+/*
+ * psl_solve_batched -- solve nsys independent systems A_i x_i = b_i, each set up by its
+ * own psl_setup_E, together: every float64 CG launch covers the work tiles of all systems
+ * through a (system, tile) work list, while each system keeps its own scalars, tolerance
+ * test and stop flag (a converged system's workgroups return at once). The per-system
+ * arithmetic is that of psl_solve in PSL_FP64, so each x_i is the one psl_solve returns
+ * for that system alone. The launch plan (argument table, work lists, captured graph of
+ * iteration chunks) is cached on ctxs[0] while the same contexts are passed in the same
+ * order.
+ *   ctxs  host[nsys]: distinct contexts on the current device.
+ *   b, x  host[nsys] arrays of device pointers, each dev[n_i] float64 (as in psl_solve).
+ *   o     options as in psl_solve (NULL = defaults); use_x0 applies to every system.
+ *   st    host out[nsys] statistics (may be NULL); st[i].status is system i's result.
+ * A system that stalls or breaks down is finished by psl_solve from its current x.
+ * Returns PSL_OK if every system converged, otherwise the first failing system's code.
+ * Errors: PSL_EINVAL (null pointers, nsys < 1, a context twice, another device),
+ * PSL_ENOTSUP (PSL_MIXED, or a context whose coarse solve needs the separate label
+ * reduction: d > 4096 or very many label partials).
+ */
+int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const double* const* b,
+                      double* const* x, const psl_solve_opts* o, psl_solve_stats* st,
+                      void* stream);
 
 /*
  * psl_apply_A -- q = A p in float64 (the stencil product used by every solve; the

@@ -64,8 +64,15 @@ struct GraphSlot {
 
 }  // namespace psl
 
+namespace psl {
+struct BatchPlan;   // batched-solve launch plan (psl_solve.hip)
+void destroy_batch_plan(BatchPlan* p);
+}  // namespace psl
+
 struct psl_ctx {
   int dev = 0;
+  uint64_t id = 0;                    // unique per context in the process (never reused)
+  psl::BatchPlan* plan = nullptr;     // batched-solve plan cached on the batch's first context
   int nx = 0, ny = 0, nz = 0;
   int64_t n = 0;
   int d = 0;

@@ -2,6 +2,7 @@
 // the interface rows of A Z, E = Z^T A Z and its float64 Cholesky factor and inverse.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 
 #include <algorithm>
@@ -900,6 +901,7 @@ extern "C" void psl_destroy(psl_ctx* c) {
   (void)hipSetDevice(c->dev);
   (void)hipDeviceSynchronize();
   psl_alloc_stream = nullptr;   // the caller's stream may be gone; the device is idle
+  psl::destroy_batch_plan(c->plan);
   for (int i = 0; i < psl::kGraphSlots; ++i) {
     if (c->graphs64[i].exec) (void)hipGraphExecDestroy(c->graphs64[i].exec);
     if (c->graphs32[i].exec) (void)hipGraphExecDestroy(c->graphs32[i].exec);
@@ -937,7 +939,24 @@ static int dalloc(psl_ctx* c, T** p, int64_t count) {
 extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
                            const double* Ty, const double* Tz, const int32_t* labels,
                            int32_t d, const int32_t nsub[3], void* stream) {
+  return psl_setup_E_ex(out, g, Tx, Ty, Tz, labels, d, nsub, nullptr, stream);
+}
+
+extern "C" void psl_default_setup_opts(psl_setup_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+}
+
+extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx,
+                              const double* Ty, const double* Tz, const int32_t* labels,
+                              int32_t d, const int32_t nsub[3], const psl_setup_opts* so,
+                              void* stream) {
   psl_alloc_stream = static_cast<hipStream_t>(stream);
+  if (so) {
+    if (so->tile_cells != 0 && (so->tile_cells < 64 || so->tile_cells > 2048)) return PSL_EINVAL;
+    for (int32_t r : so->reserved)
+      if (r != 0) return PSL_EINVAL;
+  }
   if (!out) return PSL_EINVAL;
   *out = nullptr;
   if (!grid_ok(g) || !Tx || !Ty || !Tz || !labels || d < 1) return PSL_EINVAL;
@@ -957,7 +976,9 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   }
   if (int64_t(d) > int64_t(nx) * ny * nz) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  static std::atomic<uint64_t> next_id{1};
   psl_ctx* c = new psl_ctx();
+  c->id = next_id.fetch_add(1);
   (void)hipGetDevice(&c->dev);
   c->nx = nx;
   c->ny = ny;
@@ -1026,14 +1047,11 @@ extern "C" int psl_setup_E(psl_ctx** out, const psl_grid* g, const double* Tx,
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfy)), dim3(kBlock), 0, st, c->Ty, c->Ty32, nfy);
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfz)), dim3(kBlock), 0, st, c->Tz, c->Tz32, nfz);
 
-  // tiles: enough workgroups to fill the chip (>= 8 per CU when the grid allows),
-  // then shrink until no tile holds more than kMaxSlots labels
+  // tiles: enough workgroups to fill the chip (>= 8 per CU when the grid allows) unless
+  // the caller fixes the size; then shrink until no tile holds more than kMaxSlots labels
   int tile_max = 1024;
   while (tile_max > 256 && int64_t(n) / tile_max < 2048) tile_max /= 2;
-  if (const char* env = std::getenv("PSL_TILE_MAX")) {
-    const int v = std::atoi(env);
-    if (v >= 64 && v <= 2048) tile_max = v;
-  }
+  if (so && so->tile_cells) tile_max = so->tile_cells;
   for (;;) {
     c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
     c->ntiles = int(c->h_tiles.size());

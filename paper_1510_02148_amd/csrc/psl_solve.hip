@@ -189,17 +189,16 @@ __global__ void __launch_bounds__(kBlock)
 // (zr).
 // ---------------------------------------------------------------------------------------
 template <typename R, int NS, int RP, int CPT>
-__global__ void __launch_bounds__(kBlock)
-    k_cg_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
-                 const R* __restrict__ Tz, const R* __restrict__ r, const R* __restrict__ u,
-                 R* __restrict__ v, const uint8_t* __restrict__ slot,
-                 const int32_t* __restrict__ slot_pos, double* zq, double* zr, double* red,
-                 const Scalars* sc) {
+__device__ inline void cg_stencil_tile(int t, Geo g, const R* __restrict__ Tx,
+                                       const R* __restrict__ Ty, const R* __restrict__ Tz,
+                                       const R* __restrict__ r, const R* __restrict__ u,
+                                       R* __restrict__ v, const uint8_t* __restrict__ slot,
+                                       const int32_t* __restrict__ slot_pos, double* zq,
+                                       double* zr, double* red, const Scalars* sc) {
   using psl::ld;
   constexpr int NA = NS + 3 + (RP ? NS : 0);
   __shared__ double lds[NA * kNW];
   if (sc->done) return;
-  const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -279,6 +278,17 @@ __global__ void __launch_bounds__(kBlock)
   }
 }
 
+template <typename R, int NS, int RP, int CPT>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
+                 const R* __restrict__ Tz, const R* __restrict__ r, const R* __restrict__ u,
+                 R* __restrict__ v, const uint8_t* __restrict__ slot,
+                 const int32_t* __restrict__ slot_pos, double* zq, double* zr, double* red,
+                 const Scalars* sc) {
+  cg_stencil_tile<R, NS, RP, CPT>(tile_of_block(blockIdx.x, g.ntiles), g, Tx, Ty, Tz, r, u, v,
+                                  slot, slot_pos, zq, zr, red, sc);
+}
+
 // s = Z^T v (and sr = Z^T r when RP) from label-major partials, spread over workgroups
 // (used when the coarse kernel cannot stage all of s itself).
 template <int RP>
@@ -299,19 +309,18 @@ __global__ void __launch_bounds__(kBlock)
 // for q < NQ, cpart[(1 + q) G + g] = its slice of the tile partials red[q * ntiles + .].
 // ---------------------------------------------------------------------------------------
 template <int RP, int FUSED, int NQ>
-__global__ void __launch_bounds__(kBlock)
-    k_coarse(const double* __restrict__ Einv, const double* zq, const double* zr,
-             const int32_t* lab_ptr, double* s, double* sr, double* e, double* er,
-             const double* red, int ntiles, double* cpart, int d, const Scalars* sc,
-             int check_done) {
+__device__ inline void coarse_block(int blk, int G, const double* __restrict__ Einv,
+                                    const double* zq, const double* zr, const int32_t* lab_ptr,
+                                    double* s, double* sr, double* e, double* er,
+                                    const double* red, int ntiles, double* cpart, int d,
+                                    const Scalars* sc, int check_done) {
   __shared__ double ss[kSChunk];
   __shared__ double ss2[RP ? kSChunk : 1];
   __shared__ double lds[(1 + NQ) * kNW];
   if (check_done && sc->done) return;
   const int lane = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
-  const int G = gridDim.x;
   constexpr int kRowsPerWave = kCoarseRows / kNW;
-  const int row0 = blockIdx.x * kCoarseRows + w * kRowsPerWave;
+  const int row0 = blk * kCoarseRows + w * kRowsPerWave;
   double racc[kRowsPerWave], racc2[kRowsPerWave];
 #pragma unroll
   for (int r = 0; r < kRowsPerWave; ++r) racc[r] = racc2[r] = 0.0;
@@ -323,7 +332,7 @@ __global__ void __launch_bounds__(kBlock)
       if (FUSED) {
         v = label_sum(zq, lab_ptr, c);
         if (RP) v2 = label_sum(zr, lab_ptr, c);
-        if (blockIdx.x == 0) {
+        if (blk == 0) {
           s[c] = v;
           if (RP) sr[c] = v2;
         }
@@ -367,8 +376,8 @@ __global__ void __launch_bounds__(kBlock)
       part[0] += v * srow;
     }
   }
-  const int ta = int((int64_t(ntiles) * blockIdx.x) / G);
-  const int tb = int((int64_t(ntiles) * (blockIdx.x + 1)) / G);
+  const int ta = int((int64_t(ntiles) * blk) / G);
+  const int tb = int((int64_t(ntiles) * (blk + 1)) / G);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
     for (int t = ta + threadIdx.x; t < tb; t += kBlock) part[1 + q] += red[q * ntiles + t];
@@ -378,8 +387,18 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int q = 1; q <= NQ; ++q)
       if (int(threadIdx.x) == q) val = part[q];
-    cpart[threadIdx.x * G + blockIdx.x] = val;
+    cpart[threadIdx.x * G + blk] = val;
   }
+}
+
+template <int RP, int FUSED, int NQ>
+__global__ void __launch_bounds__(kBlock)
+    k_coarse(const double* __restrict__ Einv, const double* zq, const double* zr,
+             const int32_t* lab_ptr, double* s, double* sr, double* e, double* er,
+             const double* red, int ntiles, double* cpart, int d, const Scalars* sc,
+             int check_done) {
+  coarse_block<RP, FUSED, NQ>(blockIdx.x, gridDim.x, Einv, zq, zr, lab_ptr, s, sr, e, er, red,
+                              ntiles, cpart, d, sc, check_done);
 }
 
 // Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other)
@@ -428,20 +447,21 @@ __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_p
 // coefficients (kernel timing only).
 // ---------------------------------------------------------------------------------------
 template <typename R, int RP, int CPT, int PAR>
-__global__ void __launch_bounds__(kBlock)
-    k_cg_update(Geo g, const R* __restrict__ v, R* __restrict__ r, R* __restrict__ u,
-                R* __restrict__ p, R* __restrict__ q, R* __restrict__ x,
-                const R* __restrict__ invd, const int32_t* az_ptr, const int32_t* az_cell,
-                const int32_t* az_lab, const int32_t* az_oth, const R* az_t,
-                const double* __restrict__ e, const double* __restrict__ er,
-                const double* cpart, int G, Scalars* sc, int bench) {
+__device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __restrict__ v,
+                                      R* __restrict__ r, R* __restrict__ u, R* __restrict__ p,
+                                      R* __restrict__ q, R* __restrict__ x,
+                                      const R* __restrict__ invd, const int32_t* az_ptr,
+                                      const int32_t* az_cell, const int32_t* az_lab,
+                                      const int32_t* az_oth, const R* az_t,
+                                      const double* __restrict__ e,
+                                      const double* __restrict__ er, const double* cpart, int G,
+                                      Scalars* sc, int bench) {
   using psl::ld;
   using psl::st;
   __shared__ R corr[kTileMax];            // A Z e, rounded to the working precision
   __shared__ R corr2[RP ? kTileMax : 1];  // A Z er
   __shared__ double coef[3];              // alpha, beta, go (1) / stop (0)
   if (sc->done) return;
-  const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = g.tiles[t];
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   // issue the cell loads first so their latency overlaps the reductions below
@@ -483,7 +503,7 @@ __global__ void __launch_bounds__(kBlock)
       const double gamma = s2, delta = s1 - s0, rr = s3;
       const double gprev = sc->gamma[PAR ^ 1], aprev = sc->alpha[PAR ^ 1];
       const int cnt = sc->cnt[PAR ^ 1];
-      const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+      const bool lead = lead_block && threadIdx.x == 0;
       if (!(rr < INFINITY) || !(fabs(gamma) < INFINITY) || !(fabs(delta) < INFINITY)) {
         go = 0.0;
         if (lead) {
@@ -548,6 +568,19 @@ __global__ void __launch_bounds__(kBlock)
     st(r, c, rn);
     st(u, c, rn * dv[k]);
   }
+}
+
+template <typename R, int RP, int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_cg_update(Geo g, const R* __restrict__ v, R* __restrict__ r, R* __restrict__ u,
+                R* __restrict__ p, R* __restrict__ q, R* __restrict__ x,
+                const R* __restrict__ invd, const int32_t* az_ptr, const int32_t* az_cell,
+                const int32_t* az_lab, const int32_t* az_oth, const R* az_t,
+                const double* __restrict__ e, const double* __restrict__ er,
+                const double* cpart, int G, Scalars* sc, int bench) {
+  cg_update_tile<R, RP, CPT, PAR>(tile_of_block(blockIdx.x, g.ntiles), blockIdx.x == 0, g, v, r,
+                                  u, p, q, x, invd, az_ptr, az_cell, az_lab, az_oth, az_t, e, er,
+                                  cpart, G, sc, bench);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1650,4 +1683,457 @@ extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* s
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   PSL_HIP(hipGetLastError());
   return PSL_OK;
+}
+
+// =======================================================================================
+// Batched solve: independent systems, each with its own context, advance together. One
+// launch of each float64 CG kernel covers the tiles of every system through a (system,
+// tile) work list and a per-system argument table; a converged system's workgroups return
+// at once. Chunks of iterations are captured once per batch as a graph and replayed until
+// every system has raised its flag.
+// =======================================================================================
+namespace {
+
+struct SysArgs {
+  Geo g;
+  const double *Tx, *Ty, *Tz, *invd, *Einv, *az_t;
+  const uint8_t* slot;
+  const int32_t *slot_pos, *lab_ptr, *az_ptr, *az_cell, *az_lab, *az_oth;
+  double *zq, *zr, *red, *cpart, *s, *sr, *e, *er;
+  double *xh, *rh, *p, *q, *v, *u;
+  Scalars* sc;
+  int d, G;
+};
+
+struct SysStat {   // per-system snapshot for the host
+  double rr, bnorm2;
+  int32_t done, iters, status, pad;
+};
+
+template <int NS, int CPT>
+__global__ void __launch_bounds__(kBlock)
+    k_b_cg_stencil(const SysArgs* __restrict__ sa, const int2* __restrict__ work, int nwork) {
+  const int2 w = work[tile_of_block(blockIdx.x, nwork)];
+  const SysArgs& A = sa[w.x];
+  cg_stencil_tile<double, NS, 0, CPT>(w.y, A.g, A.Tx, A.Ty, A.Tz, A.rh, A.u, A.v, A.slot,
+                                      A.slot_pos, A.zq, A.zr, A.red, A.sc);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_b_coarse(const SysArgs* __restrict__ sa, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const SysArgs& A = sa[w.x];
+  coarse_block<0, 1, kCgQ>(w.y, A.G, A.Einv, A.zq, A.zr, A.lab_ptr, A.s, A.sr, A.e, A.er,
+                           A.red, A.g.ntiles, A.cpart, A.d, A.sc, 1);
+}
+
+template <int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_b_cg_update(const SysArgs* __restrict__ sa, const int2* __restrict__ work, int nwork) {
+  const int2 w = work[tile_of_block(blockIdx.x, nwork)];
+  const SysArgs& A = sa[w.x];
+  cg_update_tile<double, 0, CPT, PAR>(w.y, w.y == 0, A.g, A.v, A.rh, A.u, A.p, A.q, A.xh,
+                                      A.invd, A.az_ptr, A.az_cell, A.az_lab, A.az_oth, A.az_t,
+                                      A.e, A.er, A.cpart, A.G, A.sc, 0);
+}
+
+__global__ void k_b_gather(const SysArgs* __restrict__ sa, int nsys, SysStat* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsys) return;
+  const Scalars* sc = sa[i].sc;
+  SysStat v;
+  v.rr = sc->rr;
+  v.bnorm2 = sc->bnorm2;
+  v.done = sc->done;
+  v.iters = sc->iters;
+  v.status = sc->status;
+  v.pad = 0;
+  out[i] = v;
+}
+
+__global__ void k_set_done(Scalars* sc) { sc->done = 1; }
+
+}  // namespace
+
+namespace psl {
+
+struct BatchPlan {
+  std::vector<uint64_t> ids;          // contexts the plan was built for, in order
+  int nsys = 0, nwork = 0, ncwork = 0, ns_max = 1, cpt_max = 1;
+  void* mem = nullptr;                // pool block: argument table, work lists, stats
+  SysArgs* args = nullptr;
+  int2* work_all = nullptr;           // [nwork_all] (system, tile) of every system
+  int2* cwork_all = nullptr;          // [ncwork_all] (system, coarse workgroup)
+  int2* work_act = nullptr;           // compacted lists of the systems still iterating
+  int2* cwork_act = nullptr;
+  int2* work = nullptr;               // lists the launches use (all or compacted)
+  int2* cwork = nullptr;
+  int nwork_all = 0, ncwork_all = 0;
+  std::vector<int2> h_work, h_cwork;  // host copies of the full lists
+  SysStat* stat = nullptr;            // [nsys]
+  SysStat* h_stat = nullptr;          // pinned mirror
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0, graph_nwork = 0;
+  const int2* graph_list = nullptr;
+  int last_iters = 0;                 // iterations the last batched solve needed
+};
+
+void destroy_batch_plan(BatchPlan* p) {
+  if (!p) return;
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  psl_internal_free(p->mem);
+  if (p->h_stat) (void)hipHostFree(p->h_stat);
+  delete p;
+}
+
+}  // namespace psl
+
+namespace {
+
+int build_plan(psl_ctx* const* ctxs, int nsys, hipStream_t st, psl::BatchPlan** out) {
+  auto* P = new psl::BatchPlan();
+  P->nsys = nsys;
+  std::vector<SysArgs> args(nsys);
+  std::vector<int2> work, cwork;
+  for (int i = 0; i < nsys; ++i) {
+    psl_ctx* c = ctxs[i];
+    P->ids.push_back(c->id);
+    const int rc = ensure_vecs<double>(c);
+    if (rc != PSL_OK) {
+      psl::destroy_batch_plan(P);
+      return rc;
+    }
+    SysArgs& a = args[i];
+    a.g = geo(c);
+    a.Tx = c->Tx;
+    a.Ty = c->Ty;
+    a.Tz = c->Tz;
+    a.invd = c->invdiag;
+    a.Einv = c->Einv;
+    a.az_t = c->az_t;
+    a.slot = c->slot;
+    a.slot_pos = c->slot_pos;
+    a.lab_ptr = c->lab_ptr;
+    a.az_ptr = c->az_ptr;
+    a.az_cell = c->az_cell;
+    a.az_lab = c->az_lab;
+    a.az_oth = c->az_oth;
+    a.zq = c->zq;
+    a.zr = c->zr;
+    a.red = c->red;
+    a.cpart = c->cpart;
+    a.s = c->s;
+    a.sr = c->sr;
+    a.e = c->e;
+    a.er = c->er;
+    a.xh = c->v64.xh;
+    a.rh = c->v64.rh;
+    a.p = c->v64.p;
+    a.q = c->v64.q;
+    a.v = c->v64.v;
+    a.u = c->v64.u;
+    a.sc = c->sc;
+    a.d = c->d;
+    a.G = c->coarse_blocks;
+    for (int t = 0; t < c->ntiles; ++t) work.push_back(int2{i, t});
+    for (int gb = 0; gb < c->coarse_blocks; ++gb) cwork.push_back(int2{i, gb});
+    P->ns_max = std::max(P->ns_max, c->nslot_max);
+    P->cpt_max = std::max(P->cpt_max, c->cpt);
+  }
+  P->nwork = P->nwork_all = int(work.size());
+  P->ncwork = P->ncwork_all = int(cwork.size());
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t o_args = 0;
+  const size_t o_work = up(sizeof(SysArgs) * nsys);
+  const size_t o_cwork = o_work + up(sizeof(int2) * work.size());
+  const size_t o_work_act = o_cwork + up(sizeof(int2) * cwork.size());
+  const size_t o_cwork_act = o_work_act + up(sizeof(int2) * work.size());
+  const size_t o_stat = o_cwork_act + up(sizeof(int2) * cwork.size());
+  const size_t bytes = o_stat + sizeof(SysStat) * nsys;
+  if (psl_internal_alloc(&P->mem, bytes) != PSL_OK ||
+      hipHostMalloc(reinterpret_cast<void**>(&P->h_stat), sizeof(SysStat) * nsys) != hipSuccess) {
+    psl::destroy_batch_plan(P);
+    return PSL_ENOMEM;
+  }
+  char* base = static_cast<char*>(P->mem);
+  P->args = reinterpret_cast<SysArgs*>(base + o_args);
+  P->work = P->work_all = reinterpret_cast<int2*>(base + o_work);
+  P->cwork = P->cwork_all = reinterpret_cast<int2*>(base + o_cwork);
+  P->work_act = reinterpret_cast<int2*>(base + o_work_act);
+  P->cwork_act = reinterpret_cast<int2*>(base + o_cwork_act);
+  P->stat = reinterpret_cast<SysStat*>(base + o_stat);
+  P->h_work = work;
+  P->h_cwork = cwork;
+  if (hipMemcpyAsync(P->args, args.data(), sizeof(SysArgs) * nsys, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(P->work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice,
+                     st) ||
+      hipMemcpyAsync(P->cwork, cwork.data(), sizeof(int2) * cwork.size(), hipMemcpyHostToDevice,
+                     st) ||
+      hipStreamSynchronize(st)) {
+    psl::destroy_batch_plan(P);
+    return PSL_EHIP;
+  }
+  *out = P;
+  return PSL_OK;
+}
+
+template <int NS>
+struct BStencilL {
+  template <int CPT>
+  struct F {
+    static void run(const psl::BatchPlan* P, hipStream_t st) {
+      hipLaunchKernelGGL((k_b_cg_stencil<NS, CPT>), dim3(P->nwork), dim3(kBlock), 0, st, P->args,
+                         P->work, P->nwork);
+    }
+  };
+  static void run(const psl::BatchPlan* P, hipStream_t st) {
+    with_cpt<F>(P->cpt_max, P, st);
+  }
+};
+
+template <int PAR>
+struct BUpdateC {
+  template <int CPT>
+  struct F {
+    static void run(const psl::BatchPlan* P, hipStream_t st) {
+      hipLaunchKernelGGL((k_b_cg_update<CPT, PAR>), dim3(P->nwork), dim3(kBlock), 0, st, P->args,
+                         P->work, P->nwork);
+    }
+  };
+};
+
+template <int PAR>
+void enqueue_b_iteration(const psl::BatchPlan* P, hipStream_t st) {
+  with_ns<BStencilL>(P->ns_max, P, st);
+  hipLaunchKernelGGL(k_b_coarse, dim3(P->ncwork), dim3(kBlock), 0, st, P->args, P->cwork);
+  with_cpt<BUpdateC<PAR>::template F>(P->cpt_max, P, st);
+}
+
+// Launch only the systems still iterating: compacted (system, tile) and coarse lists.
+int compact_work(psl::BatchPlan* P, const std::vector<char>& live, hipStream_t st) {
+  std::vector<int2> w, cw;
+  for (const int2& v : P->h_work)
+    if (live[v.x]) w.push_back(v);
+  for (const int2& v : P->h_cwork)
+    if (live[v.x]) cw.push_back(v);
+  if (w.empty()) return PSL_OK;
+  PSL_HIP(hipMemcpyAsync(P->work_act, w.data(), sizeof(int2) * w.size(), hipMemcpyHostToDevice, st));
+  PSL_HIP(hipMemcpyAsync(P->cwork_act, cw.data(), sizeof(int2) * cw.size(), hipMemcpyHostToDevice,
+                         st));
+  PSL_HIP(hipStreamSynchronize(st));   // the host vectors go out of scope
+  P->work = P->work_act;
+  P->cwork = P->cwork_act;
+  P->nwork = int(w.size());
+  P->ncwork = int(cw.size());
+  return PSL_OK;
+}
+
+int run_b_chunk(psl::BatchPlan* P, int chunk, hipStream_t st) {
+  if (!P->graph || P->graph_chunk != chunk || P->graph_nwork != P->nwork ||
+      P->graph_list != P->work) {
+    if (P->graph) {
+      (void)hipGraphExecDestroy(P->graph);
+      P->graph = nullptr;
+    }
+    hipStream_t cap = psl_internal_capture_stream();
+    if (!cap) return PSL_EHIP;
+    hipGraph_t graph;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PSL_EHIP;
+    for (int i = 0; i < chunk; i += 2) {
+      enqueue_b_iteration<0>(P, cap);
+      enqueue_b_iteration<1>(P, cap);
+    }
+    const hipError_t e1 = hipStreamEndCapture(cap, &graph);
+    if (e1 != hipSuccess) return PSL_EHIP;
+    const hipError_t e2 = hipGraphInstantiate(&P->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      P->graph = nullptr;
+      return PSL_EHIP;
+    }
+    P->graph_chunk = chunk;
+    P->graph_nwork = P->nwork;
+    P->graph_list = P->work;
+  }
+  PSL_HIP(hipGraphLaunch(P->graph, st));
+  return PSL_OK;
+}
+
+int gather(psl::BatchPlan* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_b_gather, dim3((P->nsys + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                     P->args, P->nsys, P->stat);
+  PSL_HIP(hipMemcpyAsync(P->h_stat, P->stat, sizeof(SysStat) * P->nsys, hipMemcpyDeviceToHost, st));
+  PSL_HIP(hipStreamSynchronize(st));
+  return PSL_OK;
+}
+
+}  // namespace
+
+extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const double* const* b,
+                                 double* const* x, const psl_solve_opts* o_in,
+                                 psl_solve_stats* st_out, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
+  if (!ctxs || !b || !x || nsys < 1) return PSL_EINVAL;
+  psl_solve_opts o;
+  psl_default_opts(&o);
+  if (o_in) o = *o_in;
+  if (!(o.tol > 0.0) || o.maxit < 0 || o.check_every < 1 || o.check_every > 4096) return PSL_EINVAL;
+  if (o.mode != PSL_FP64) return PSL_ENOTSUP;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (int i = 0; i < nsys; ++i) {
+    if (!ctxs[i] || !b[i] || !x[i]) return PSL_EINVAL;
+    if (ctxs[i]->dev != dev) return PSL_EINVAL;
+    if (!ctxs[i]->coarse_fused) return PSL_ENOTSUP;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return PSL_EINVAL;   // a context holds one system's state
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // launch plan, cached on the first context while the batch is the same
+  psl_ctx* c0 = ctxs[0];
+  bool same = c0->plan && c0->plan->nsys == nsys;
+  for (int i = 0; same && i < nsys; ++i) same = c0->plan->ids[i] == ctxs[i]->id;
+  if (!same) {
+    psl::destroy_batch_plan(c0->plan);
+    c0->plan = nullptr;
+    const int rc = build_plan(ctxs, nsys, st, &c0->plan);
+    if (rc != PSL_OK) return rc;
+  }
+  psl::BatchPlan* P = c0->plan;
+  P->work = P->work_all;
+  P->cwork = P->cwork_all;
+  P->nwork = P->nwork_all;
+  P->ncwork = P->ncwork_all;
+  std::vector<psl_solve_stats> stats(nsys);
+  std::vector<int> active(nsys, 0);
+  std::vector<double> bnorm(nsys, 0.0), rnorm(nsys, 0.0);
+  for (auto& s : stats) std::memset(&s, 0, sizeof(s));
+  int rc;
+  // prologue of every system: ||b||, x0, first refinement step (no host round trip)
+  for (int i = 0; i < nsys; ++i) {
+    psl_ctx* c = ctxs[i];
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, c->sc);
+    hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), b[i], red(c, 1));
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles,
+                       &c->sc->bnorm2);
+    if (!o.use_x0)
+      hipLaunchKernelGGL(k_zero, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, x[i], int(c->n));
+    enqueue_outer_step(c, b[i], x[i], st);
+  }
+  if ((rc = gather(P, st)) != PSL_OK) return rc;
+  for (int i = 0; i < nsys; ++i) {
+    psl_ctx* c = ctxs[i];
+    bnorm[i] = std::sqrt(P->h_stat[i].bnorm2);
+    rnorm[i] = std::sqrt(P->h_stat[i].rr);
+    stats[i].bnorm = bnorm[i];
+    if (!std::isfinite(bnorm[i]) || !std::isfinite(rnorm[i])) {
+      stats[i].status = PSL_ENONFINITE;
+    } else if (bnorm[i] == 0.0) {
+      hipLaunchKernelGGL(k_zero, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, x[i], int(c->n));
+      stats[i].status = PSL_OK;
+    } else if (rnorm[i] <= o.tol * bnorm[i]) {
+      stats[i].status = PSL_OK;
+    } else {
+      active[i] = 1;
+      const double goal = o.tol * bnorm[i] / rnorm[i];
+      hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, o.maxit);
+      hipLaunchKernelGGL(k_cg_init<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                         int(c->n), c->r64, c->invdiag, c->v64.rh, c->v64.u, c->v64.xh,
+                         c->v64.p, c->v64.q, c->sc);
+      continue;
+    }
+    hipLaunchKernelGGL(k_set_done, dim3(1), dim3(1), 0, st, c->sc);
+  }
+  // batched iterations until every system has raised its flag
+  const int chunk = o.check_every + (o.check_every & 1);
+  int batches = std::max(1, (3 * P->last_iters / 4) / chunk);
+  std::vector<double> best(nsys, INFINITY);
+  std::vector<int> best_it(nsys, 0), stalled(nsys, 0);
+  int max_iters = 0;
+  for (int any = std::count(active.begin(), active.end(), 1); any > 0;) {
+    for (int k = 0; k < batches; ++k)
+      if ((rc = run_b_chunk(P, chunk, st)) != PSL_OK) return rc;
+    batches = 1;
+    if ((rc = gather(P, st)) != PSL_OK) return rc;
+    any = 0;
+    std::vector<char> live(nsys, 0);
+    int64_t live_tiles = 0;
+    for (int i = 0; i < nsys; ++i) {
+      if (!active[i] || P->h_stat[i].done) continue;
+      const SysStat& s = P->h_stat[i];
+      if (s.rr < 0.25 * best[i]) {
+        best[i] = s.rr;
+        best_it[i] = s.iters;
+      } else if (s.iters - best_it[i] >= kStallWindow) {
+        stalled[i] = 1;   // handed to the single-system path below
+        hipLaunchKernelGGL(k_set_done, dim3(1), dim3(1), 0, st, ctxs[i]->sc);
+        continue;
+      }
+      ++any;
+      live[i] = 1;
+      live_tiles += ctxs[i]->ntiles;
+    }
+    // once most launched workgroups would only find their system finished, launch fewer
+    if (any > 0 && live_tiles < int64_t(P->nwork) * 3 / 5)
+      if ((rc = compact_work(P, live, st)) != PSL_OK) return rc;
+  }
+  // epilogue: x += ||r|| xhat, projection, check
+  for (int i = 0; i < nsys; ++i) {
+    if (!active[i]) continue;
+    psl_ctx* c = ctxs[i];
+    stats[i].iters = P->h_stat[i].iters;
+    max_iters = std::max(max_iters, stats[i].iters);
+    hipLaunchKernelGGL(k_accumulate<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                       int(c->n), x[i], c->v64.xh, c->sc);
+    enqueue_outer_step(c, b[i], x[i], st);
+  }
+  P->last_iters = max_iters;
+  std::vector<int> inner_status(nsys);
+  for (int i = 0; i < nsys; ++i) inner_status[i] = P->h_stat[i].status;
+  if ((rc = gather(P, st)) != PSL_OK) return rc;
+  for (int i = 0; i < nsys; ++i) {
+    if (!active[i]) continue;
+    stats[i].outer = 1;
+    const double rn = std::sqrt(P->h_stat[i].rr);
+    if (rn <= o.tol * bnorm[i]) {
+      stats[i].status = PSL_OK;
+      continue;
+    }
+    if (inner_status[i] == PSL_ENONFINITE || !std::isfinite(rn)) {
+      stats[i].status = PSL_ENONFINITE;
+      continue;
+    }
+    if (stats[i].iters >= o.maxit) {
+      stats[i].status = PSL_EMAXIT;
+      continue;
+    }
+    // stall, breakdown or a residual just above the tolerance: finish on the
+    // single-system path from the current x
+    psl_solve_opts o1 = o;
+    o1.use_x0 = 1;
+    o1.maxit = o.maxit - stats[i].iters;
+    psl_solve_stats s1;
+    const int r1 = psl_solve(ctxs[i], b[i], x[i], &o1, &s1, stream);
+    if (r1 == PSL_EINVAL || r1 == PSL_EHIP || r1 == PSL_ENOMEM) return r1;
+    stats[i].status = r1;
+    stats[i].iters += s1.iters;
+    stats[i].outer += s1.outer;
+  }
+  // float64 residual of every returned x
+  for (int i = 0; i < nsys; ++i) {
+    psl_ctx* c = ctxs[i];
+    launch_stencil<double, 1>(c, x[i], b[i], c->t64, st);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
+  }
+  if ((rc = gather(P, st)) != PSL_OK) return rc;
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int overall = PSL_OK;
+  for (int i = 0; i < nsys; ++i) {
+    stats[i].relres_true = bnorm[i] > 0.0 ? std::sqrt(P->h_stat[i].rr) / bnorm[i] : 0.0;
+    stats[i].t_solve_s = wall;
+    if (overall == PSL_OK && stats[i].status != PSL_OK) overall = stats[i].status;
+    if (st_out) st_out[i] = stats[i];
+  }
+  return overall;
 }

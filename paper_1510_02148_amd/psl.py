@@ -38,6 +38,10 @@ class psl_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
 
 
+class psl_setup_opts(ctypes.Structure):
+    _fields_ = [("tile_cells", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 class psl_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("max_outer", ctypes.c_int32),
@@ -79,8 +83,15 @@ _build_z = _sig("psl_build_Z", ctypes.c_int,
                 [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
 _setup_e = _sig("psl_setup_E", ctypes.c_int,
                 [ctypes.POINTER(_P), ctypes.POINTER(psl_grid), _P, _P, _P, _P, _I32, _I32P, _P])
+_setup_e_ex = _sig("psl_setup_E_ex", ctypes.c_int,
+                   [ctypes.POINTER(_P), ctypes.POINTER(psl_grid), _P, _P, _P, _P, _I32, _I32P,
+                    ctypes.POINTER(psl_setup_opts), _P])
+_default_setup_opts = _sig("psl_default_setup_opts", None, [ctypes.POINTER(psl_setup_opts)])
 _solve = _sig("psl_solve", ctypes.c_int,
               [_P, _P, _P, ctypes.POINTER(psl_solve_opts), ctypes.POINTER(psl_solve_stats), _P])
+_solve_batched = _sig("psl_solve_batched", ctypes.c_int,
+                      [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                       ctypes.POINTER(psl_solve_opts), ctypes.POINTER(psl_solve_stats), _P])
 _apply_a = _sig("psl_apply_A", ctypes.c_int, [_P, _P, _P, _P])
 _deflate = _sig("psl_deflate", ctypes.c_int, [_P, _P, _P, _P, _P])
 _get_coarse = _sig("psl_get_coarse", ctypes.c_int, [_P, _P, _P, _I32P, _P])
@@ -91,7 +102,9 @@ _bench_copy = _sig("psl_bench_copy", ctypes.c_int, [_P, _P, ctypes.c_int64, _P])
 _status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
 _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
 
-EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_setup_E", "psl_solve", "psl_apply_A",
+EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_setup_E", "psl_setup_E_ex",
+            "psl_default_setup_opts", "psl_solve",
+            "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
             "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info")
 KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL = range(5)
@@ -200,17 +213,25 @@ class Context:
 
 
 def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
-                labels: torch.Tensor, d: int, nsub=None) -> Context:
+                labels: torch.Tensor, d: int, nsub=None, tile_cells: Optional[int] = None
+                ) -> Context:
+    """psl_setup_E, or psl_setup_E_ex when a tile size is given."""
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
     fx, fy, fz = face_counts(grid)
     g = _grid(grid)
     out = ctypes.c_void_p(0)
     ns = (ctypes.c_int32 * 3)(*[int(v) for v in nsub]) if nsub is not None else None
-    _check(_setup_e(ctypes.byref(out), ctypes.byref(g), _dev(Tx, torch.float64, fx, "Tx"),
-                    _dev(Ty, torch.float64, fy, "Ty"), _dev(Tz, torch.float64, fz, "Tz"),
-                    _dev(labels, torch.int32, n, "labels"), int(d),
-                    ns if ns is not None else ctypes.cast(None, _I32P), _stream()),
-           "psl_setup_E")
+    args = (ctypes.byref(out), ctypes.byref(g), _dev(Tx, torch.float64, fx, "Tx"),
+            _dev(Ty, torch.float64, fy, "Ty"), _dev(Tz, torch.float64, fz, "Tz"),
+            _dev(labels, torch.int32, n, "labels"), int(d),
+            ns if ns is not None else ctypes.cast(None, _I32P))
+    if tile_cells is None:
+        _check(_setup_e(*args, _stream()), "psl_setup_E")
+    else:
+        so = psl_setup_opts()
+        _default_setup_opts(ctypes.byref(so))
+        so.tile_cells = int(tile_cells)
+        _check(_setup_e_ex(*args, ctypes.byref(so), _stream()), "psl_setup_E_ex")
     return Context(out.value, grid, int(d))
 
 
@@ -256,6 +277,41 @@ def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *
     stats = st.as_dict()
     stats["status_str"] = psl_status_str(rc)
     return x, stats
+
+
+def psl_solve_batched(ctxs, bs, xs=None, *, tol: Optional[float] = None,
+                      maxit: Optional[int] = None, use_x0: bool = False,
+                      check_every: Optional[int] = None, check: bool = False):
+    """Solve independent systems A_i x_i = b_i together (float64 CG, one launch per kernel
+    for all systems). Returns (xs, [stats dict per system], overall status)."""
+    n = len(ctxs)
+    if n < 1 or len(bs) != n or (xs is not None and len(xs) != n):
+        raise ValueError("need one b (and x) per context")
+    o = default_opts()
+    if tol is not None:
+        o.tol = tol
+    if maxit is not None:
+        o.maxit = maxit
+    o.use_x0 = 1 if use_x0 else 0
+    if check_every is not None:
+        o.check_every = check_every
+    if xs is None:
+        if use_x0:
+            raise ValueError("use_x0 needs xs")
+        xs = [torch.empty_like(b) for b in bs]
+    handles = (_P * n)(*[c.handle.value for c in ctxs])
+    bp = (_P * n)(*[_dev(b, torch.float64, c.n, "b") for b, c in zip(bs, ctxs)])
+    xp = (_P * n)(*[_dev(x, torch.float64, c.n, "x") for x, c in zip(xs, ctxs)])
+    st = (psl_solve_stats * n)()
+    rc = _solve_batched(handles, n, bp, xp, ctypes.byref(o), st, _stream())
+    if check:
+        _check(rc, "psl_solve_batched")
+    stats = []
+    for i in range(n):
+        d = st[i].as_dict()
+        d["status_str"] = psl_status_str(d["status"])
+        stats.append(d)
+    return xs, stats, rc
 
 
 def psl_apply_A(ctx: Context, p: torch.Tensor, q: Optional[torch.Tensor] = None) -> torch.Tensor:

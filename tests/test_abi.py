@@ -22,8 +22,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ("psl_build_Z", "psl_setup_E", "psl_solve", "psl_assemble_tpfa", "psl_destroy",
-                 "psl_status_str"):
+    for must in ("psl_build_Z", "psl_setup_E", "psl_solve", "psl_solve_batched",
+                 "psl_assemble_tpfa", "psl_destroy", "psl_status_str"):
         assert must in names
 
 
@@ -51,10 +51,11 @@ def test_binding_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
         " sizeof(psl_solve_stats), offsetof(psl_solve_opts, tau_inner),"
         " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_opts, mixed_floor),"
-        " offsetof(psl_solve_stats, relres_true), sizeof(psl_grid));return 0;}\n")
+        " offsetof(psl_solve_stats, relres_true), sizeof(psl_grid), sizeof(psl_setup_opts));"
+        "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -63,7 +64,7 @@ def test_binding_struct_layout_matches_c(tmp_path):
     want = [ctypes.sizeof(psl.psl_solve_opts), ctypes.sizeof(psl.psl_solve_stats),
             psl.psl_solve_opts.tau_inner.offset, psl.psl_solve_opts.check_every.offset,
             psl.psl_solve_opts.mixed_floor.offset, psl.psl_solve_stats.relres_true.offset,
-            ctypes.sizeof(psl.psl_grid)]
+            ctypes.sizeof(psl.psl_grid), ctypes.sizeof(psl.psl_setup_opts)]
     assert got == want
 
 
@@ -90,3 +91,12 @@ def test_invalid_arguments_rejected_before_any_device_work(lib):
                       ctypes.c_void_p(16), ctypes.byref(d), None)
     assert rc == psl.EINVAL
     assert psl._solve(None, None, None, None, None, None) == psl.EINVAL
+
+
+def test_batched_rejects_bad_arguments_without_device_work(lib):
+    from paper_1510_02148_amd import psl
+    st = (psl.psl_solve_stats * 1)()
+    assert psl._solve_batched(None, 1, None, None, None, st, None) == psl.EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert psl._solve_batched(arr, 0, arr, arr, None, st, None) == psl.EINVAL
+    assert psl._solve_batched(arr, 1, arr, arr, None, st, None) == psl.EINVAL
