@@ -143,11 +143,14 @@ def init_params(arch: Arch = Arch(), seed: int = 0) -> Dict[str, np.ndarray]:
 
 
 def forward(params: Dict[str, np.ndarray], x: np.ndarray, arch: Arch = Arch(),
-            bf16: bool = False) -> Tuple[np.ndarray, dict]:
+            bf16: bool = False, store_bf16: bool = False) -> Tuple[np.ndarray, dict]:
     """Network output y (nz, ny, nx, 1) and the activations the backward pass needs.
     bf16=True rounds every convolution's weight and input to bfloat16 (the GPU operands);
-    sums stay in float64 here."""
+    sums stay in float64 here. store_bf16=True also keeps every hidden activation as
+    bfloat16 (each convolution output and each pooled field rounded when stored), the
+    storage precision of the GPU network; the output layer stays unrounded."""
     rd = bf16_round if bf16 else (lambda a: a)
+    st = bf16_round if store_bf16 else (lambda a: a)
     nl = len(arch.widths)
     cache = {"in": {}, "out": {}}
 
@@ -157,6 +160,8 @@ def forward(params: Dict[str, np.ndarray], x: np.ndarray, arch: Arch = Arch(),
         cache["in"][name] = xi
         o = conv3d(xi, w, params[name + ".b"])
         o = relu(o) if act else o
+        if act:
+            o = st(o)
         cache["out"][name] = o
         return o
 
@@ -164,7 +169,7 @@ def forward(params: Dict[str, np.ndarray], x: np.ndarray, arch: Arch = Arch(),
     skips = []
     for i in range(nl):
         if i > 0:
-            h = pool2(h)
+            h = st(pool2(h))
         h = conv(f"e{i}a", h)
         h = conv(f"e{i}b", h)
         skips.append(h)
@@ -215,18 +220,51 @@ def backward(params: Dict[str, np.ndarray], cache: dict, gy: np.ndarray,
 # ---------------------------------------------------------------------------------------
 # energy loss of the projected start-vector error, scale-free in y
 # ---------------------------------------------------------------------------------------
-def energy_loss(y: np.ndarray, P1b: np.ndarray, P1A, c: float) -> Tuple[float, np.ndarray, float]:
-    """For x0 = alpha y with the best alpha, the squared A-norm of P2 (x0 - x*) relative
-    to that of P2 x*:  L = 1 - (y, P1 b)^2 / ((y, P1 A y) c),  c = (x*, P1 b).
-    (P1 A = A P2 is symmetric and P2^T A P2 = P1 A, so ||P2 e||_A^2 = (e, P1 A e).)
-    Returns L, dL/dy and alpha = (y, P1 b) / (y, P1 A y). P1A is a callable v -> P1 A v."""
+def energy_loss(y: np.ndarray, P1b: np.ndarray, P1A, c: float, sigma: float = 0.0
+                ) -> Tuple[float, np.ndarray, float]:
+    """Energy-norm error of the projected start vector, relative to ||P2 x*||_A^2 = c with
+    c = (x*, P1 b). (P1 A = A P2 is symmetric and P2^T A P2 = P1 A, so ||P2 e||_A^2 =
+    (e, P1 A e); with A x* = b, P1 A x* = P1 b.) With u = (y, P1 b), v = (y, P1 A y):
+      sigma > 0: regression of y on the scaled solution t = x* / sigma,
+        L = ||P2 (y - t)||_A^2 / ||P2 t||_A^2 = (sigma^2 v - 2 sigma u + c) / c,
+        dL/dy = 2 (sigma^2 P1 A y - sigma P1 b) / c;
+      sigma = 0: the same error for the best multiple alpha y,
+        L = 1 - u^2 / (v c),  dL/dy = (2u / (v c)) ((u / v) P1 A y - P1 b).
+    Returns L, dL/dy and the best scale alpha = u / v (0, the zero start, when v = 0).
+    P1A is a callable v -> P1 A v."""
     yv = y.reshape(-1)
     u = float(yv @ P1b)
     Ay = P1A(yv)
     v = float(yv @ Ay)
-    L = 1.0 - u * u / (v * c)
-    grad = (2.0 * u / (v * c)) * ((u / v) * Ay - P1b)
-    return L, grad.reshape(y.shape), u / v
+    if sigma > 0.0:
+        L = (sigma * sigma * v - 2.0 * sigma * u + c) / c
+        grad = (2.0 / c) * (sigma * sigma * Ay - sigma * P1b)
+    elif v > 0.0:
+        L = 1.0 - u * u / (v * c)
+        grad = (2.0 * u / (v * c)) * ((u / v) * Ay - P1b)
+    else:                       # no direction: the zero start
+        L, grad = 1.0, np.zeros_like(yv)
+    return L, grad.reshape(y.shape), (u / v if v > 0.0 else 0.0)
+
+
+def weighted_l2_loss(y: np.ndarray, t: np.ndarray, d: np.ndarray) -> Tuple[float, np.ndarray]:
+    """Training regression of the output y on the target t with cell weights d > 0:
+    L = sum d (y - t)^2 / sum d t^2, dL/dy = 2 d (y - t) / sum d t^2 (all cells)."""
+    yv, tv, dv = y.reshape(-1), t.reshape(-1), d.reshape(-1)
+    den = float(np.sum(dv * tv * tv))
+    e = yv - tv
+    return float(np.sum(dv * e * e)) / den, (2.0 * dv * e / den).reshape(y.shape)
+
+
+def cell_diag(Tx: np.ndarray, Ty: np.ndarray, Tz: np.ndarray, grid) -> np.ndarray:
+    """diag(A) of the two-point flux matrix: the sum of the six face transmissibilities
+    of each cell (face arrays in the (nx+1) ny nz, nx (ny+1) nz, nx ny (nz+1) layouts)."""
+    nx, ny, nz = grid
+    tx = Tx.reshape(nz, ny, nx + 1)
+    ty = Ty.reshape(nz, ny + 1, nx)
+    tz = Tz.reshape(nz + 1, ny, nx)
+    d = tx[:, :, :-1] + tx[:, :, 1:] + ty[:, :-1, :] + ty[:, 1:, :] + tz[:-1] + tz[1:]
+    return d.reshape(-1)
 
 
 # ---------------------------------------------------------------------------------------

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
-SOURCES = ["psl_setup.hip", "psl_solve.hip"]
+SOURCES = ["psl_setup.hip", "psl_solve.hip", "psl_nn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -14,7 +14,8 @@ LIB = os.path.join(ROOT, "paper_1510_02148_amd", "libpsl.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    import glob
+    src = "\n".join(open(h).read() for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(psl_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))

@@ -26,9 +26,15 @@ MUTANTS = {
     "relu_backward_uses_input_sign": ("return np.where(y > 0.0, gy, 0.0)", "return np.where(y >= 0.0, gy, 0.0)"),
     "skip_gradient_dropped": ("            g = g + gskip[i]", "            g = g"),
     "decoder_split_swapped": ("gskip[i] = gcat[..., cup:]", "gskip[i] = gcat[..., :gcat.shape[3] - cup]"),
-    "loss_alpha_missing": ("    L = 1.0 - u * u / (v * c)", "    L = 1.0 - u / c"),
+    "loss_alpha_missing": ("        L = 1.0 - u * u / (v * c)", "        L = 1.0 - u / c"),
+    "regression_cross_term_sign": ("L = (sigma * sigma * v - 2.0 * sigma * u + c) / c",
+                                   "L = (sigma * sigma * v + 2.0 * sigma * u + c) / c"),
+    "regression_grad_scale": ("grad = (2.0 / c) * (sigma * sigma * Ay - sigma * P1b)",
+                              "grad = (2.0 / c) * (sigma * Ay - sigma * P1b)"),
     "loss_grad_sign": ("grad = (2.0 * u / (v * c)) * ((u / v) * Ay - P1b)",
                        "grad = (2.0 * u / (v * c)) * (P1b - (u / v) * Ay)"),
+    "wl2_unweighted_denominator": ("den = float(np.sum(dv * tv * tv))", "den = float(np.sum(tv * tv))"),
+    "diag_missing_z_faces": ("+ tz[:-1] + tz[1:]", ""),
     "adam_no_bias_correction": ("    mh = m / (1.0 - b1 ** t)", "    mh = m"),
     "input_not_standardised": ("lk = (lk - lk.mean()) / max(lk.std(), 1e-12)", "lk = lk - lk.mean()"),
 }

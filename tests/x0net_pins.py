@@ -142,6 +142,21 @@ def pin_energy_loss_closed_form_and_gradient(N):
         d = np.zeros_like(y); d[idx] = 1e-6
         fd = (N.energy_loss(y + d, P1b, P1A, c)[0] - N.energy_loss(y - d, P1b, P1A, c)[0]) / 2e-6
         assert np.isclose(gL[idx], fd, rtol=1e-5, atol=1e-10)
+    # fixed-scale regression on t = x* / sigma: definition, zero at t, differences
+    sigma = 3.0
+    Ls, gs, _ = N.energy_loss(y, P1b, P1A, c, sigma=sigma)
+    t = xs / sigma
+    e = P2 @ (y.reshape(-1) - t)
+    assert np.isclose(Ls, (e @ (A @ e)) / ((P2 @ t) @ (A @ (P2 @ t))), rtol=1e-9)
+    assert abs(N.energy_loss(t.reshape(y.shape), P1b, P1A, c, sigma=sigma)[0]) < 1e-10
+    assert np.isclose(N.energy_loss(0 * y, P1b, P1A, c, sigma=sigma)[0], 1.0)
+    assert Ls >= L - 1e-12            # the best multiple is never worse
+    for idx in [(1, 2, 3, 0), (6, 0, 5, 0)]:
+        # the loss is quadratic in y: central differences are exact for any step
+        d = np.zeros_like(y); d[idx] = 1e-2
+        fd = (N.energy_loss(y + d, P1b, P1A, c, sigma=sigma)[0]
+              - N.energy_loss(y - d, P1b, P1A, c, sigma=sigma)[0]) / 2e-2
+        assert np.isclose(gs[idx], fd, rtol=1e-8, atol=1e-12)
 
 
 def pin_adam_first_step_and_convergence(N):
@@ -165,3 +180,20 @@ def pin_make_input_normalisation(N):
     assert abs(x[..., 0].mean()) < 1e-12 and abs(x[..., 0].std() - 1) < 1e-12
     assert np.isclose(np.abs(x[..., 1]).max(), 1.0)
     assert np.array_equal(x[..., 1].reshape(-1), prob.q / np.abs(prob.q).max())
+
+
+def pin_weighted_l2_and_cell_diag(N):
+    prob, A, b, Z = _tiny_system()
+    Tx, Ty, Tz = O.transmissibilities(prob.K, prob.grid, prob.dirichlet_mask)
+    assert np.allclose(N.cell_diag(Tx, Ty, Tz, prob.grid), A.diagonal(), rtol=1e-14)
+    g = rng(21)
+    y, t = g.normal(size=(4, 5, 6, 1)), g.normal(size=(4, 5, 6, 1))
+    d = np.exp(g.normal(size=120))
+    L, gL = N.weighted_l2_loss(y, t, d)
+    assert np.isclose(L, np.sum(d * (y - t).reshape(-1) ** 2) / np.sum(d * t.reshape(-1) ** 2))
+    assert N.weighted_l2_loss(t, t, d)[0] == 0.0
+    assert np.isclose(N.weighted_l2_loss(0 * y, t, d)[0], 1.0)
+    for idx in [(0, 0, 0, 0), (3, 4, 5, 0)]:
+        e = np.zeros_like(y); e[idx] = 1e-2            # quadratic: central differences exact
+        fd = (N.weighted_l2_loss(y + e, t, d)[0] - N.weighted_l2_loss(y - e, t, d)[0]) / 2e-2
+        assert np.isclose(gL[idx], fd, rtol=1e-8)
