@@ -34,7 +34,12 @@ WORKLOADS = {
           "16x16x8 subdomains x 2 levelsets",
     "c4": "batch of 64 layered cubes, side U{32..96} (seed-drawn), contrast log-uniform "
           "1e4..1e6, 4x4x4 subdomains x 2 levelsets, well columns; solved together",
+    "c5": "learned start vector: 128x128x64 layered / channelized instances (contrast "
+          "log-uniform 1e4..1e6, well columns), 8x8x4 subdomains x 2; 4-level bf16 conv net "
+          "(16/32/48/64 channels) trained on plain float64 solutions",
 }
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
 def log(msg):
@@ -214,6 +219,111 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _gen_instance(seed):
+    import psl_inputs as pi
+    return pi.learned_x0_instance(seed)
+
+
+def run_learned(args):
+    """Learned start vector on held-out instances: one step = network inference + scale +
+    float64 solve from that start, against the same solve from x0 = 0. Training (outside
+    the timed region) uses a reduced set of instances and steps."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_1510_02148_amd import nn, x0net, x0train
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ntr, nte = args.train_instances, args.test_instances
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        tr = pool.map(_gen_instance, [1000 + i for i in range(ntr)])
+        te = pool.map(_gen_instance, [5000 + i for i in range(nte)])
+    log(f"generated {ntr} + {nte} instances in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    dtr, dte = x0train.prepare(tr), x0train.prepare(te)
+    log(f"reference solves in {time.perf_counter() - t0:.1f} s")
+    grid = tuple(tr[0].grid)
+    net = x0net.X0Net(grid, seed=args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = x0train.train(net, dtr, args.train_steps, lr=1e-3, log=log, log_every=500,
+                           loss=args.loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training: {args.train_steps} steps in {t_train:.1f} s "
+        f"({t_train / args.train_steps * 1e3:.2f} ms/step), loss {losses[:50].mean():.4f} -> "
+        f"{losses[-50:].mean():.4f}")
+    for _ in range(args.warmup):
+        x0train.evaluate(net, dte[:1])
+    ev = x0train.evaluate(net, dte, repeats=args.steps)
+    t_zero = float(np.mean([r["t_zero"] for r in ev]))
+    t_net = float(np.mean([r["t_net"] for r in ev]))
+    it_zero = float(np.mean([r["iters_zero"] for r in ev]))
+    it_net = float(np.mean([r["iters_net"] for r in ev]))
+    ok = all(r["relres_net"] <= 1e-8 for r in ev)
+    log(f"test: iterations {it_zero:.1f} (x0 = 0) vs {it_net:.1f} (learned), time "
+        f"{t_zero * 1e3:.2f} vs {t_net * 1e3:.2f} ms, start loss "
+        f"{np.mean([r['loss_net'] for r in ev]):.4f}")
+    # dominant convolution: the full-resolution decoder layer (largest forward time)
+    L = net.P["d0"]
+    n0 = net.ns[0]
+    flops = 2.0 * 27 * L["cin"] * L["cout"] * n0
+    stream = torch.cuda.current_stream()
+    nn.conv3(net.grids[0], net.A["cat0"], L["cin"], L["w"], L["cout"], L["pb"], True, net.A["d0"])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        nn.conv3(net.grids[0], net.A["cat0"], L["cin"], L["w"], L["cout"], L["pb"], True,
+                 net.A["d0"])
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / 20
+    tfs = flops / (us * 1e-6) / 1e12
+    e0.record(stream)
+    for _ in range(5):
+        net.forward()
+    e1.record(stream)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 5
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import psl_oracle as O
+        p = te[0]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+            lab, dd = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+            res = O.dpcg(A, bh, O.deflation_matrix(lab, dd), tol=p.tol)
+            cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(cpu_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"test instance 0 solved by the oracle from x0 = 0 ({res.iters} "
+                         f"iterations), 1 thread"}
+    out = {
+        "metric": METRIC, "value": round(t_net, 6), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_net * 1e3, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-net/f64-solve", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"], "grid": list(grid), "train_instances": ntr,
+                   "test_instances": nte, "train_steps": args.train_steps, "loss": args.loss,
+                   "tol": 1e-8, "seed": args.seed},
+        "converged": bool(ok), "iterations_zero_start": it_zero, "iterations_learned": it_net,
+        "time_zero_start_s": t_zero, "speedup_vs_zero_start": round(t_zero / t_net, 3),
+        "start_loss": float(np.mean([r["loss_net"] for r in ev])),
+        "train_s": round(t_train, 2), "train_ms_per_step": round(t_train / args.train_steps * 1e3, 3),
+        "train_loss_first": float(losses[:50].mean()), "train_loss_last": float(losses[-50:].mean()),
+        "inference_ms": round(fwd_ms, 3),
+        "roofline": {"bound": "mfma", "kernel": "conv3 d0 forward (48->16, 1M cells, bf16)",
+                     "achieved": round(tfs, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tfs / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +335,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain float64 comparison")
+    ap.add_argument("--train-instances", type=int, default=128)
+    ap.add_argument("--test-instances", type=int, default=16)
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--loss", default="energy", choices=["energy", "diag", "l2"])
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -239,6 +353,8 @@ def main():
         args.steps, args.warmup, args.no_fp64, args.no_cpu_baseline = 1, 0, True, True
     if args.workload == "c4":
         return run_batched(args)
+    if args.workload == "c5":
+        return run_learned(args)
 
     import numpy as np
     import torch

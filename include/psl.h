@@ -208,10 +208,15 @@ int psl_setup_E_ex(psl_ctx** ctx, const psl_grid* g, const double* Tx, const dou
  * ||rhat|| over 512 iterations) returns to the refinement loop, which restarts it from
  * the new float64 residual; in PSL_MIXED a refinement step that does not halve the
  * float64 residual also switches the remaining steps to float64 CG.
+ * A fresh float64 run of the single-reduction loop that fails to reduce the residual by
+ * 10 % sends the solve back to its best iterate, to finish with the two-reduction loop
+ * and residual replacement; a second such failure ends it.
  * Returns PSL_OK when ||b - A x|| <= tol ||b|| was reached; otherwise PSL_EMAXIT
  * (iteration or refinement cap; x is the projected last iterate), PSL_ESTAGNATION
  * (float64 refinement stopped reducing the residual), PSL_EBREAKDOWN (breakdown on the
- * first iteration of a refinement step) or PSL_ENONFINITE. ||b|| = 0 gives x = 0, PSL_OK.
+ * first iteration of a refinement step) or PSL_ENONFINITE; after these three x is the
+ * projected iterate with the smallest residual seen.
+ * ||b|| = 0 gives x = 0, PSL_OK.
  */
 int psl_solve(psl_ctx* ctx, const double* b, double* x, const psl_solve_opts* o,
               psl_solve_stats* st, void* stream);

@@ -122,6 +122,7 @@ struct psl_ctx {
   double* er = nullptr;               // [d] E^-1 Z^T rhat
   double* r64 = nullptr;              // [n] FP64 outer residual
   double* t64 = nullptr;              // [n] FP64 scratch
+  double* xbest = nullptr;            // [n] best projected iterate of the current solve
   psl::Scalars* sc = nullptr;
   psl::Scalars* h_sc = nullptr;       // pinned host mirror
   psl::VecSet<double> v64;

@@ -1536,13 +1536,24 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   double inner_reached = 0.0;   // recursive float32 residual norm the last run ended at
   int widen_direction = 0;      // next float64 run continues the float32 direction
   int last_fresh64 = 0;         // the last inner run was a fresh float64 run that did not stall
-  const int form64 = kFormSingle;   // float64: single-reduction recurrences
-  const int form32 = kFormTwo;      // float32: two-reduction loop with residual replacement
+  int form64 = kFormSingle;     // float64: single-reduction recurrences, until they stagnate
+  const int form32 = kFormTwo;  // float32: two-reduction loop with residual replacement
+  int keep64 = 0;               // float64 two-reduction runs keep their direction
+  double scale64 = 1.0;
+  // the best projected iterate so far: a failed run never leaves a worse x behind
+  if (!c->xbest && psl_ctx_alloc(c, reinterpret_cast<void**>(&c->xbest), sizeof(double) * n) != PSL_OK)
+    return finish(PSL_ENOMEM);
+  double best_rnorm = INFINITY, last_rnorm = INFINITY;
   for (int outer = 0;; ++outer) {
     // projects the previous inner correction and forms x* for the next inner solve
     enqueue_outer_step(c, b, x, st);
     if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
     const double rnorm = std::sqrt(c->h_sc->rr);
+    last_rnorm = rnorm;
+    if (rnorm < best_rnorm) {
+      best_rnorm = rnorm;
+      PSL_HIP(hipMemcpyAsync(c->xbest, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
     stats.outer = outer;
     if (verbose)
       std::fprintf(stderr, "libpsl: outer %d  ||P1 r||/||b|| = %.3e  mode %s  iters %d\n", outer,
@@ -1573,8 +1584,19 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
         widen_direction = keep_direction && !(outer > 0 && rnorm > 0.5 * prev_rnorm);
         keep_direction = 0;
       } else if (rnorm > 0.9 * prev_rnorm && last_fresh64) {
-        // only a fresh float64 run that made no progress ends the solve; after a
-        // continued or stalled run the next one starts fresh
+        // a fresh float64 run made no progress. The single-reduction recurrences can lose
+        // their accuracy at deep tolerances; go back to the best iterate and finish with
+        // the two-reduction loop and residual replacement, which stays accurate. If that
+        // fails too, the solve ends (with the best iterate).
+        if (form64 == kFormSingle) {
+          form64 = kFormTwo;
+          keep64 = 0;
+          last_fresh64 = 0;
+          prev_rnorm = INFINITY;
+          PSL_HIP(hipMemcpyAsync(x, c->xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+          if (verbose) std::fprintf(stderr, "libpsl: float64 two-reduction loop from the best x\n");
+          continue;
+        }
         status = last_inner_broke ? PSL_EBREAKDOWN : PSL_ESTAGNATION;
         break;
       }
@@ -1601,6 +1623,14 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       rc = inner_solve<double>(c, x, kFormTwo, 0, o.tol * bnorm / scale, o.maxit - total_iters,
                                o.check_every, 0, use_graph, outer, st, &it, &ist, &stalled);
       last_fresh64 = 0;
+    } else if (form64 == kFormTwo) {
+      const int fresh = !keep64;
+      if (fresh) scale64 = rnorm;
+      const double goal = std::max(o.tau_inner * rnorm, o.tol * bnorm) / scale64;
+      rc = inner_solve<double>(c, x, kFormTwo, fresh, goal, o.maxit - total_iters,
+                               o.check_every, 0, use_graph, outer, st, &it, &ist, &stalled);
+      keep64 = (rc == PSL_OK && ist == PSL_OK && !stalled);
+      last_fresh64 = fresh && !stalled;
     } else {
       const int rp = o.reproject == 1;
       rc = inner_solve<double>(c, x, form64, 1, target, o.maxit - total_iters, o.check_every,
@@ -1616,12 +1646,16 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
     stats.iters = total_iters;
     if (ist == PSL_ENONFINITE) {
       status = ist;
-      enqueue_outer_step(c, b, x, st);  // leave x projected
+      last_rnorm = INFINITY;   // x holds the failed correction: return the best iterate
       break;
     }
     // a breakdown or stall ends this inner solve; the refinement loop decides what next
     last_inner_broke = (ist == PSL_EBREAKDOWN && it == 0);
   }
+  // a solve that failed (not one that ran out of iterations) returns the best projected
+  // iterate it has seen
+  if (status != PSL_OK && status != PSL_EMAXIT && best_rnorm < last_rnorm)
+    PSL_HIP(hipMemcpyAsync(x, c->xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   // fresh float64 residual of the returned x
   launch_stencil<double, 1>(c, x, b, c->t64, st);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
