@@ -359,20 +359,33 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1510_02148_amd import pipeline, psl
+    from paper_1510_02148_amd import autotune, pipeline, psl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prob = make_problem(args.workload, args.seed)
     log(f"workload {args.workload} grid={prob.grid} nsub={prob.nsub} n={prob.n}")
+    # tile size per precision from the autotuner's table (tuned now, outside the timed
+    # region, when this machine has no entry)
+    tiles = {}
+    for prec in ("f64", "f32"):
+        t = autotune.tiles_for([prob.grid], precision=prec, kind="single")[0]
+        if t is None:
+            log(f"no tuned {prec} tile size for this shape class: tuning")
+            entries = autotune.tune_single(prob, prec, log=log)
+            autotune.save_table(entries)
+            t = autotune.tiles_for([prob.grid], entries, precision=prec, kind="single")[0]
+        tiles[prec] = t
+    log(f"tile sizes: float64 {tiles['f64']}, mixed {tiles['f32']}")
     K = torch.as_tensor(prob.K, dtype=torch.float64, device=dev)
     b = torch.as_tensor(prob.q, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
     def step(mode):
         t0 = time.perf_counter()
-        s = pipeline.setup(prob.grid, K, prob.dirichlet_mask, prob.nsub, list(prob.thr))
+        s = pipeline.setup(prob.grid, K, prob.dirichlet_mask, prob.nsub, list(prob.thr),
+                           tile_cells=tiles["f32" if mode == psl.MIXED else "f64"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
@@ -489,7 +502,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid),
                    "nsub": list(prob.nsub), "d": d, "tol": prob.tol, "mode": args.mode,
-                   "seed": args.seed},
+                   "seed": args.seed, "tile_cells": tiles},
         "converged": bool(ok), "iterations": st["iters"], "outer": st["outer"],
         "relres_true": st["relres_true"], "setup_s": setup_s, "solve_s": solve_s,
         "spmv_gbs": spmv_gbs, "ctx_info": info, "kernels": kernels, "roofline": roofline,

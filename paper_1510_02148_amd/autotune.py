@@ -3,11 +3,13 @@
 A work tile is one workgroup's box of cells (inside one subdomain). Its size trades the
 number of workgroups (latency hiding, early exit of finished systems) against the work
 and registers per workgroup, and the best value depends on the grid shape: this module
-measures it. For every shape class (cell count rounded to a power of two) it builds
+measures it. For every shape class (cell count rounded to a power of two) `tune` builds
 contexts for a sample of that class's systems with each candidate tile size, times the
-batched float64 solve (warm, best of a few runs) and keeps the fastest. Results are kept
-in a JSON table keyed by GPU architecture and precision, so tuning runs once per machine
-type; `tiles_for` looks sizes up for a list of grids.
+batched float64 solve (warm, best of a few runs) and keeps the fastest; `tune_single` does
+the same for one system's solve in a given precision (float64 and float32 loops move
+different amounts per cell and prefer different sizes). Results are kept in a JSON table
+keyed by GPU architecture and by solve kind, precision and shape class, so tuning runs
+once per machine type; `tiles_for` looks sizes up for a list of grids.
 """
 from __future__ import annotations
 
@@ -53,8 +55,9 @@ def save_table(entries: Dict[str, dict], path: str = TABLE_PATH) -> None:
         json.dump(data, f, indent=1, sort_keys=True)
 
 
-def _key(precision: str, cls: int) -> str:
-    return f"{precision}:{cls}"
+def _key(precision: str, cls: int, kind: str = "batch") -> str:
+    """Table key: solve kind (batch / single), precision (f64 / f32), shape class."""
+    return f"{kind}-{precision}:{cls}"
 
 
 def _time_batch(problems, tensors, tile: int, reps: int) -> float:
@@ -78,7 +81,8 @@ def _time_batch(problems, tensors, tile: int, reps: int) -> float:
 def tune(problems: Sequence, candidates: Iterable[int] = CANDIDATES, sample: int = 8,
          reps: int = 2, precision: str = "f64", log=print) -> Dict[str, dict]:
     """Time each candidate tile size per shape class of `problems` (psl_inputs.Problem
-    objects) and return the table entries {"f64:<class>": {"tile_cells", "ms"}}."""
+    objects) for the batched solve; returns the table entries
+    {"batch-<precision>:<class>": {"tile_cells", "ms", "systems"}}."""
     by_class: Dict[int, List] = {}
     for p in problems:
         by_class.setdefault(shape_class(p.n), []).append(p)
@@ -91,7 +95,7 @@ def tune(problems: Sequence, candidates: Iterable[int] = CANDIDATES, sample: int
         for tile in candidates:
             times[int(tile)] = _time_batch(group, tensors, int(tile), reps) * 1e3
         best = min(times, key=times.get)
-        entries[_key(precision, cls)] = {"tile_cells": best,
+        entries[_key(precision, cls, "batch")] = {"tile_cells": best,
                                          "ms": {str(k): round(v, 3) for k, v in times.items()},
                                          "systems": len(group)}
         if log:
@@ -100,13 +104,44 @@ def tune(problems: Sequence, candidates: Iterable[int] = CANDIDATES, sample: int
     return entries
 
 
+def tune_single(problem, precision: str = "f64", candidates: Iterable[int] = CANDIDATES,
+                reps: int = 3, log=print) -> Dict[str, dict]:
+    """Time the single-system solve (psl_solve in the given precision, from set-up to
+    1e-8) of one problem for each candidate tile size; the table entry for its class."""
+    K = torch.as_tensor(problem.K, dtype=torch.float64, device="cuda")
+    b = torch.as_tensor(problem.q, dtype=torch.float64, device="cuda")
+    mode = psl.MIXED if precision == "f32" else psl.FP64
+    times = {}
+    for tile in candidates:
+        s = pipeline.setup(problem.grid, K, problem.dirichlet_mask, problem.nsub,
+                           list(problem.thr), tile_cells=int(tile))
+        psl.psl_solve(s.ctx, b, tol=problem.tol, mode=mode)       # warm
+        best = math.inf
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            psl.psl_solve(s.ctx, b, tol=problem.tol, mode=mode)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        times[int(tile)] = best * 1e3
+        s.ctx.destroy()
+    win = min(times, key=times.get)
+    cls = shape_class(problem.n)
+    if log:
+        log(f"[autotune] single {precision} class 2^{cls}: "
+            + " ".join(f"{k}:{v:.2f}ms" for k, v in times.items()) + f" -> {win}")
+    return {_key(precision, cls, "single"): {"tile_cells": win,
+                                             "ms": {str(k): round(v, 3) for k, v in times.items()},
+                                             "systems": 1}}
+
+
 def tiles_for(grids: Sequence[Sequence[int]], table: Optional[Dict[str, dict]] = None,
-              precision: str = "f64") -> List[Optional[int]]:
+              precision: str = "f64", kind: str = "batch") -> List[Optional[int]]:
     """Tuned tile size for each grid (None where the table has no entry for its class:
     psl_setup_E then chooses)."""
     table = load_table() if table is None else table
     out = []
     for g in grids:
-        e = table.get(_key(precision, shape_class(int(g[0]) * int(g[1]) * int(g[2]))))
+        e = table.get(_key(precision, shape_class(int(g[0]) * int(g[1]) * int(g[2])), kind))
         out.append(int(e["tile_cells"]) if e else None)
     return out

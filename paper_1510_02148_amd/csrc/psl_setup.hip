@@ -656,35 +656,36 @@ __global__ void __launch_bounds__(kBlock) k_E_rows(const int32_t* lab_ptr,
 // ---------------------------------------------------------------------------------------
 constexpr int kNB = 64;
 
-// Factor the kb diagonal block in LDS (right-looking). Thread t updates row t/4 at the
-// columns congruent to t mod 4; a non-positive pivot raises *bad.
-__global__ void __launch_bounds__(kBlock) k_potrf_diag(double* A, int d, int kb, int32_t* bad) {
-  __shared__ double a[kNB][kNB + 1];
-  __shared__ double col[kNB];
+// Factor the kb diagonal block in LDS by columns (left-looking, one wave): lane i owns row
+// i; column j needs s_i = sum_{k<j} L[i][k] L[j][k], read from the finished rows (row j is
+// a broadcast), then L[j][j] = sqrt(A[j][j] - s_j) and L[i][j] = (A[i][j] - s_i) / L[j][j].
+// A non-positive pivot raises *bad.
+__global__ void __launch_bounds__(psl::kWave) k_potrf_diag(double* A, int d, int kb, int32_t* bad) {
+  __shared__ double l[kNB][kNB + 1];
+  const int i = threadIdx.x;
   const int nb = min(kNB, d - kb);
-  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
-    const int i = t / nb, j = t % nb;
-    a[i][j] = A[int64_t(kb + i) * d + kb + j];
+  for (int t = i; t < nb * nb; t += psl::kWave) {
+    const int r = t / nb, cc = t % nb;
+    l[r][cc] = A[int64_t(kb + r) * d + kb + cc];
   }
   __syncthreads();
-  const int ri = threadIdx.x >> 2, cj = threadIdx.x & 3;
-  for (int k = 0; k < nb; ++k) {
-    const double p = a[k][k];
-    const double piv = sqrt(p > 0.0 ? p : 1.0);
-    if (threadIdx.x == 0 && (!(p > 0.0) || !(p < INFINITY))) bad[0] = 1;
-    if (threadIdx.x < nb && int(threadIdx.x) > k) col[threadIdx.x] = a[threadIdx.x][k] / piv;
-    __syncthreads();
-    if (ri < nb && ri > k) {
-      const double ci = col[ri];
-      for (int j = k + 1 + ((cj - (k + 1)) & 3); j <= ri; j += 4) a[ri][j] -= ci * col[j];
+  const bool own = i < nb;
+  for (int j = 0; j < nb; ++j) {
+    double s = 0.0;
+    if (own && i >= j)
+      for (int k = 0; k < j; ++k) s += l[i][k] * l[j][k];
+    if (i == j) {
+      const double p = l[j][j] - s;
+      if (!(p > 0.0) || !(p < INFINITY)) bad[0] = 1;
+      l[j][j] = sqrt(p > 0.0 ? p : 1.0);
     }
-    if (threadIdx.x < nb && int(threadIdx.x) > k) a[threadIdx.x][k] = col[threadIdx.x];
-    if (threadIdx.x == 0) a[k][k] = piv;
+    __syncthreads();
+    if (own && i > j) l[i][j] = (l[i][j] - s) / l[j][j];
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
-    const int i = t / nb, j = t % nb;
-    A[int64_t(kb + i) * d + kb + j] = (j <= i) ? a[i][j] : 0.0;
+  for (int t = i; t < nb * nb; t += psl::kWave) {
+    const int r = t / nb, cc = t % nb;
+    A[int64_t(kb + r) * d + kb + cc] = (cc <= r) ? l[r][cc] : 0.0;
   }
 }
 
@@ -801,7 +802,7 @@ __global__ void k_identity(double* X, int d) {
 static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream_t st) {
   for (int kb = 0; kb < d; kb += kNB) {
     const int nb = std::min(kNB, d - kb);
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(kBlock), 0, st, L, d, kb, bad);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(psl::kWave), 0, st, L, d, kb, bad);
     const int rest = d - kb - nb;
     if (rest > 0) {
       hipLaunchKernelGGL(k_trsm_panel, dim3(nblocks(rest, kBlock / psl::kWave)), dim3(kBlock), 0,
