@@ -656,54 +656,106 @@ __global__ void __launch_bounds__(kBlock) k_E_rows(const int32_t* lab_ptr,
 // ---------------------------------------------------------------------------------------
 constexpr int kNB = 64;
 
-// Factor the kb diagonal block in LDS by columns (left-looking, one wave): lane i owns row
-// i; column j needs s_i = sum_{k<j} L[i][k] L[j][k], read from the finished rows (row j is
-// a broadcast), then L[j][j] = sqrt(A[j][j] - s_j) and L[i][j] = (A[i][j] - s_i) / L[j][j].
-// A non-positive pivot raises *bad.
+// The nb x nb block at src (leading dimension ld) into l[0:nb][0:nb] (zeros beyond nb),
+// for a workgroup of NT threads: thread t covers column t % 64 of every (NT / 64)-th row,
+// and issues all its global loads before its first LDS store.
+template <int NT>
+__device__ inline void stage_block(double (*l)[kNB + 1], const double* src, int64_t ld, int nb) {
+  constexpr int kRows = NT / psl::kWave, kLoads = kNB / kRows;
+  const int c = threadIdx.x % psl::kWave, r0 = threadIdx.x / psl::kWave;
+  double v[kLoads];
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) {
+    const int r = r0 + kRows * u;
+    v[u] = (r < nb && c < nb) ? src[int64_t(r) * ld + c] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) l[r0 + kRows * u][c] = v[u];
+}
+
+__device__ inline double readlane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Factor the kb diagonal block by columns (left-looking, one wave): lane i owns row i;
+// column j needs s_i = sum_{k<j} L[i][k] L[j][k], then L[j][j] = sqrt(A[j][j] - s_j) and
+// L[i][j] = (A[i][j] - s_i) / L[j][j]. Columns go in groups of eight. The terms of the
+// finished columns k < jb are summed for the whole group in one pass over row i in LDS
+// (with a transposed copy lt[k][j] = L[j][k], so the eight multipliers of a k are one
+// contiguous read); inside the group each lane keeps its new entries in registers and
+// row j's come by lane reads, so a column costs no LDS round trip or barrier. Every s_i
+// is the plain sequential sum in k order. A non-positive pivot raises *bad.
 __global__ void __launch_bounds__(psl::kWave) k_potrf_diag(double* A, int d, int kb, int32_t* bad) {
+  constexpr int kG = 8;
   __shared__ double l[kNB][kNB + 1];
+  __shared__ __align__(16) double lt[kNB][kNB + 2];  // rows of 528 bytes keep 16-byte reads aligned
   const int i = threadIdx.x;
   const int nb = min(kNB, d - kb);
-  for (int t = i; t < nb * nb; t += psl::kWave) {
-    const int r = t / nb, cc = t % nb;
-    l[r][cc] = A[int64_t(kb + r) * d + kb + cc];
-  }
-  __syncthreads();
   const bool own = i < nb;
-  for (int j = 0; j < nb; ++j) {
-    double s = 0.0;
-    if (own && i >= j)
-      for (int k = 0; k < j; ++k) s += l[i][k] * l[j][k];
-    if (i == j) {
-      const double p = l[j][j] - s;
-      if (!(p > 0.0) || !(p < INFINITY)) bad[0] = 1;
-      l[j][j] = sqrt(p > 0.0 ? p : 1.0);
+  stage_block<psl::kWave>(l, A + int64_t(kb) * d + kb, d, nb);
+  __syncthreads();
+  for (int jb = 0; jb < nb; jb += kG) {
+    double t[kG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (own && i >= jb) {
+      for (int k = 0; k < jb; ++k) {
+        const double x = l[i][k];
+        const double2* q = reinterpret_cast<const double2*>(&lt[k][jb]);
+#pragma unroll
+        for (int u = 0; u < kG / 2; ++u) {
+          const double2 w = q[u];
+          t[2 * u] += x * w.x;
+          t[2 * u + 1] += x * w.y;
+        }
+      }
+    }
+    double g[kG];
+#pragma unroll
+    for (int c = 0; c < kG; ++c) {
+      const int j = jb + c;
+      g[c] = 0.0;
+      if (j < nb) {  // uniform
+        double s = t[c];
+#pragma unroll
+        for (int u = 0; u < c; ++u) s += g[u] * readlane_f64(g[u], j);
+        const double r = l[i][j] - s;
+        const double p = readlane_f64(r, j);
+        if (i == 0 && (!(p > 0.0) || !(p < INFINITY))) bad[0] = 1;
+        const double piv = sqrt(p > 0.0 ? p : 1.0);
+        g[c] = (i == j) ? piv : r / piv;  // entries above the diagonal are never used
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kG; ++c) {
+      if (jb + c < nb) {
+        l[i][jb + c] = g[c];
+        lt[jb + c][i] = g[c];
+      }
     }
     __syncthreads();
-    if (own && i > j) l[i][j] = (l[i][j] - s) / l[j][j];
-    __syncthreads();
   }
-  for (int t = i; t < nb * nb; t += psl::kWave) {
-    const int r = t / nb, cc = t % nb;
-    A[int64_t(kb + r) * d + kb + cc] = (cc <= r) ? l[r][cc] : 0.0;
-  }
+  double* o = A + int64_t(kb) * d + kb + i;
+  if (own)
+    for (int r = 0; r < nb; ++r) o[int64_t(r) * d] = (i <= r) ? l[r][i] : 0.0;
 }
 
 // Wave-parallel substitution with the nb x nb lower block l (in LDS): lane j holds x_j.
 // forward (trans = 0): solves l x = x_in; backward (trans = 1): solves l^T x = x_in.
+// Each solved entry is divided once (uniformly) and broadcast with a lane read.
 __device__ inline double wave_trsv(const double (*l)[kNB + 1], int nb, double x, int trans) {
   const int lane = threadIdx.x & (psl::kWave - 1);
   if (!trans) {
     for (int m = 0; m < nb; ++m) {
-      if (lane == m) x /= l[m][m];
-      const double xm = __shfl(x, m, psl::kWave);
-      if (lane > m && lane < nb) x -= l[lane][m] * xm;
+      const double xm = readlane_f64(x, m) / l[m][m];
+      if (lane == m) x = xm;
+      else if (lane > m && lane < nb) x -= l[lane][m] * xm;
     }
   } else {
     for (int m = nb - 1; m >= 0; --m) {
-      if (lane == m) x /= l[m][m];
-      const double xm = __shfl(x, m, psl::kWave);
-      if (lane < m) x -= l[m][lane] * xm;
+      const double xm = readlane_f64(x, m) / l[m][m];
+      if (lane == m) x = xm;
+      else if (lane < m) x -= l[m][lane] * xm;
     }
   }
   return x;
@@ -714,10 +766,7 @@ __device__ inline double wave_trsv(const double (*l)[kNB + 1], int nb, double x,
 __global__ void __launch_bounds__(kBlock) k_trsm_panel(double* A, int d, int kb) {
   __shared__ double l[kNB][kNB + 1];
   const int nb = min(kNB, d - kb);
-  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
-    const int i = t / nb, j = t % nb;
-    l[i][j] = A[int64_t(kb + i) * d + kb + j];
-  }
+  stage_block<kBlock>(l, A + int64_t(kb) * d + kb, d, nb);
   __syncthreads();
   const int lane = threadIdx.x & (psl::kWave - 1);
   const int i = kb + nb + blockIdx.x * (kBlock / psl::kWave) + threadIdx.x / psl::kWave;
@@ -740,13 +789,29 @@ __global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const d
   __shared__ double sb[kNB][64 + 1];  // sb[k][j]
   const int ti = blockIdx.y * 64, tj = blockIdx.x * 64;
   if (LOWER && tj > ti + 63) return;
-  for (int t = threadIdx.x; t < K * 64; t += kBlock) {
-    // walk the contiguous dimension of each operand fastest
+  // K * 64 <= 4096 entries per operand: 16 per thread, all loads issued before the stores;
+  // each operand is walked along its contiguous dimension
+  constexpr int kLoads = kNB * 64 / kBlock;
+  double va[kLoads], vb[kLoads];
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) {
+    const int t = threadIdx.x + u * kBlock;
     const int ka = AM ? t / 64 : t % K, ra = AM ? t % 64 : t / K;
     const int kb = BM ? t % K : t / 64, rb = BM ? t / K : t % 64;
     const int i = ti + ra, j = tj + rb;
-    sa[ka][ra] = i < M ? (AM ? A[int64_t(ka) * lda + i] : A[int64_t(i) * lda + ka]) : 0.0;
-    sb[kb][rb] = j < N ? (BM ? B[int64_t(j) * ldb + kb] : B[int64_t(kb) * ldb + j]) : 0.0;
+    const bool in = t < K * 64;
+    va[u] = in && i < M ? (AM ? A[int64_t(ka) * lda + i] : A[int64_t(i) * lda + ka]) : 0.0;
+    vb[u] = in && j < N ? (BM ? B[int64_t(j) * ldb + kb] : B[int64_t(kb) * ldb + j]) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kLoads; ++u) {
+    const int t = threadIdx.x + u * kBlock;
+    if (t < K * 64) {
+      const int ka = AM ? t / 64 : t % K, ra = AM ? t % 64 : t / K;
+      const int kb = BM ? t % K : t / 64, rb = BM ? t / K : t % 64;
+      sa[ka][ra] = va[u];
+      sb[kb][rb] = vb[u];
+    }
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
@@ -778,10 +843,7 @@ __global__ void __launch_bounds__(kBlock) k_trsm_cols(const double* L, double* X
                                                       int trans) {
   __shared__ double l[kNB][kNB + 1];
   const int nb = min(kNB, d - kb);
-  for (int t = threadIdx.x; t < nb * nb; t += kBlock) {
-    const int i = t / nb, j = t % nb;
-    l[i][j] = L[int64_t(kb + i) * d + kb + j];
-  }
+  stage_block<kBlock>(l, L + int64_t(kb) * d + kb, d, nb);
   __syncthreads();
   const int lane = threadIdx.x & (psl::kWave - 1);
   const int c = blockIdx.x * (kBlock / psl::kWave) + threadIdx.x / psl::kWave;
