@@ -79,7 +79,7 @@ typedef struct {
   int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
   int32_t max_outer;    /* cap on refinement steps (default 30) */
   double  tau_inner;    /* PSL_MIXED: reduction of the float32 CG residual after which it
-                           is replaced by the float64 residual (default 0.1); PSL_FP64
+                           is replaced by the float64 residual (default 0.01); PSL_FP64
                            ignores it */
   int32_t check_every;  /* CG iterations enqueued between host convergence checks
                            (default 16; iterations after convergence are skipped on device) */
@@ -88,8 +88,9 @@ typedef struct {
                            0 or -1 (default) off. PSL_MIXED ignores it (its residual is
                            replaced by the projected float64 residual instead) */
   double  mixed_floor;  /* PSL_MIXED: once ||b - A x|| <= mixed_floor ||b||, float64 CG
-                           continues along the float32 search direction (default 1e-4;
-                           0 keeps float32 until it stalls) */
+                           continues along the float32 search direction (default 1e-7;
+                           0 keeps float32 until it stalls; float32 also hands over as
+                           soon as its float64 residual detaches from its own) */
 } psl_solve_opts;
 
 typedef struct {

@@ -43,10 +43,10 @@ extern "C" void psl_default_opts(psl_solve_opts* o) {
   o->mode = PSL_FP64;
   o->use_x0 = 0;
   o->max_outer = 30;
-  o->tau_inner = 0.1;
+  o->tau_inner = 0.01;
   o->check_every = 16;
   o->reproject = -1;
-  o->mixed_floor = 1e-4;
+  o->mixed_floor = 1e-7;
 }
 
 // Device memory comes from the device's stream-ordered pool, which keeps freed blocks

@@ -1389,6 +1389,7 @@ int read_scalars(psl_ctx* c, hipStream_t st) {
 }
 
 constexpr int kStallWindow = 512;   // inner iterations without halving ||r|| -> stop
+constexpr int64_t kGraphMaxCells = int64_t(1) << 18;
 
 // Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
@@ -1520,7 +1521,10 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   }
   if (!o.use_x0) hipLaunchKernelGGL(k_zero, dim3(elem_grid(n)), dim3(kBlock), 0, st, x, n);
 
-  const int use_graph = 1;
+  // Replayed graphs pay off only when the iteration kernels are shorter than a launch;
+  // above that size direct launches keep the queue ahead of the GPU just as well and save
+  // capturing and instantiating a graph for every new context.
+  const int use_graph = c->n < kGraphMaxCells;
   const char* verbose_env = std::getenv("PSL_VERBOSE");
   const bool verbose = verbose_env && verbose_env[0] == '1';
   int mode = o.mode;

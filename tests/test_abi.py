@@ -73,7 +73,7 @@ def test_default_opts(lib):
     from paper_1510_02148_amd import psl
     o = psl.default_opts()
     assert o.tol == 1e-8 and o.maxit == 10000 and o.mode == psl.FP64 and o.check_every == 16
-    assert o.tau_inner == 0.1 and o.reproject == -1 and o.mixed_floor == 1e-4
+    assert o.tau_inner == 0.01 and o.reproject == -1 and o.mixed_floor == 1e-7
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):

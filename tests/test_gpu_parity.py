@@ -381,16 +381,18 @@ def test_reprojection_option(gpu_lib, mode, reproject):
         assert abs(st["iters"] - ref.iters) <= max(2, slack * ref.iters)
 
 
-@pytest.mark.parametrize("floor", [0.0, 1e-6, 1e-4, 0.5], ids=["stall", "1e-6", "1e-4", "at-once"])
-def test_mixed_handover(gpu_lib, floor):
+@pytest.mark.parametrize("floor,tau", [(0.0, None), (1e-7, None), (1e-6, None), (1e-4, 0.1),
+                                       (0.5, None)],
+                         ids=["stall", "1e-7", "1e-6", "1e-4-tau0.1", "at-once"])
+def test_mixed_handover(gpu_lib, floor, tau):
     """Float32 CG with residual replacement hands over to float64 (continuing its search
     direction) at the floor, after its float64 residual detaches, or, with floor 0, only
     when it stalls; every route must end at the float64 accuracy of the plain solve."""
     psl = gpu_lib
     from paper_1510_02148_amd import pipeline
     p = pi.config("c3", scale=4, contrast=1e7)
-    say(f"mixed handover floor={floor} c3/4 contrast 1e7")
-    x, st, s = pipeline.solve_problem(p, mode=psl.MIXED, mixed_floor=floor)
+    say(f"mixed handover floor={floor} tau={tau} c3/4 contrast 1e7")
+    x, st, s = pipeline.solve_problem(p, mode=psl.MIXED, mixed_floor=floor, tau_inner=tau)
     A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
     res = O.relres(A, b, host(x))
     Z = O.deflation_matrix(*O.levelset_labels(p.grid, p.K, p.nsub, p.thr))
