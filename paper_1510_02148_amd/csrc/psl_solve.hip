@@ -1390,6 +1390,7 @@ int read_scalars(psl_ctx* c, hipStream_t st) {
 
 constexpr int kStallWindow = 512;   // inner iterations without halving ||r|| -> stop
 constexpr int64_t kGraphMaxCells = int64_t(1) << 18;
+constexpr double kDetach = 1.05;    // float64 / recursive float32 residual -> hand over
 
 // Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
@@ -1574,9 +1575,11 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       status = PSL_EMAXIT;
       break;
     }
-    // float32 has reached its attainable accuracy once the float64 residual no longer
-    // follows the recursive one (it lags by more than half again)
-    const bool detached = mode == PSL_MIXED && keep_direction && rnorm > 1.5 * inner_reached;
+    // float32 is near its attainable accuracy once the float64 residual no longer follows
+    // the recursive one: a lag of a few per cent already means its rounding errors are a
+    // visible part of the residual, and every further float32 step then costs float64
+    // steps later (the lag grows to tens of times within one more run)
+    const bool detached = mode == PSL_MIXED && keep_direction && rnorm > kDetach * inner_reached;
     const bool floor = mode == PSL_MIXED && rnorm <= o.mixed_floor * bnorm;
     if ((outer > 0 && (rnorm > 0.5 * prev_rnorm || detached)) || floor) {
       if (mode == PSL_MIXED) {
