@@ -1392,12 +1392,31 @@ constexpr int kStallWindow = 512;   // inner iterations without halving ||r|| ->
 constexpr int64_t kGraphMaxCells = int64_t(1) << 18;
 constexpr double kDetach = 1.05;    // float64 / recursive float32 residual -> hand over
 
+// Enqueue `count` iterations (even): replays of the captured chunk where it fits, the rest
+// launched directly (same kernels, same order).
+template <typename R>
+int enqueue_count(psl_ctx* c, int form, int chunk, int count, int rp, int use_graph,
+                  hipStream_t st) {
+  if (use_graph) {
+    for (; count >= chunk; count -= chunk) {
+      const int rc = run_chunk<R>(c, form, chunk, rp, st);
+      if (rc != PSL_OK) return rc;
+    }
+  }
+  if (count > 0) {
+    enqueue_form<R>(c, form, count, rp, st);
+    PSL_HIP(hipGetLastError());
+  }
+  return PSL_OK;
+}
+
 // Inner deflated PCG on the current refinement residual (c->r64, ||r||^2 in sc->rr); adds
 // ||r|| xhat to x. *status: PSL_OK (goal reached or stalled), PSL_EBREAKDOWN, PSL_ENONFINITE.
+// `hint`: iterations the previous inner run of this solve took (0 if none).
 template <typename R>
 int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int maxit,
-                int check_every, int rp, int use_graph, int outer, hipStream_t st, int* iters,
-                int* status, int* stalled) {
+                int check_every, int rp, int use_graph, int outer, int hint, hipStream_t st,
+                int* iters, int* status, int* stalled) {
   int rc = form == kFormTwo ? ensure_sd<R>(c) : ensure_vecs<R>(c);
   if (rc != PSL_OK) return rc;
   psl::VecSet<R>& v = Prec<R>::vecs(c);
@@ -1414,32 +1433,45 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
   double best = INFINITY;
   int best_it = 0;
   *stalled = 0;
-  // the first check comes after about 3/4 of the iterations the same refinement step of
-  // the previous solve needed (launches after convergence return at once)
+  // The first check comes after about 3/4 of the iterations the same refinement step of
+  // the previous solve on this context needed (else the previous step of this solve).
+  // Later enqueues are a chunk, or, once the convergence rate between the last two checks
+  // says fewer are left, about that many: iterations enqueued past the goal return at once
+  // but still cost a launch each. (Enqueueing more than a chunk on an extrapolation is
+  // not safe: a slowly converging run extrapolates to thousands of iterations.)
   int& last = (std::is_same<R, double>::value ? c->last_iters64 : c->last_iters32)[std::min(outer, 7)];
-  int batches = std::max(1, (3 * last / 4) / chunk);
+  const int known = last > 0 ? last : std::min(hint, 4 * chunk);   // a long run's count is no guide
+  int count = (3 * known / 4) & ~1;
+  if (count < 2) count = chunk;
+  double prev_rr = -1.0;
+  int prev_it = 0;
   for (;;) {
-    for (int bi = 0; bi < batches; ++bi) {
-      if (use_graph) {
-        rc = run_chunk<R>(c, form, chunk, rp, st);
-        if (rc != PSL_OK) return rc;
-      } else {
-        enqueue_form<R>(c, form, chunk, rp, st);
-        PSL_HIP(hipGetLastError());
-      }
-    }
-    batches = 1;
+    rc = enqueue_count<R>(c, form, chunk, count, rp, use_graph, st);
+    if (rc != PSL_OK) return rc;
     rc = read_scalars(c, st);
     if (rc != PSL_OK) return rc;
     if (c->h_sc->done) break;
     const double rr = c->h_sc->rr;
+    const int its = c->h_sc->iters;
     if (rr < 0.25 * best) {
       best = rr;
-      best_it = c->h_sc->iters;
-    } else if (c->h_sc->iters - best_it >= kStallWindow) {
+      best_it = its;
+    } else if (its - best_it >= kStallWindow) {
       *stalled = 1;
       break;
     }
+    count = chunk;
+    if (prev_rr > 0.0 && rr > 0.0 && rr < prev_rr && its > prev_it &&
+        c->h_sc->goal2 > 0.0 && c->h_sc->goal2 < rr) {
+      const double per_it = std::log(rr / prev_rr) / double(its - prev_it);
+      const double need = std::log(c->h_sc->goal2 / rr) / per_it;
+      if (need < chunk) {
+        count = int(std::ceil(1.2 * need)) + 2;
+        count = std::min(chunk, count + (count & 1));
+      }
+    }
+    prev_rr = rr;
+    prev_it = its;
   }
   *iters = c->h_sc->iters;
   *status = c->h_sc->status;
@@ -1549,6 +1581,7 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   if (!c->xbest && psl_ctx_alloc(c, reinterpret_cast<void**>(&c->xbest), sizeof(double) * n) != PSL_OK)
     return finish(PSL_ENOMEM);
   double best_rnorm = INFINITY, last_rnorm = INFINITY;
+  int hint32 = 0;               // iterations of the last float32 run (first-check estimate)
   for (int outer = 0;; ++outer) {
     // projects the previous inner correction and forms x* for the next inner solve
     enqueue_outer_step(c, b, x, st);
@@ -1618,7 +1651,8 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       // goal of this run relative to `scale`: a reduction by tau_inner, or the tolerance
       const double goal = std::max(o.tau_inner * rnorm, o.tol * bnorm) / scale;
       rc = inner_solve<float>(c, x, form32, fresh, goal, o.maxit - total_iters, o.check_every,
-                              rp, use_graph, outer, st, &it, &ist, &stalled);
+                              rp, use_graph, outer, hint32, st, &it, &ist, &stalled);
+      hint32 = it;
       keep_direction = (rc == PSL_OK && ist == PSL_OK && !stalled);
       inner_reached = std::sqrt(c->h_sc->rr) * scale;
     } else if (widen_direction) {
@@ -1628,20 +1662,20 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
       hipLaunchKernelGGL(k_widen2, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->v32.p,
                          c->v32.p2, c->v64.p, c->v64.p2);
       rc = inner_solve<double>(c, x, kFormTwo, 0, o.tol * bnorm / scale, o.maxit - total_iters,
-                               o.check_every, 0, use_graph, outer, st, &it, &ist, &stalled);
+                               o.check_every, 0, use_graph, outer, 0, st, &it, &ist, &stalled);
       last_fresh64 = 0;
     } else if (form64 == kFormTwo) {
       const int fresh = !keep64;
       if (fresh) scale64 = rnorm;
       const double goal = std::max(o.tau_inner * rnorm, o.tol * bnorm) / scale64;
       rc = inner_solve<double>(c, x, kFormTwo, fresh, goal, o.maxit - total_iters,
-                               o.check_every, 0, use_graph, outer, st, &it, &ist, &stalled);
+                               o.check_every, 0, use_graph, outer, 0, st, &it, &ist, &stalled);
       keep64 = (rc == PSL_OK && ist == PSL_OK && !stalled);
       last_fresh64 = fresh && !stalled;
     } else {
       const int rp = o.reproject == 1;
       rc = inner_solve<double>(c, x, form64, 1, target, o.maxit - total_iters, o.check_every,
-                               rp, use_graph, outer, st, &it, &ist, &stalled);
+                               rp, use_graph, outer, 0, st, &it, &ist, &stalled);
       last_fresh64 = !stalled;
     }
     if (rc != PSL_OK) return finish(rc);
