@@ -1443,7 +1443,10 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
   const int known = last > 0 ? last : std::min(hint, 4 * chunk);   // a long run's count is no guide
   int count = (3 * known / 4) & ~1;
   if (count < 2) count = chunk;
-  double prev_rr = -1.0;
+  // the run starts at ||r||^2 = 1 (fresh: scaled by the current residual) or at the
+  // refinement residual in the scale of the direction it keeps
+  const double rr_start = c->h_sc->rr * c->h_sc->sigma * c->h_sc->sigma;
+  double prev_rr = fresh ? 1.0 : (rr_start > 0.0 && rr_start < INFINITY ? rr_start : -1.0);
   int prev_it = 0;
   for (;;) {
     rc = enqueue_count<R>(c, form, chunk, count, rp, use_graph, st);
@@ -1466,7 +1469,7 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
       const double per_it = std::log(rr / prev_rr) / double(its - prev_it);
       const double need = std::log(c->h_sc->goal2 / rr) / per_it;
       if (need < chunk) {
-        count = int(std::ceil(1.2 * need)) + 2;
+        count = int(std::ceil(1.1 * need)) + 1;
         count = std::min(chunk, count + (count & 1));
       }
     }
