@@ -837,30 +837,175 @@ __global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const d
     }
 }
 
-// X[kb:kb+nb, c] = L_kk^-1 X[kb:kb+nb, c] (trans = 0) or L_kk^-T X[...] (trans = 1);
-// one wave per column c.
-__global__ void __launch_bounds__(kBlock) k_trsm_cols(const double* L, double* X, int d, int kb,
-                                                      int trans) {
+// A rows x cols block at src (leading dimension ld) on its way into LDS, zero beyond rows /
+// cols: dst[r][c] (TRANS = 0) or dst[c][r] (TRANS = 1). A workgroup of kBlock threads; each
+// thread holds 16 entries of one column (loads along a row are coalesced). Loading and
+// storing are separate steps so the next block's loads can be in flight during a product.
+struct RectRegs {
+  double v[kNB / (kBlock / psl::kWave)];
+  __device__ void load(const double* src, int64_t ld, int rows, int cols) {
+    constexpr int kRows = kBlock / psl::kWave;
+    const int c = threadIdx.x % psl::kWave, r0 = threadIdx.x / psl::kWave;
+#pragma unroll
+    for (int u = 0; u < kNB / kRows; ++u) {
+      const int r = r0 + kRows * u;
+      v[u] = (r < rows && c < cols) ? src[int64_t(r) * ld + c] : 0.0;
+    }
+  }
+  template <int TRANS>
+  __device__ void store(double (*dst)[kNB + 2]) const {
+    constexpr int kRows = kBlock / psl::kWave;
+    const int c = threadIdx.x % psl::kWave, r0 = threadIdx.x / psl::kWave;
+#pragma unroll
+    for (int u = 0; u < kNB / kRows; ++u) {
+      const int r = r0 + kRows * u;
+      if (TRANS)
+        dst[c][r] = v[u];
+      else
+        dst[r][c] = v[u];
+    }
+  }
+};
+
+template <int TRANS>
+__device__ inline void stage_rect(double (*dst)[kNB + 2], const double* src, int64_t ld,
+                                  int rows, int cols) {
+  RectRegs g;
+  g.load(src, ld, rows, cols);
+  g.template store<TRANS>(dst);
+}
+
+// acc[u][v] += sum_m sa[m][4 ty + u] sb[m][4 tx + v] over m < 64 (a 64x64 block product,
+// 4x4 outputs per thread, tx = thread % 16, ty = thread / 16). A thread's four rows and
+// four columns are contiguous, so each k step is two 16-byte reads per operand (the rows
+// are shared by the 16 threads of a row group, i.e. broadcast).
+__device__ inline void block_mac(const double (*sa)[kNB + 2], const double (*sb)[kNB + 2],
+                                 double (&acc)[4][4]) {
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  for (int m = 0; m < kNB; ++m) {
+    const double2* pa = reinterpret_cast<const double2*>(&sa[m][4 * ty]);
+    const double2* pb = reinterpret_cast<const double2*>(&sb[m][4 * tx]);
+    const double2 a01 = pa[0], a23 = pa[1], b01 = pb[0], b23 = pb[1];
+    const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+    const double b[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+}
+
+// Inverse of each diagonal block of the lower factor, all blocks at once (one wave per
+// block): lane j forms column j of L_kk^-1 by forward substitution,
+// X_kk[i][j] = (delta_ij - sum_{k<i} L_kk[i][k] X_kk[k][j]) / L_kk[i][i]; entries above
+// the diagonal are written as 0.
+__global__ void __launch_bounds__(psl::kWave) k_trtri_diag(const double* L, double* X, int d) {
   __shared__ double l[kNB][kNB + 1];
-  const int nb = min(kNB, d - kb);
-  stage_block<kBlock>(l, L + int64_t(kb) * d + kb, d, nb);
+  __shared__ double xs[kNB][kNB + 1];
+  const int kb = blockIdx.x * kNB, nb = min(kNB, d - kb), j = threadIdx.x;
+  stage_block<psl::kWave>(l, L + int64_t(kb) * d + kb, d, nb);
   __syncthreads();
-  const int lane = threadIdx.x & (psl::kWave - 1);
-  const int c = blockIdx.x * (kBlock / psl::kWave) + threadIdx.x / psl::kWave;
-  if (c >= d) return;
-  double x = lane < nb ? X[int64_t(kb + lane) * d + c] : 0.0;
-  x = wave_trsv(l, nb, x, trans);
-  if (lane < nb) X[int64_t(kb + lane) * d + c] = x;
+  for (int i = 0; i < nb; ++i) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};   // independent partial sums: the LDS reads overlap
+    int k = 0;
+    for (; k + 4 <= i; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += l[i][k + u] * xs[k + u][j];   // xs[k][j] = 0, k < j
+    }
+    for (; k < i; ++k) s4[0] += l[i][k] * xs[k][j];
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    xs[i][j] = (i >= j) ? ((i == j ? 1.0 : 0.0) - s) / l[i][i] : 0.0;
+  }
+  __syncthreads();
+  if (j < nb)
+    for (int r = 0; r < nb; ++r) X[int64_t(kb + r) * d + kb + j] = xs[r][j];
 }
 
-__global__ void k_identity(double* X, int d) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(d) * d) return;
-  X[t] = (t / d == t % d) ? 1.0 : 0.0;
+// Off-diagonal blocks of L^-1 on block diagonal s (block row i, column j = i - s), all in
+// one launch: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj, which needs only blocks of lower
+// diagonals (formed by earlier launches).
+__global__ void __launch_bounds__(kBlock) k_trtri_off(const double* L, double* X, int d, int s) {
+  __shared__ __align__(16) double sa[kNB][kNB + 2];   // rows of 528 bytes: 16-byte reads stay aligned
+  __shared__ __align__(16) double sb[kNB][kNB + 2];
+  const int i = blockIdx.x + s, j = i - s;
+  const int ri = i * kNB, cj = j * kNB, mi = min(kNB, d - ri);
+  double acc[4][4] = {};
+  RectRegs ga, gb;   // blocks k < i are full
+  ga.load(L + int64_t(ri) * d + j * kNB, d, mi, kNB);
+  gb.load(X + int64_t(j * kNB) * d + cj, d, kNB, kNB);
+  for (int k = j; k < i; ++k) {
+    ga.store<1>(sa);   // sa[m][r] = L_ik(r, m)
+    gb.store<0>(sb);   // sb[m][c] = X_kj(m, c)
+    __syncthreads();
+    if (k + 1 < i) {
+      ga.load(L + int64_t(ri) * d + (k + 1) * kNB, d, mi, kNB);
+      gb.load(X + int64_t((k + 1) * kNB) * d + cj, d, kNB, kNB);
+    }
+    block_mac(sa, sb, acc);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sb[4 * ty + u][4 * tx + v] = acc[u][v];   // T(m, c)
+  stage_rect<1>(sa, X + int64_t(ri) * d + ri, d, mi, mi);                  // sa[m][r] = X_ii(r, m)
+  __syncthreads();
+  double y[4][4] = {};
+  block_mac(sa, sb, y);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 4 * ty + u;
+    if (r < mi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[int64_t(ri + r) * d + cj + 4 * tx + v] = -y[u][v];
+  }
 }
 
-// E (in L, overwritten by its lower Cholesky factor) -> X = E^-1 = L^-T L^-1.
-// A non-positive pivot raises *bad.
+// out = Li^T Li for lower-block-triangular Li (= L^-1), one 64x64 block (I >= J) per
+// workgroup: out_IJ = sum_{k >= I} Li_kI^T Li_kJ, written to (I, J) and mirrored to (J, I).
+__global__ void __launch_bounds__(kBlock) k_lower_gram(const double* Li, double* out, int d,
+                                                       int nblk) {
+  __shared__ __align__(16) double sa[kNB][kNB + 2];
+  __shared__ __align__(16) double sb[kNB][kNB + 2];
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= int(blockIdx.x)) ++I;
+  const int J = int(blockIdx.x) - I * (I + 1) / 2;
+  const int mI = min(kNB, d - I * kNB), mJ = min(kNB, d - J * kNB);
+  double acc[4][4] = {};
+  RectRegs ga, gb;
+  {
+    const int mk = min(kNB, d - I * kNB);
+    ga.load(Li + int64_t(I * kNB) * d + I * kNB, d, mk, mI);
+    gb.load(Li + int64_t(I * kNB) * d + J * kNB, d, mk, mJ);
+  }
+  for (int k = I; k < nblk; ++k) {
+    ga.store<0>(sa);   // sa[m][r] = Li_kI(m, r)
+    gb.store<0>(sb);   // sb[m][c] = Li_kJ(m, c)
+    __syncthreads();
+    if (k + 1 < nblk) {
+      const int mk = min(kNB, d - (k + 1) * kNB);
+      ga.load(Li + int64_t((k + 1) * kNB) * d + I * kNB, d, mk, mI);
+      gb.load(Li + int64_t((k + 1) * kNB) * d + J * kNB, d, mk, mJ);
+    }
+    block_mac(sa, sb, acc);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * ty + u, c = 4 * tx + v;
+      if (r < mI && c < mJ) {
+        out[int64_t(I * kNB + r) * d + J * kNB + c] = acc[u][v];
+        if (I != J) out[int64_t(J * kNB + c) * d + I * kNB + r] = acc[u][v];
+      }
+    }
+}
+
+// E (in L, overwritten by its lower Cholesky factor and then by scratch) -> X = E^-1 =
+// L^-T L^-1. A non-positive pivot raises *bad.
 static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream_t st) {
   for (int kb = 0; kb < d; kb += kNB) {
     const int nb = std::min(kNB, d - kb);
@@ -876,32 +1021,16 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream
                          rest, rest, nb);
     }
   }
-  hipLaunchKernelGGL(k_identity, dim3(nblocks(int64_t(d) * d)), dim3(kBlock), 0, st, X, d);
-  // forward: L Y = I (Y lower triangular, block row kb has no entries right of kb+nb)
-  for (int kb = 0; kb < d; kb += kNB) {
-    const int nb = std::min(kNB, d - kb);
-    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d, kBlock / psl::kWave)), dim3(kBlock), 0, st, L,
-                       X, d, kb, 0);
-    const int rest = d - kb - nb;
-    if (rest > 0) {
-      const int ncol = kb + nb;
-      dim3 grid(nblocks(ncol, 64), nblocks(rest, 64));
-      hipLaunchKernelGGL((k_gemm_sub<0, 0, 0>), grid, dim3(kBlock), 0, st,
-                         X + int64_t(kb + nb) * d, d, L + int64_t(kb + nb) * d + kb, d,
-                         X + int64_t(kb) * d, d, rest, ncol, nb);
-    }
-  }
-  // backward: L^T X = Y
-  for (int kb = ((d - 1) / kNB) * kNB; kb >= 0; kb -= kNB) {
-    const int nb = std::min(kNB, d - kb);
-    hipLaunchKernelGGL(k_trsm_cols, dim3(nblocks(d, kBlock / psl::kWave)), dim3(kBlock), 0, st, L,
-                       X, d, kb, 1);
-    if (kb > 0) {
-      dim3 grid(nblocks(d, 64), nblocks(kb, 64));
-      hipLaunchKernelGGL((k_gemm_sub<1, 0, 0>), grid, dim3(kBlock), 0, st, X, d,
-                         L + int64_t(kb) * d, d, X + int64_t(kb) * d, d, kb, d, nb);
-    }
-  }
+  // L^-1: diagonal blocks, then one block diagonal per launch (into X); E^-1 = L^-T L^-1
+  // as a block Gram product into L's storage (the factor is no longer needed), copied to X
+  const int nblk = (d + kNB - 1) / kNB;
+  hipLaunchKernelGGL(k_trtri_diag, dim3(nblk), dim3(psl::kWave), 0, st, L, X, d);
+  for (int s = 1; s < nblk; ++s)
+    hipLaunchKernelGGL(k_trtri_off, dim3(nblk - s), dim3(kBlock), 0, st, L, X, d, s);
+  hipLaunchKernelGGL(k_lower_gram, dim3(nblk * (nblk + 1) / 2), dim3(kBlock), 0, st, X, L, d,
+                     nblk);
+  PSL_HIP(hipMemcpyAsync(X, L, sizeof(double) * size_t(d) * size_t(d), hipMemcpyDeviceToDevice,
+                         st));
   PSL_HIP(hipGetLastError());
   return PSL_OK;
 }

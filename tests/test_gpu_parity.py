@@ -120,6 +120,8 @@ OP_CASES = [("c1", 1), ("c2", 4), ("chan", 0)]
 def _op_problem(name, scale):
     if name == "chan":
         return pi.channelized(48, 40, 24, contrast=1e6, corr_len=6.0, nsub=(6, 5, 3), seed=8)
+    if name == "chan2":
+        return pi.channelized(64, 48, 32, contrast=1e4, corr_len=6.0, nsub=(8, 6, 3), seed=9)
     return pi.config(name, scale=scale)
 
 
@@ -137,8 +139,11 @@ def test_apply_A(gpu_lib, name, scale):
     assert np.all(np.abs(q - ref) <= bound)
 
 
-@pytest.mark.parametrize("name,scale", OP_CASES)
+@pytest.mark.parametrize("name,scale", OP_CASES + [("chan2", 0)])
 def test_coarse_matrix_and_inverse(gpu_lib, name, scale):
+    """E against the oracle's Z^T A Z, and E^-1 E = I to within the conditioning; the
+    cases span one to eight 64-wide blocks of the blocked factor and inverse, with and
+    without a ragged last block."""
     psl = gpu_lib
     p = _op_problem(name, scale)
     say(f"coarse E {name}/{scale}")
@@ -153,6 +158,7 @@ def test_coarse_matrix_and_inverse(gpu_lib, name, scale):
     cond = np.linalg.cond(Eref)
     err = np.linalg.norm(Einv @ Eref - np.eye(d), 2)
     assert err <= max(1e-12, 2e-12 * cond), (err, cond)
+    assert np.array_equal(Einv, Einv.T)   # the Gram product writes both triangles
 
 
 @pytest.mark.parametrize("name,scale", OP_CASES)
