@@ -1204,10 +1204,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   PSL_TRY(dalloc(c, &c->slot, n));
   int32_t* flags = nullptr;  // 0 diag, 1 tile overflow, 2 empty column, 3 label range, 4 E pivot
   PSL_TRY(dalloc(c, &flags, 8));
-  auto free_flags = [&]() {
-    
-    flags = nullptr;
-  };
+  auto free_flags = [&]() { flags = nullptr; };   // arena memory, freed with the context
   int32_t hflags[8] = {0};
   auto read_flags = [&]() -> int {
     if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -1232,9 +1229,6 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
                      flags + 3);
   hipLaunchKernelGGL(k_diag, dim3(nblocks(n)), dim3(kBlock), 0, st, gd, c->Tx, c->Ty, c->Tz,
                      c->invdiag, c->invdiag32, flags);
-  if (read_flags()) PSL_FAIL(PSL_EHIP);
-  if (hflags[3]) PSL_FAIL(PSL_EINVAL);  // a label outside [0, d)
-  if (hflags[0]) PSL_FAIL(PSL_ENOTSPD);
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfx)), dim3(kBlock), 0, st, c->Tx, c->Tx32, nfx);
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfy)), dim3(kBlock), 0, st, c->Ty, c->Ty32, nfy);
   hipLaunchKernelGGL(k_cast_f32, dim3(nblocks(nfz)), dim3(kBlock), 0, st, c->Tz, c->Tz32, nfz);
@@ -1247,8 +1241,6 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   for (;;) {
     c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
     c->ntiles = int(c->h_tiles.size());
-    
-    
     c->tiles = nullptr;
     c->tile_lab = nullptr;
     if (dalloc(c, &c->tiles, c->ntiles) || dalloc(c, &c->tile_lab, int64_t(c->ntiles) * kMaxSlots))
@@ -1258,26 +1250,16 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
       PSL_FAIL(PSL_EHIP);
     hipLaunchKernelGGL(k_tile_labels, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles,
                        c->labels, c->tile_lab, c->tiles, c->slot, flags + 1);
+    // the first read also reports the label-range and diagonal checks above (the tile
+    // pass only compares labels, so it is safe on out-of-range values)
     if (read_flags()) PSL_FAIL(PSL_EHIP);
+    if (hflags[3]) PSL_FAIL(PSL_EINVAL);  // a label outside [0, d)
     if (hflags[0]) PSL_FAIL(PSL_ENOTSPD);
     if (!hflags[1]) break;
     if (tile_max == 1) PSL_FAIL(PSL_EINVAL);
     tile_max = std::max(1, tile_max / 2);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, flags, 0, int64_t(8));
   }
-  if (hipMemcpyAsync(c->h_tiles.data(), c->tiles, sizeof(Tile) * c->ntiles,
-                     hipMemcpyDeviceToHost, st) ||
-      hipStreamSynchronize(st))
-    PSL_FAIL(PSL_EHIP);
-  c->nslot_max = 1;
-  int max_cells = 1;
-  for (const Tile& t : c->h_tiles) {
-    c->nslot_max = std::max(c->nslot_max, t.nslot);
-    max_cells = std::max(max_cells, t.ncell);
-  }
-  c->tile_max = max_cells;
-  c->cpt = (max_cells + kBlock - 1) / kBlock;
-
   // label -> partial lists
   const int nparts = c->ntiles * kMaxSlots;
   int32_t* cnt = nullptr;
@@ -1294,10 +1276,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
                      nparts, c->lab_ptr, cnt, c->lab_part, d);
   hipLaunchKernelGGL(k_lab_sort, dim3(nblocks(d)), dim3(kBlock), 0, st, c->lab_ptr,
                      c->lab_part, d, flags + 2);
-  if (dalloc(c, &c->slot_pos, nparts)) {
-    
-    PSL_FAIL(PSL_ENOMEM);
-  }
+  if (dalloc(c, &c->slot_pos, nparts)) PSL_FAIL(PSL_ENOMEM);
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->slot_pos, 0,
                      int64_t(nparts));
   hipLaunchKernelGGL(k_slot_pos, dim3(nblocks(nparts)), dim3(kBlock), 0, st, c->lab_ptr,
@@ -1305,23 +1284,29 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
 
   // interface rows of A Z
   int32_t* tile_cnt = nullptr;
-  if (dalloc(c, &tile_cnt, c->ntiles + 1) || dalloc(c, &c->az_ptr, c->ntiles + 1)) {
-    
+  if (dalloc(c, &tile_cnt, c->ntiles + 1) || dalloc(c, &c->az_ptr, c->ntiles + 1))
     PSL_FAIL(PSL_ENOMEM);
-  }
   hipLaunchKernelGGL(k_az_count, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
                      c->Ty, c->Tz, c->labels, tile_cnt);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, tile_cnt, c->az_ptr, c->ntiles);
+
+  // one round trip for every size the host needs: the tiles with their label counts, the
+  // number of cut faces and of label partials
   int32_t m = 0;
-  if (hipMemcpyAsync(&m, c->az_ptr + c->ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
+  if (hipMemcpyAsync(c->h_tiles.data(), c->tiles, sizeof(Tile) * c->ntiles,
+                     hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(&m, c->az_ptr + c->ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
       hipMemcpyAsync(&c->npart, c->lab_ptr + d, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
-      hipStreamSynchronize(st)) {
-    
-    
+      hipStreamSynchronize(st))
     PSL_FAIL(PSL_EHIP);
+  c->nslot_max = 1;
+  int max_cells = 1;
+  for (const Tile& t : c->h_tiles) {
+    c->nslot_max = std::max(c->nslot_max, t.nslot);
+    max_cells = std::max(max_cells, t.ncell);
   }
-  
-  
+  c->tile_max = max_cells;
+  c->cpt = (max_cells + kBlock - 1) / kBlock;
   c->m_az = m;
   if (dalloc(c, &c->az_cell, m) || dalloc(c, &c->az_lab, m) || dalloc(c, &c->az_oth, m) ||
       dalloc(c, &c->az_t, m) || dalloc(c, &c->az_t32, m))
@@ -1330,32 +1315,15 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
                      c->Ty, c->Tz, c->labels, c->az_ptr, c->az_cell, c->az_lab, c->az_oth,
                      c->az_t, c->az_t32);
 
-  // E = Z^T A Z, then Cholesky and inverse
-  const int64_t dd = int64_t(d) * d;
-  double* Lw = nullptr;
-  if (dalloc(c, &c->E, dd) || dalloc(c, &c->Einv, dd) || dalloc(c, &Lw, dd)) {
-    
-    PSL_FAIL(PSL_ENOMEM);
-  }
-  hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, c->lab_ptr, c->lab_part, c->az_ptr,
-                     c->az_lab, c->az_oth, c->az_t, c->E, d);
-  if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st)) {
-    
-    PSL_FAIL(PSL_EHIP);
-  }
-  int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, st);
-  if (rc == PSL_OK) rc = read_flags();
-  
-  if (rc != PSL_OK) PSL_FAIL(rc);
-  if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range
-  if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
-
   // coarse GEMV layout and solve work space
   c->coarse_blocks = (d + psl::kCoarseRows - 1) / psl::kCoarseRows;
   // coarse workgroups stage all of s (d <= 4096 doubles of LDS) and each re-sums the
   // label partials; beyond ~4M partial reads a separate reduction kernel is cheaper
   c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
-  if (dalloc(c, &c->zq, std::max(1, c->npart)) || dalloc(c, &c->zr, std::max(1, c->npart)) ||
+  const int64_t dd = int64_t(d) * d;
+  double* Lw = nullptr;
+  if (dalloc(c, &c->E, dd) || dalloc(c, &c->Einv, dd) || dalloc(c, &Lw, dd) ||
+      dalloc(c, &c->zq, std::max(1, c->npart)) || dalloc(c, &c->zr, std::max(1, c->npart)) ||
       dalloc(c, &c->red, int64_t(c->ntiles) * 4) || dalloc(c, &c->s, d) || dalloc(c, &c->e, d) ||
       dalloc(c, &c->sr, d) || dalloc(c, &c->er, d) || dalloc(c, &c->cpart, 4 * c->coarse_blocks) ||
       dalloc(c, &c->r64, n) || dalloc(c, &c->t64, n) || dalloc(c, &c->sc, 1))
@@ -1364,9 +1332,19 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   c->h_sc = static_cast<psl::Scalars*>(psl_internal_pinned_get(sizeof(psl::Scalars)));
   if (!c->h_sc) PSL_FAIL(PSL_ENOMEM);
   std::memset(c->h_sc, 0, sizeof(psl::Scalars));
-  if (hipMemcpyAsync(c->sc, c->h_sc, sizeof(psl::Scalars), hipMemcpyHostToDevice, st) ||
-      hipStreamSynchronize(st))
+  if (hipMemcpyAsync(c->sc, c->h_sc, sizeof(psl::Scalars), hipMemcpyHostToDevice, st))
     PSL_FAIL(PSL_EHIP);
+
+  // E = Z^T A Z, then Cholesky and inverse; the flags read waits for all of the set-up
+  hipLaunchKernelGGL(k_E_rows, dim3(d), dim3(kBlock), 0, st, c->lab_ptr, c->lab_part, c->az_ptr,
+                     c->az_lab, c->az_oth, c->az_t, c->E, d);
+  if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st))
+    PSL_FAIL(PSL_EHIP);
+  int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, st);
+  if (rc == PSL_OK) rc = read_flags();
+  if (rc != PSL_OK) PSL_FAIL(rc);
+  if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range
+  if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
   free_flags();
 #undef PSL_FAIL
   *out = c;
