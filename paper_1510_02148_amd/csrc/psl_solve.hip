@@ -53,6 +53,24 @@ struct Geo {
   const Tile* tiles;
 };
 
+// A tile descriptor is read-only during every launch and the same for the whole
+// workgroup; reading it through the constant address space lets the compiler use one
+// scalar load instead of a vector load that every later address waits for.
+__device__ inline Tile load_tile(const Tile* tiles, int t) {
+  using ConstTile = const __attribute__((address_space(4))) Tile;
+  const ConstTile* p = (const ConstTile*)(tiles + t);   // address-space cast: no-op for global
+  Tile T;
+  T.x0 = p->x0;
+  T.y0 = p->y0;
+  T.z0 = p->z0;
+  T.sx = p->sx;
+  T.sy = p->sy;
+  T.sz = p->sz;
+  T.ncell = p->ncell;
+  T.nslot = p->nslot;
+  return T;
+}
+
 // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of tiles
 // (a slab of the grid) so that neighbouring tiles share an L2.
 __device__ inline int tile_of_block(int b, int ntiles) {
@@ -110,7 +128,7 @@ __global__ void __launch_bounds__(kBlock)
               double* zq, double* red) {
   __shared__ double lds[(NS + 1) * kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int sxy = nx * ny;
@@ -198,8 +216,10 @@ __device__ inline void cg_stencil_tile(int t, Geo g, const R* __restrict__ Tx,
   using psl::ld;
   constexpr int NA = NS + 3 + (RP ? NS : 0);
   __shared__ double lds[NA * kNW];
-  if (sc->done) return;
-  const Tile T = g.tiles[t];
+  // the stop flag is read first but acted on once the cell loads are in flight: the
+  // launch then costs one memory round trip less on its critical path
+  const bool stop = sc->done != 0;
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int sxy = nx * ny;
@@ -235,6 +255,7 @@ __device__ inline void cg_stencil_tile(int t, Geo g, const R* __restrict__ Tx,
       sl[k] = ld(slot, c);
     }
   }
+  if (stop) return;
   double acc[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc[k] = 0.0;
@@ -461,8 +482,8 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
   __shared__ R corr[kTileMax];            // A Z e, rounded to the working precision
   __shared__ R corr2[RP ? kTileMax : 1];  // A Z er
   __shared__ double coef[3];              // alpha, beta, go (1) / stop (0)
-  if (sc->done) return;
-  const Tile T = g.tiles[t];
+  const bool stop = sc->done != 0;        // acted on once the cell loads are in flight
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   // issue the cell loads first so their latency overlaps the reductions below
   int cc[CPT];
@@ -485,6 +506,7 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
       dv[k] = ld(invd, c);
     }
   }
+  if (stop) return;
   if (threadIdx.x < psl::kWave) {
     // one wave reduces the coarse partials (fixed order) and decides the step
     double alpha_d = 1e-3, beta_d = 0.5, go = 1.0;
@@ -616,9 +638,9 @@ __global__ void __launch_bounds__(kBlock)
   using psl::st;
   __shared__ double lds[(NS + 1) * kNW];
   __shared__ double lds2[2 * kNW];
-  if (sc->done) return;
+  const bool stop = sc->done != 0;   // acted on once the cell loads are in flight
   const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int sxy = nx * ny;
@@ -663,6 +685,7 @@ __global__ void __launch_bounds__(kBlock)
       sl[k] = ld(slot, c);
     }
   }
+  if (stop) return;
   // rho and ||r||^2 of the current residual, summed from the update partials
   double rs[2] = {0.0, 0.0};
   for (int i = threadIdx.x; i < GU; i += kBlock) {
@@ -742,12 +765,12 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ R corr[kTileMax];   // A Z e, rounded to the working precision
   __shared__ double coef[2];     // alpha, go (1) / stop (0)
   __shared__ double lds[2 * kNW];
-  if (sc->done) return;
+  const bool stop = sc->done != 0;   // acted on once the first tile's loads are in flight
   double acc[2] = {0.0, 0.0};
   bool first = true;
   for (int tb = blockIdx.x; tb < g.ntiles; tb += gridDim.x) {
     const int t = tile_of_block(tb, g.ntiles);
-    const Tile T = g.tiles[t];
+    const Tile T = load_tile(g.tiles, t);
     const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
     int cc[CPT];
     R qv[CPT], rv[CPT], pv[CPT], xv[CPT], dv[CPT];
@@ -767,6 +790,7 @@ __global__ void __launch_bounds__(kBlock)
         dv[k] = ld(invd, c);
       }
     }
+    if (stop) return;
     if (first && threadIdx.x < psl::kWave) {
       // one wave reduces the coarse partials (fixed order) and takes the step decision
       double alpha_d = 1e-3, go = 1.0;
@@ -841,7 +865,7 @@ __global__ void __launch_bounds__(kBlock)
   double acc[2] = {0.0, 0.0};
   for (int tb = blockIdx.x; tb < g.ntiles; tb += gridDim.x) {
     const int t = tile_of_block(tb, g.ntiles);
-    const Tile T = g.tiles[t];
+    const Tile T = load_tile(g.tiles, t);
     const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
     for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
       int ix, iy, iz;
@@ -913,7 +937,7 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double corr[kTileMax];
   __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
+  const Tile T = load_tile(g.tiles, t);
   tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
                   static_cast<const double*>(nullptr), corr, corr);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
@@ -938,7 +962,7 @@ __global__ void __launch_bounds__(kBlock)
          const int32_t* __restrict__ slot_pos, double* zq) {
   __shared__ double lds[NS * kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   double acc[NS];
 #pragma unroll
@@ -961,7 +985,7 @@ __global__ void __launch_bounds__(kBlock) k_norm2(Geo g, const double* __restric
                                                   double* red) {
   __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
-  const Tile T = g.tiles[t];
+  const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   double acc[1] = {0.0};
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
