@@ -250,6 +250,30 @@ def test_solve_deterministic(gpu_lib):
     assert torch.equal(x1, x3)
 
 
+@pytest.mark.parametrize("name,scale", [("c2", 4), ("c2", 1)], ids=["graph-replay", "direct"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_result_independent_of_host_checks(gpu_lib, name, scale, mode):
+    """How many iterations the host enqueues between looks at the device (check_every, the
+    rate-based tail, the first-enqueue estimate from an earlier solve) only changes how many
+    launches exit at once: x and the iteration count are bit-identical. Covers the graph
+    replay (small grids) and the direct launches (large grids)."""
+    psl = gpu_lib
+    p = pi.config(name, scale=scale)
+    say(f"host-check independence {name}/{scale} {mode}")
+    md = psl.FP64 if mode == "fp64" else psl.MIXED
+    b = dev(p.q)
+    runs = []
+    # (check_every, fresh context): a reused context starts from its iteration history
+    for check, fresh in ((2, True), (16, False), (64, True), (16, False)):
+        if fresh:
+            s = _setup(psl, p)
+        x, st = psl.psl_solve(s.ctx, b, mode=md, check_every=check)
+        assert st["status"] == 0
+        runs.append((x, st["iters"], st["outer"]))
+    for x, it, outer in runs[1:]:
+        assert torch.equal(x, runs[0][0]) and it == runs[0][1] and outer == runs[0][2]
+
+
 def test_x0_independence(gpu_lib):
     psl = gpu_lib
     p = pi.config("c2", scale=4)
