@@ -15,7 +15,9 @@ method in reservoir simulation") by eye:
   * ``levelset_labels`` -- subdomain-levelset deflation vectors: indicator
     vectors (Section 3.2, eq. "domdefl") of every (subdomain, permeability
     class) region (Section 3.2, subdomain-levelset figure; Vuik02 choice of
-    vectors on both high and low layers).
+    vectors on both high and low layers). ``levelset_components`` splits each
+    region into its connected components (a reading of the automatic
+    construction Section 3.2 defers).
   * ``coarse_matrix`` -- E = Z^T A Z (Definition 3.1, eq. "E").
   * ``dpcg`` -- CG on the deflated system P1 A xhat = P1 b (eq. "defsys") with
     Jacobi preconditioning applied after P1 and E built from A itself
@@ -170,6 +172,50 @@ def levelset_labels(grid, K, nsub, thr, cls=None, ncls=None) -> Tuple[np.ndarray
     key = sub * ncls + c
     present, labels = np.unique(key, return_inverse=True)
     return labels.astype(np.int32), int(present.size)
+
+
+def levelset_components(grid, K, nsub, thr, cls=None, ncls=None) -> Tuple[np.ndarray, int]:
+    """Automatic subdomain-levelset construction, connected-components reading.
+
+    Section 3.2 draws every region as one connected piece and leaves an automatic
+    construction for later. Here each non-empty (subdomain, class) region is split into
+    its face-connected components (cells sharing a face: 6 neighbours in 3D, 4 in 2D),
+    and every component is one deflation vector. Columns are ordered by the smallest
+    cell index (c = ix + nx (iy + ny iz)) of their component. The components come from
+    ``scipy.sparse.csgraph.connected_components`` on the graph whose edges join
+    face neighbours with equal (subdomain, class) key.
+    """
+    from scipy.sparse.csgraph import connected_components
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    sub = subdomain_index(grid, nsub)
+    if cls is None:
+        c = levelset_class(K, thr)
+        ncls = len(thr) + 1
+    else:
+        c = np.asarray(cls, dtype=np.int64)
+        if ncls is None:
+            ncls = int(c.max()) + 1
+    key = (sub * ncls + c).reshape(nz, ny, nx)
+    idx = np.arange(n, dtype=np.int64).reshape(nz, ny, nx)
+    rows, cols = [], []
+    for axis in (2, 1, 0):                      # x, y, z neighbours
+        a = [slice(None)] * 3
+        b = [slice(None)] * 3
+        a[axis] = slice(0, -1)
+        b[axis] = slice(1, None)
+        same = key[tuple(a)] == key[tuple(b)]
+        rows.append(idx[tuple(a)][same])
+        cols.append(idx[tuple(b)][same])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    graph = sp.csr_matrix((np.ones(rows.size), (rows, cols)), shape=(n, n))
+    ncomp, comp = connected_components(graph, directed=False)
+    first = np.full(ncomp, n, dtype=np.int64)
+    np.minimum.at(first, comp, np.arange(n, dtype=np.int64))
+    order = np.empty(ncomp, dtype=np.int64)
+    order[np.argsort(first, kind="stable")] = np.arange(ncomp)
+    return order[comp].astype(np.int32), int(ncomp)
 
 
 def deflation_matrix(labels, d) -> sp.csr_matrix:

@@ -9,7 +9,8 @@ Sources of truth used (none of them is the oracle's own formula retyped):
   * series-resistance closed forms of 1D Darcy flow (discrete flux balance),
   * second differences of polynomials on homogeneous media,
   * row sums = boundary transmissibility, symmetry, M-matrix sign pattern,
-  * brute-force pure-Python labelling on tiny grids,
+  * brute-force pure-Python labelling on tiny grids (regions and their connected
+    components), scipy.ndimage.label per region,
   * brute-force face sums for the coarse matrix E = Z^T A Z,
   * textbook Jacobi-PCG (scipy.sparse.linalg.cg) when no vector is deflated,
   * dense direct solves (numpy.linalg.solve),
@@ -203,6 +204,90 @@ def pin_labels_layered2d(O):
     assert np.array_equal(ZtZ, 128 * np.eye(32)), "Z^T Z != 128 I"
 
 
+def _components_bruteforce(grid, K, nsub, thr, cls=None, ncls=None):
+    """Breadth-first search over face neighbours with equal (subdomain, class) key,
+    started from each unlabelled cell in natural order: labels come out ordered by the
+    smallest cell index of their component."""
+    nx, ny, nz = grid
+    keys, _ = _labels_bruteforce(grid, K, nsub, thr, cls=cls, ncls=ncls)   # rank of key
+    n = nx * ny * nz
+    lab = [-1] * n
+    d = 0
+    for start in range(n):
+        if lab[start] >= 0:
+            continue
+        lab[start] = d
+        queue = [start]
+        while queue:
+            c = queue.pop()
+            ix, iy, iz = c % nx, (c // nx) % ny, c // (nx * ny)
+            for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                jx, jy, jz = ix + dx, iy + dy, iz + dz
+                if 0 <= jx < nx and 0 <= jy < ny and 0 <= jz < nz:
+                    m = jx + nx * (jy + ny * jz)
+                    if lab[m] < 0 and keys[m] == keys[c]:
+                        lab[m] = d
+                        queue.append(m)
+        d += 1
+    return np.array(lab, dtype=np.int32), d
+
+
+def pin_components_bruteforce(O):
+    """Connected-component labels against a pure-Python search on tiny grids (3D and 2D,
+    several partitions and thresholds, manual classes)."""
+    g = np.random.Generator(np.random.PCG64(14))
+    for grid, nsub, thr in (((7, 5, 4), (2, 2, 2), [0.3, 2.0]),
+                            ((9, 7, 1), (3, 2, 1), [1.0]),
+                            ((6, 6, 6), (1, 1, 1), [0.2, 1.0, 3.0]),
+                            ((8, 3, 5), (4, 3, 1), [0.7])):
+        n = grid[0] * grid[1] * grid[2]
+        K = np.exp(1.5 * g.standard_normal(n))
+        lab, d = O.levelset_components(grid, K, nsub, np.array(thr))
+        ref, dref = _components_bruteforce(grid, K, nsub, thr)
+        assert d == dref and np.array_equal(lab, ref), f"components differ on {grid} {nsub}"
+    grid = (6, 5, 4)
+    cls = g.integers(0, 3, size=120)
+    lab, d = O.levelset_components(grid, None, (2, 1, 2), None, cls=cls, ncls=3)
+    ref, dref = _components_bruteforce(grid, None, (2, 1, 2), None, cls=cls, ncls=3)
+    assert d == dref and np.array_equal(lab, ref), "manual-class components differ"
+
+
+def pin_components_ndimage(O):
+    """The same partition as scipy.ndimage.label (face connectivity) applied to each
+    (subdomain, class) region separately, on a channel-like field; and on the 64x64
+    layered case, where every region is connected, the plain subdomain-levelset
+    partition."""
+    from scipy import ndimage
+    grid = (24, 20, 12)
+    nx, ny, nz = grid
+    g = np.random.Generator(np.random.PCG64(15))
+    field = ndimage.gaussian_filter(g.standard_normal((nz, ny, nx)), 2.0)
+    K = np.where(field > 0.1, 1.0, 1e-4).reshape(-1)
+    nsub, thr = (3, 2, 2), np.array([1e-2])
+    lab, d = O.levelset_components(grid, K, nsub, thr)
+    keys, _ = O.levelset_labels(grid, K, nsub, thr)
+    keys = keys.reshape(nz, ny, nx)
+    structure = ndimage.generate_binary_structure(3, 1)
+    parts = set()
+    for k in np.unique(keys):
+        comp, num = ndimage.label(keys == k, structure=structure)
+        for j in range(1, num + 1):
+            parts.add(frozenset(np.flatnonzero(comp.reshape(-1) == j).tolist()))
+    mine = {frozenset(np.flatnonzero(lab == j).tolist()) for j in range(d)}
+    assert d == len(parts) and mine == parts, "partition differs from ndimage.label"
+    assert d > len(np.unique(keys)), "the field should split some regions"
+    # columns ordered by their first cell
+    first = [int(np.flatnonzero(lab == j)[0]) for j in range(d)]
+    assert first == sorted(first)
+    nx = ny = 64
+    K = np.repeat(np.where((np.arange(ny) // 8) % 2 == 0, 1.0, 1e-4), nx)
+    lab, d = O.levelset_components((nx, ny, 1), K, (4, 4, 1), np.array([1e-2]))
+    lab0, d0 = O.levelset_labels((nx, ny, 1), K, (4, 4, 1), np.array([1e-2]))
+    assert d == d0 == 32
+    assert {frozenset(np.flatnonzero(lab == j).tolist()) for j in range(d)} == \
+        {frozenset(np.flatnonzero(lab0 == j).tolist()) for j in range(d0)}
+
+
 # ------------------------------------------------------------------ coarse E
 
 def pin_coarse_matrix(O):
@@ -383,7 +468,8 @@ def pin_jump_independence(O):
 
 ALL_PINS = [
     pin_row_sums, pin_symmetric_mmatrix, pin_second_difference, pin_series_resistance,
-    pin_labels_bruteforce, pin_labels_layered2d, pin_coarse_matrix, pin_textbook_pcg,
+    pin_labels_bruteforce, pin_labels_layered2d, pin_components_bruteforce,
+    pin_components_ndimage, pin_coarse_matrix, pin_textbook_pcg,
     pin_full_deflation, pin_dense_direct, pin_projectors, pin_x0_independence,
     pin_theorem21, pin_jump_independence,
 ]

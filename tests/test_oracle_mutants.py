@@ -38,6 +38,11 @@ MUTANTS = {
     "projector_P1_P2_swapped": ("P1 = np.eye(n) - A @ Z @ Einv @ Z.T\n    P2 = np.eye(n) - Z @ Einv @ Z.T @ A",
                                 "P2 = np.eye(n) - A @ Z @ Einv @ Z.T\n    P1 = np.eye(n) - Z @ Einv @ Z.T @ A"),
     "no_initial_deflation": ("rhat = P1(b - A @ xhat)", "rhat = b - A @ xhat"),
+    "components_ignore_class": ("key = (sub * ncls + c).reshape(nz, ny, nx)",
+                                "key = (sub * ncls + 0 * c).reshape(nz, ny, nx)"),
+    "components_no_z_faces": ("for axis in (2, 1, 0):", "for axis in (2, 1):"),
+    "components_reverse_order": ("order[np.argsort(first, kind=\"stable\")] = np.arange(ncomp)",
+                                 "order[np.argsort(-first, kind=\"stable\")] = np.arange(ncomp)"),
 }
 
 
