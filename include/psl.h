@@ -147,6 +147,20 @@ int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
                 int32_t* labels, int32_t* d, void* stream);
 
 /*
+ * psl_build_Z_cc -- automatic subdomain-levelset construction: like psl_build_Z, but
+ * every (subdomain, class) region is split into its face-connected components (cells
+ * sharing a face: 6 neighbours in 3D, 4 in 2D), one deflation vector each. Section 3.2
+ * draws every region as one connected piece and leaves an automatic construction for
+ * later; this is its connected-components reading. Same arguments, conventions and
+ * errors as psl_build_Z. The columns are ordered by the smallest cell index
+ * (c = ix + nx (iy + ny iz)) of their component. Integer result, bit-exact and
+ * independent of thread scheduling. Uses n + 2n/1024 int32 of temporary device memory.
+ */
+int psl_build_Z_cc(const psl_grid* g, const double* K, const int32_t nsub[3],
+                   const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                   int32_t* labels, int32_t* d, void* stream);
+
+/*
  * psl_setup_E -- build the deflation operators once (Definition 3.1): copies of the
  * transmissibilities, diag(A), the interface rows of A Z, E = Z^T A Z assembled in
  * float64 from the faces, its Cholesky factor E = L L^T and E^-1 (float64).

@@ -341,6 +341,217 @@ extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsu
 }
 
 // ---------------------------------------------------------------------------------------
+// psl_build_Z_cc: connected components of the (subdomain, class) regions
+// ---------------------------------------------------------------------------------------
+// Union-find over face neighbours with equal key. A union always hangs the larger root
+// under the smaller one, so whatever order the atomics land in, the final root of every
+// component is its smallest cell index; parent[c] <= c at all times, so every search
+// ends. The parent array is read and written with device-scope atomics (coherent across
+// the XCDs' L2 caches).
+__device__ inline int cc_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int cc_find(int32_t* parent, int x) {
+  int cur = x;
+  int next = cc_load(parent + cur);
+  while (next != cur) {
+    const int up = cc_load(parent + next);
+    if (up != next)   // path halving: cur is not a root, so no union targets it
+      __hip_atomic_store(parent + cur, up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cur = next;
+    next = up;
+  }
+  return cur;
+}
+
+__device__ inline void cc_union(int32_t* parent, int a, int b) {
+  a = cc_find(parent, a);
+  b = cc_find(parent, b);
+  while (a != b) {
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    int expected = a;   // a must still be a root
+    if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return;
+    a = cc_find(parent, expected);   // a was hung under a smaller root meanwhile
+    b = cc_find(parent, b);
+  }
+}
+
+__global__ void k_cc_init(int n, int nx, int ny, int nz, int sx, int sy, int sz, int ncls,
+                          const double* K, const int32_t* cls, ThrPack thr, int nkeys,
+                          int32_t* key, int32_t* parent, int32_t* bad) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k = cell_key(c, nx, ny, nz, sx, sy, sz, ncls, K, cls, thr);
+  if (k < 0 || k >= nkeys) bad[0] = 1;
+  key[c] = k;
+  parent[c] = c;
+}
+
+__global__ void k_cc_hook(int n, int nx, int ny, int nz, const int32_t* __restrict__ key,
+                          int32_t* parent) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int ix = c % nx, iy = (c / nx) % ny, iz = c / (nx * ny);
+  const int k = key[c];
+  if (ix + 1 < nx && key[c + 1] == k) cc_union(parent, c, c + 1);
+  if (iy + 1 < ny && key[c + nx] == k) cc_union(parent, c, c + nx);
+  if (iz + 1 < nz && key[c + nx * ny] == k) cc_union(parent, c, c + nx * ny);
+}
+
+// Every cell points straight at its root. The walk does not halve paths: a halving
+// store from one thread could land after another thread has written the root to that
+// cell and leave it pointing at an intermediate node. Here each thread writes only its
+// own cell, and only the root, so every pointer a walk reads is an ancestor or the root.
+__global__ void k_cc_compress(int n, int32_t* parent) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int r = c;
+  int next = cc_load(parent + r);
+  while (next != r) {
+    r = next;
+    next = cc_load(parent + r);
+  }
+  __hip_atomic_store(parent + c, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kCcBlock = 4 * kBlock;   // cells per counting block (4 consecutive per thread)
+
+// roots (parent[c] == c) per block of kCcBlock cells
+__global__ void __launch_bounds__(kBlock) k_cc_count(int n, const int32_t* parent,
+                                                     int32_t* bsum) {
+  __shared__ int32_t red[kBlock / psl::kWave];
+  const int base = blockIdx.x * kCcBlock + 4 * threadIdx.x;
+  int cnt = 0;
+  for (int u = 0; u < 4; ++u)
+    if (base + u < n && parent[base + u] == base + u) ++cnt;
+  for (int off = psl::kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & (psl::kWave - 1)) == 0) red[threadIdx.x / psl::kWave] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kBlock / psl::kWave; ++w) s += red[w];
+    bsum[blockIdx.x] = s;
+  }
+}
+
+// column of each root = number of roots before it (block offset + exclusive scan in the
+// block, in cell order)
+__global__ void __launch_bounds__(kBlock) k_cc_rank(int n, const int32_t* parent,
+                                                    const int32_t* boff, int32_t* rank) {
+  __shared__ int32_t part[kBlock];
+  const int base = blockIdx.x * kCcBlock + 4 * threadIdx.x;
+  int is_root[4];
+  int cnt = 0;
+  for (int u = 0; u < 4; ++u) {
+    is_root[u] = base + u < n && parent[base + u] == base + u;
+    cnt += is_root[u];
+  }
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = boff[blockIdx.x] + part[threadIdx.x] - cnt;
+  for (int u = 0; u < 4; ++u)
+    if (is_root[u]) rank[base + u] = run++;
+}
+
+// labels[c] = column of c's root (labels may hold the parent array: each cell reads its
+// own entry before writing it)
+__global__ void k_cc_label(int n, const int32_t* parent, const int32_t* rank, int32_t* labels) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  labels[c] = rank[parent[c]];
+}
+
+// argument checks shared by psl_build_Z and psl_build_Z_cc
+static int build_z_args(const psl_grid* g, const double* K, const int32_t nsub[3],
+                        const double* thr, int32_t nthr, const int32_t* cls, int32_t& ncls,
+                        int32_t* labels, int32_t* d, ThrPack& tp, int& nkeys) {
+  if (!grid_ok(g) || !nsub || !labels || !d) return PSL_EINVAL;
+  if (!cls && !K) return PSL_EINVAL;
+  const int ext[3] = {g->nx, g->ny, g->nz};
+  for (int a = 0; a < 3; ++a)
+    if (nsub[a] < 1 || nsub[a] > ext[a]) return PSL_EINVAL;
+  tp = ThrPack{};
+  if (cls) {
+    if (ncls < 1 || ncls > PSL_MAX_THRESHOLDS + 1) return PSL_EINVAL;
+    tp.nthr = 0;
+  } else {
+    if (nthr < 0 || nthr > PSL_MAX_THRESHOLDS || (nthr > 0 && !thr)) return PSL_EINVAL;
+    for (int t = 0; t < nthr; ++t) {
+      if (!std::isfinite(thr[t])) return PSL_EINVAL;
+      if (t > 0 && !(thr[t] > thr[t - 1])) return PSL_EINVAL;
+      tp.t[t] = thr[t];
+    }
+    tp.nthr = nthr;
+    ncls = nthr + 1;
+  }
+  const int64_t nkeys64 = int64_t(nsub[0]) * nsub[1] * nsub[2] * ncls;
+  if (nkeys64 > (int64_t(1) << 26)) return PSL_ENOTSUP;
+  nkeys = int(nkeys64);
+  return PSL_OK;
+}
+
+extern "C" int psl_build_Z_cc(const psl_grid* g, const double* K, const int32_t nsub[3],
+                              const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                              int32_t* labels, int32_t* d, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
+  ThrPack tp;
+  int nkeys = 0;
+  int rc = build_z_args(g, K, nsub, thr, nthr, cls, ncls, labels, d, tp, nkeys);
+  if (rc != PSL_OK) return rc;
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  const int n = nx * ny * nz;
+  const int nblk = (n + kCcBlock - 1) / kCcBlock;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t *key = nullptr, *bsum = nullptr, *boff = nullptr, *bad = nullptr;
+  rc = psl_internal_alloc((void**)&key, sizeof(int32_t) * n);
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bsum, sizeof(int32_t) * nblk);
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&boff, sizeof(int32_t) * (nblk + 1));
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bad, sizeof(int32_t));
+  auto release = [&]() {
+    psl_internal_free(key);
+    psl_internal_free(bsum);
+    psl_internal_free(boff);
+    psl_internal_free(bad);
+  };
+  if (rc != PSL_OK) {
+    release();
+    return rc;
+  }
+  int32_t* parent = labels;   // the output array holds the union-find forest until the end
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, bad, 0, int64_t(1));
+  hipLaunchKernelGGL(k_cc_init, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, nsub[0],
+                     nsub[1], nsub[2], ncls, K, cls, tp, nkeys, key, parent, bad);
+  hipLaunchKernelGGL(k_cc_hook, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, key, parent);
+  hipLaunchKernelGGL(k_cc_compress, dim3(nblocks(n)), dim3(kBlock), 0, st, n, parent);
+  hipLaunchKernelGGL(k_cc_count, dim3(nblk), dim3(kBlock), 0, st, n, parent, bsum);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bsum, boff, nblk);
+  hipLaunchKernelGGL(k_cc_rank, dim3(nblk), dim3(kBlock), 0, st, n, parent, boff, key);
+  hipLaunchKernelGGL(k_cc_label, dim3(nblocks(n)), dim3(kBlock), 0, st, n, parent, key, labels);
+  int32_t h[2] = {0, 0};
+  hipError_t e1 = hipMemcpyAsync(&h[0], boff + nblk, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipMemcpyAsync(&h[1], bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  hipError_t e3 = hipStreamSynchronize(st);
+  release();
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return PSL_EHIP;
+  if (h[1]) return PSL_EINVAL;  // a manual class outside [0, ncls)
+  *d = h[0];
+  return PSL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
 // psl_setup_E kernels
 // ---------------------------------------------------------------------------------------
 struct GridDev {

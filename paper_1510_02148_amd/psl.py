@@ -81,6 +81,8 @@ _assemble = _sig("psl_assemble_tpfa", ctypes.c_int,
                  [ctypes.POINTER(psl_grid), _P, ctypes.c_uint32, _P, _P, _P, _P])
 _build_z = _sig("psl_build_Z", ctypes.c_int,
                 [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
+_build_z_cc = _sig("psl_build_Z_cc", ctypes.c_int,
+                   [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
 _setup_e = _sig("psl_setup_E", ctypes.c_int,
                 [ctypes.POINTER(_P), ctypes.POINTER(psl_grid), _P, _P, _P, _P, _I32, _I32P, _P])
 _setup_e_ex = _sig("psl_setup_E_ex", ctypes.c_int,
@@ -102,7 +104,7 @@ _bench_copy = _sig("psl_bench_copy", ctypes.c_int, [_P, _P, ctypes.c_int64, _P])
 _status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
 _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
 
-EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_setup_E", "psl_setup_E_ex",
+EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E", "psl_setup_E_ex",
             "psl_default_setup_opts", "psl_solve",
             "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
@@ -167,8 +169,9 @@ def psl_assemble_tpfa(grid, K: torch.Tensor, dirichlet_mask: int,
 
 
 def psl_build_Z(grid, K: Optional[torch.Tensor], nsub, thr=None, cls: Optional[torch.Tensor] = None,
-                ncls: int = 0, labels: Optional[torch.Tensor] = None):
-    """Subdomain-levelset labels (int32 device tensor) and d."""
+                ncls: int = 0, labels: Optional[torch.Tensor] = None, components: bool = False):
+    """Subdomain-levelset labels (int32 device tensor) and d; components=True splits every
+    region into its connected components (psl_build_Z_cc)."""
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
     dev = (K if K is not None else cls).device
     labels = torch.empty(n, dtype=torch.int32, device=dev) if labels is None else labels
@@ -179,9 +182,9 @@ def psl_build_Z(grid, K: Optional[torch.Tensor], nsub, thr=None, cls: Optional[t
     d = ctypes.c_int32(0)
     kp = _dev(K, torch.float64, n, "K") if K is not None else ctypes.c_void_p(0)
     cp = _dev(cls, torch.int32, n, "cls") if cls is not None else ctypes.c_void_p(0)
-    _check(_build_z(ctypes.byref(g), kp, ns, th, len(thr), cp, int(ncls),
-                    _dev(labels, torch.int32, n, "labels"), ctypes.byref(d), _stream()),
-           "psl_build_Z")
+    fn, name = (_build_z_cc, "psl_build_Z_cc") if components else (_build_z, "psl_build_Z")
+    _check(fn(ctypes.byref(g), kp, ns, th, len(thr), cp, int(ncls),
+              _dev(labels, torch.int32, n, "labels"), ctypes.byref(d), _stream()), name)
     return labels, int(d.value)
 
 

@@ -107,6 +107,73 @@ def test_labels_full_size(gpu_lib, name):
         assert d == 512 and np.all(np.bincount(ref) == 2048)
 
 
+# connected components (psl_build_Z_cc)
+
+@pytest.mark.parametrize("grid,nsub,thr", LABEL_CASES)
+def test_components_bit_exact(gpu_lib, grid, nsub, thr):
+    """Union-find labels equal the oracle's connected components exactly, and two runs
+    give the same array (the result does not depend on how the atomics interleave)."""
+    psl = gpu_lib
+    say(f"components grid={grid} nsub={nsub} thr={thr}")
+    n = grid[0] * grid[1] * grid[2]
+    K = lognormal(n, 11 + n)
+    lab, d = psl.psl_build_Z(grid, dev(K), nsub, thr, components=True)
+    lab2, d2 = psl.psl_build_Z(grid, dev(K), nsub, thr, components=True)
+    ref, dref = O.levelset_components(grid, K, nsub, np.array(thr))
+    assert d == dref and np.array_equal(host(lab), ref)
+    assert d2 == d and torch.equal(lab, lab2)
+
+
+def test_components_manual_classes(gpu_lib):
+    psl = gpu_lib
+    say("components manual classes")
+    grid = (21, 13, 8)
+    n = 21 * 13 * 8
+    cls = np.random.Generator(np.random.PCG64(5)).integers(0, 3, size=n).astype(np.int32)
+    lab, d = psl.psl_build_Z(grid, None, (3, 2, 2), cls=dev(cls, torch.int32), ncls=3,
+                             components=True)
+    ref, dref = O.levelset_components(grid, None, (3, 2, 2), None, cls=cls, ncls=3)
+    assert d == dref and np.array_equal(host(lab), ref)
+
+
+@pytest.mark.parametrize("contrast", [1e4, 1e6])
+def test_components_full_size(gpu_lib, contrast):
+    """256x256x128 channelized field (8.4 M cells): channels cut into pieces inside many
+    subdomains, so the components outnumber the regions."""
+    psl = gpu_lib
+    p = pi.config("c3", contrast=contrast)
+    say(f"components full size c3 contrast {contrast:g}")
+    Kd = dev(p.K)
+    lab, d = psl.psl_build_Z(p.grid, Kd, p.nsub, list(p.thr), components=True)
+    ref, dref = O.levelset_components(p.grid, p.K, p.nsub, p.thr)
+    _, dplain = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+    assert d == dref and np.array_equal(host(lab), ref)
+    assert d > dplain
+    for _ in range(3):   # millions of racing unions: the same array every time
+        again, d2 = psl.psl_build_Z(p.grid, Kd, p.nsub, list(p.thr), components=True)
+        assert d2 == d and torch.equal(again, lab)
+
+
+def test_components_solve(gpu_lib):
+    """The whole path on component labels: same x as the oracle's DEF1-PCG with the same
+    deflation space, and about its iteration count."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = pi.channelized(48, 40, 24, contrast=1e5, corr_len=6.0, nsub=(6, 5, 3), seed=8)
+    say("components solve chan 48x40x24")
+    s = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr), components=True)
+    x, st = psl.psl_solve(s.ctx, dev(p.q), tol=1e-8)
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    lab, d = O.levelset_components(p.grid, p.K, p.nsub, p.thr)
+    assert d == s.d
+    Z = O.deflation_matrix(lab, d)
+    ref = O.dpcg(A, b, Z, tol=1e-8)
+    xr = O.dpcg(A, b, Z, tol=1e-12).x
+    assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
+    assert np.linalg.norm(host(x) - xr) / np.linalg.norm(xr) <= 1e-6
+    assert abs(st["iters"] - ref.iters) <= max(2, 0.02 * ref.iters)
+
+
 # ------------------------------------------------------------------ operators
 
 def _setup(psl, p):
