@@ -339,6 +339,9 @@ def main():
     ap.add_argument("--test-instances", type=int, default=16)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--loss", default="energy", choices=["energy", "diag", "l2"])
+    ap.add_argument("--labels", default="regions", choices=["regions", "components"],
+                    help="deflation space: one vector per (subdomain, class) region, or per "
+                         "connected component of each region (psl_build_Z_cc)")
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -385,7 +388,8 @@ def main():
     def step(mode):
         t0 = time.perf_counter()
         s = pipeline.setup(prob.grid, K, prob.dirichlet_mask, prob.nsub, list(prob.thr),
-                           tile_cells=tiles["f32" if mode == psl.MIXED else "f64"])
+                           tile_cells=tiles["f32" if mode == psl.MIXED else "f64"],
+                           components=args.labels == "components")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
@@ -481,13 +485,15 @@ def main():
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             A, bh = O.assemble(prob.K, prob.grid, prob.dirichlet_mask, prob.q)
-            lab, dd = O.levelset_labels(prob.grid, prob.K, prob.nsub, prob.thr)
+            label_fn = (O.levelset_components if args.labels == "components"
+                        else O.levelset_labels)
+            lab, dd = label_fn(prob.grid, prob.K, prob.nsub, prob.thr)
             Z = O.deflation_matrix(lab, dd)
             res = O.dpcg(A, bh, Z, tol=prob.tol)
             cpu_s = time.perf_counter() - t0
         xg = x.cpu().numpy()
         cpu = {"value": round(cpu_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"one full {args.workload} solve (assembly, labels, E + Cholesky, "
+               "sample": f"one full {args.workload} solve (assembly, {args.labels} labels, E + Cholesky, "
                          f"DEF1-PCG to 1e-8), {res.iters} iterations, 1 thread",
                "host_cores_available": len(os.sched_getaffinity(0)),
                "gpu_vs_oracle_rel_err": float(np.linalg.norm(xg - res.x) / np.linalg.norm(res.x)),
@@ -501,8 +507,8 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid),
-                   "nsub": list(prob.nsub), "d": d, "tol": prob.tol, "mode": args.mode,
-                   "seed": args.seed, "tile_cells": tiles},
+                   "nsub": list(prob.nsub), "d": d, "labels": args.labels, "tol": prob.tol,
+                   "mode": args.mode, "seed": args.seed, "tile_cells": tiles},
         "converged": bool(ok), "iterations": st["iters"], "outer": st["outer"],
         "relres_true": st["relres_true"], "setup_s": setup_s, "solve_s": solve_s,
         "spmv_gbs": spmv_gbs, "ctx_info": info, "kernels": kernels, "roofline": roofline,
