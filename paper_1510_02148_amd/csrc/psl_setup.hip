@@ -1173,6 +1173,85 @@ __global__ void __launch_bounds__(kBlock) k_trtri_off(const double* L, double* X
   }
 }
 
+// Long block diagonals (s > kTrtriChunk products per block) are split: workgroup (ii, ch)
+// sums the products L_ik X_kj of its chunk of k into a partial block of P, and a second
+// launch adds the chunks in order and applies -X_ii. A workgroup's chain of dependent
+// block products stays at most kTrtriChunk long (on d = 4141 the unsplit form spent up
+// to 65 products in one workgroup).
+constexpr int kTrtriChunk = 8;
+
+__global__ void __launch_bounds__(kBlock) k_trtri_part(const double* L, const double* X, int d,
+                                                       int s, int nchunk, double* P) {
+  __shared__ __align__(16) double sa[kNB][kNB + 2];
+  __shared__ __align__(16) double sb[kNB][kNB + 2];
+  const int ii = blockIdx.x / nchunk, ch = blockIdx.x % nchunk;
+  const int i = ii + s, j = i - s;
+  const int ri = i * kNB, cj = j * kNB, mi = min(kNB, d - ri);
+  const int k0 = j + ch * kTrtriChunk, k1 = min(i, k0 + kTrtriChunk);
+  double acc[4][4] = {};
+  RectRegs ga, gb;   // blocks k < i are full
+  ga.load(L + int64_t(ri) * d + k0 * kNB, d, mi, kNB);
+  gb.load(X + int64_t(k0 * kNB) * d + cj, d, kNB, kNB);
+  for (int k = k0; k < k1; ++k) {
+    ga.store<1>(sa);   // sa[m][r] = L_ik(r, m)
+    gb.store<0>(sb);   // sb[m][c] = X_kj(m, c)
+    __syncthreads();
+    if (k + 1 < k1) {
+      ga.load(L + int64_t(ri) * d + (k + 1) * kNB, d, mi, kNB);
+      gb.load(X + int64_t((k + 1) * kNB) * d + cj, d, kNB, kNB);
+    }
+    block_mac(sa, sb, acc);
+    __syncthreads();
+  }
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double* out = P + int64_t(blockIdx.x) * kNB * kNB;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(4 * ty + u) * kNB + 4 * tx + v] = acc[u][v];
+}
+
+__global__ void __launch_bounds__(kBlock) k_trtri_fin(double* X, int d, int s, int nchunk,
+                                                      const double* P) {
+  __shared__ __align__(16) double sa[kNB][kNB + 2];
+  __shared__ __align__(16) double sb[kNB][kNB + 2];
+  const int ii = blockIdx.x, i = ii + s, j = i - s;
+  const int ri = i * kNB, cj = j * kNB, mi = min(kNB, d - ri);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double t[4][4] = {};
+  for (int ch = 0; ch < nchunk; ++ch) {   // fixed order
+    const double* part = P + int64_t(ii * nchunk + ch) * kNB * kNB;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) t[u][v] += part[(4 * ty + u) * kNB + 4 * tx + v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sb[4 * ty + u][4 * tx + v] = t[u][v];   // T(m, c)
+  stage_rect<1>(sa, X + int64_t(ri) * d + ri, d, mi, mi);                // sa[m][r] = X_ii(r, m)
+  __syncthreads();
+  double y[4][4] = {};
+  block_mac(sa, sb, y);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 4 * ty + u;
+    if (r < mi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[int64_t(ri + r) * d + cj + 4 * tx + v] = -y[u][v];
+  }
+}
+
+// doubles of scratch the split diagonals of cholesky_inverse need (0 when none is split)
+static int64_t trtri_scratch(int d) {
+  const int nblk = (d + kNB - 1) / kNB;
+  int64_t most = 0;
+  for (int s = kTrtriChunk + 1; s < nblk; ++s)
+    most = std::max<int64_t>(most, int64_t(nblk - s) * ((s + kTrtriChunk - 1) / kTrtriChunk));
+  return most * kNB * kNB;
+}
+
 // out = Li^T Li for lower-block-triangular Li (= L^-1), one 64x64 block (I >= J) per
 // workgroup: out_IJ = sum_{k >= I} Li_kI^T Li_kJ, written to (I, J) and mirrored to (J, I).
 __global__ void __launch_bounds__(kBlock) k_lower_gram(const double* Li, double* out, int d,
@@ -1217,7 +1296,8 @@ __global__ void __launch_bounds__(kBlock) k_lower_gram(const double* Li, double*
 
 // E (in L, overwritten by its lower Cholesky factor and then by scratch) -> X = E^-1 =
 // L^-T L^-1. A non-positive pivot raises *bad.
-static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream_t st) {
+static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, double* scratch,
+                            hipStream_t st) {
   for (int kb = 0; kb < d; kb += kNB) {
     const int nb = std::min(kNB, d - kb);
     hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(psl::kWave), 0, st, L, d, kb, bad);
@@ -1236,8 +1316,17 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, hipStream
   // as a block Gram product into L's storage (the factor is no longer needed), copied to X
   const int nblk = (d + kNB - 1) / kNB;
   hipLaunchKernelGGL(k_trtri_diag, dim3(nblk), dim3(psl::kWave), 0, st, L, X, d);
-  for (int s = 1; s < nblk; ++s)
-    hipLaunchKernelGGL(k_trtri_off, dim3(nblk - s), dim3(kBlock), 0, st, L, X, d, s);
+  for (int s = 1; s < nblk; ++s) {
+    const int nchunk = (s + kTrtriChunk - 1) / kTrtriChunk;
+    if (nchunk == 1) {
+      hipLaunchKernelGGL(k_trtri_off, dim3(nblk - s), dim3(kBlock), 0, st, L, X, d, s);
+    } else {
+      hipLaunchKernelGGL(k_trtri_part, dim3((nblk - s) * nchunk), dim3(kBlock), 0, st, L, X, d,
+                         s, nchunk, scratch);
+      hipLaunchKernelGGL(k_trtri_fin, dim3(nblk - s), dim3(kBlock), 0, st, X, d, s, nchunk,
+                         scratch);
+    }
+  }
   hipLaunchKernelGGL(k_lower_gram, dim3(nblk * (nblk + 1) / 2), dim3(kBlock), 0, st, X, L, d,
                      nblk);
   PSL_HIP(hipMemcpyAsync(X, L, sizeof(double) * size_t(d) * size_t(d), hipMemcpyDeviceToDevice,
@@ -1551,7 +1640,10 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
                      c->az_lab, c->az_oth, c->az_t, c->E, d);
   if (hipMemcpyAsync(Lw, c->E, sizeof(double) * dd, hipMemcpyDeviceToDevice, st))
     PSL_FAIL(PSL_EHIP);
-  int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, st);
+  double* tri_scratch = nullptr;
+  const int64_t ntri = trtri_scratch(d);
+  if (ntri > 0 && dalloc(c, &tri_scratch, ntri)) PSL_FAIL(PSL_ENOMEM);
+  int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, tri_scratch, st);
   if (rc == PSL_OK) rc = read_flags();
   if (rc != PSL_OK) PSL_FAIL(rc);
   if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range

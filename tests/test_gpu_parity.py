@@ -189,6 +189,8 @@ def _op_problem(name, scale):
         return pi.channelized(48, 40, 24, contrast=1e6, corr_len=6.0, nsub=(6, 5, 3), seed=8)
     if name == "chan2":
         return pi.channelized(64, 48, 32, contrast=1e4, corr_len=6.0, nsub=(8, 6, 3), seed=9)
+    if name == "chan3":
+        return pi.channelized(96, 80, 48, contrast=1e4, corr_len=6.0, nsub=(16, 10, 6), seed=10)
     return pi.config(name, scale=scale)
 
 
@@ -206,11 +208,12 @@ def test_apply_A(gpu_lib, name, scale):
     assert np.all(np.abs(q - ref) <= bound)
 
 
-@pytest.mark.parametrize("name,scale", OP_CASES + [("chan2", 0)])
+@pytest.mark.parametrize("name,scale", OP_CASES + [("chan2", 0), ("chan3", 0)])
 def test_coarse_matrix_and_inverse(gpu_lib, name, scale):
     """E against the oracle's Z^T A Z, and E^-1 E = I to within the conditioning; the
-    cases span one to eight 64-wide blocks of the blocked factor and inverse, with and
-    without a ragged last block."""
+    cases span one to ~30 64-wide blocks of the blocked factor and inverse (block
+    diagonals longer than eight blocks take the split two-launch form), with and without a
+    ragged last block."""
     psl = gpu_lib
     p = _op_problem(name, scale)
     say(f"coarse E {name}/{scale}")
