@@ -23,6 +23,8 @@ method in reservoir simulation") by eye:
     Jacobi preconditioning applied after P1 and E built from A itself
     (Remark 3.1), then the projection back x = Z E^-1 Z^T b + P2 xhat
     (eq. "projectback").
+  * ``pdgmres`` -- the paper's own solver: right-preconditioned restarted GMRES
+    on P1 A M^-1 with the a priori vectors (Algorithm 1, Section 3.2).
   * ``projectors`` -- dense P1 = I - A Z E^-1 Z^T and P2 = I - Z E^-1 Z^T A
     (eq. "deflops") for identity checks on tiny grids.
 
@@ -348,6 +350,79 @@ def dpcg(A, b, Z, x0=None, tol: float = 1e-8, maxit: int = 10000,
     x = xhat + coarse.correction(b - A @ xhat)
     relres = np.linalg.norm(b - A @ x) / bnorm
     return Result(x, xhat, it, status, relres, np.array(hist), drift)
+
+
+def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000,
+            coarse: Optional[Coarse] = None) -> Result:
+    """Right-preconditioned restarted GMRES(m) on the deflated system with a priori
+    subdomain-levelset vectors (Algorithm 1 with Z, E, P1, P2 and x* formed before the
+    iteration, Section 3.2), M = diag(A):
+
+      r0 = P1 (b - A x0), beta = ||r0||, v1 = r0 / beta
+      Arnoldi with modified Gram-Schmidt on w = P1 A M^-1 v_j, h_ij, h_{j+1,j} = ||w||
+      u = argmin ||beta e1 - Hbar_j u|| (library least squares), stop when its residual is
+      <= tol ||b|| or h_{j+1,j} = 0, or after m steps (restart from x0 + M^-1 V u)
+      at convergence x = P2 x_m + x* = x_m + Z E^-1 Z^T (b - A x_m).
+
+    ``iters`` counts products with A inside the cycles; ``history`` holds the least-
+    squares residual after every step (starting with ||r0||).
+    """
+    n = A.shape[0]
+    b = np.asarray(b, dtype=np.float64)
+    if coarse is None:
+        coarse = Coarse(A, Z)
+    dg = A.diagonal()
+    if not coarse.ok or np.any(dg <= 0):
+        return Result(np.zeros(n), np.zeros(n), 0, "notspd", np.inf, np.zeros(0), 0.0)
+    bnorm = np.linalg.norm(b)
+    x0 = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64)
+    if bnorm == 0.0:
+        return Result(np.zeros(n), np.zeros(n), 0, "ok", 0.0, np.zeros(1), 0.0)
+
+    def P1(v):
+        return v - A @ coarse.correction(v)
+
+    xm = x0.copy()
+    it = 0
+    hist = []
+    status = "ok"
+    while True:
+        r0 = P1(b - A @ xm)
+        beta = np.linalg.norm(r0)
+        if not hist:
+            hist.append(beta)
+        if beta <= tol * bnorm:
+            break
+        if it >= maxit:
+            status = "maxit"
+            break
+        V = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        V[:, 0] = r0 / beta
+        u = np.zeros(0)
+        j_end = 0
+        for j in range(m):
+            w = P1(A @ (V[:, j] / dg))
+            for i in range(j + 1):
+                H[i, j] = w @ V[:, i]
+                w = w - H[i, j] * V[:, i]
+            H[j + 1, j] = np.linalg.norm(w)
+            it += 1
+            rhs = np.zeros(j + 2)
+            rhs[0] = beta
+            u = np.linalg.lstsq(H[:j + 2, :j + 1], rhs, rcond=None)[0]
+            res = np.linalg.norm(rhs - H[:j + 2, :j + 1] @ u)
+            hist.append(res)
+            j_end = j + 1
+            if H[j + 1, j] == 0.0 or res <= tol * bnorm or it >= maxit:
+                break
+            V[:, j + 1] = w / H[j + 1, j]
+        xm = xm + (V[:, :j_end] @ u) / dg
+        if hist[-1] <= tol * bnorm:
+            break
+    x = xm + coarse.correction(b - A @ xm)
+    relres = np.linalg.norm(b - A @ x) / bnorm
+    return Result(x, xm, it, status, relres, np.array(hist), 0.0)
 
 
 def solve(K, grid, dirichlet_mask, q, nsub, thr, tol=1e-8, maxit=10000, x0=None,

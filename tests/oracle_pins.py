@@ -14,6 +14,8 @@ Sources of truth used (none of them is the oracle's own formula retyped):
   * brute-force face sums for the coarse matrix E = Z^T A Z,
   * textbook Jacobi-PCG (scipy.sparse.linalg.cg) when no vector is deflated,
   * dense direct solves (numpy.linalg.solve),
+  * GMRES's defining property: the minimal residual over an explicitly built Krylov
+    space,
   * the projector identities of Definition 3.1 and Section 3.1,
   * Theorem 2.1 (eigenvalue count of the diagonally scaled matrix),
   * jump independence of deflated CG (Section 1).
@@ -288,6 +290,64 @@ def pin_components_ndimage(O):
         {frozenset(np.flatnonzero(lab0 == j).tolist()) for j in range(d0)}
 
 
+def _tiny_system(O, seed, grid=(6, 5, 4), nsub=(2, 2, 1), thr=(0.5,)):
+    nx, ny, nz = grid
+    K = _lognormal(nx * ny * nz, seed)
+    q = np.zeros(nx * ny * nz)
+    q[0], q[-1] = 1.0, -0.5
+    A, b = O.assemble(K, grid, XLO, q)
+    lab, d = O.levelset_labels(grid, K, nsub, np.array(thr))
+    return A, b, O.deflation_matrix(lab, d)
+
+
+def pin_gmres_direct(O):
+    """Deflated GMRES(m) reaches the dense direct solution, with and without restarts and
+    with no deflation vectors at all (d = 0: plain right-preconditioned GMRES)."""
+    for seed, m in ((21, 5), (22, 40)):
+        A, b, Z = _tiny_system(O, seed)
+        xd = np.linalg.solve(A.toarray(), b)
+        for ZZ in (Z, Z[:, :0]):
+            r = O.pdgmres(A, b, ZZ, m=m, tol=1e-12)
+            assert r.status == "ok"
+            assert np.linalg.norm(r.x - xd) <= 1e-9 * np.linalg.norm(xd), (seed, m, ZZ.shape)
+
+
+def pin_gmres_minimal_residual(O):
+    """After k steps of a first cycle the least-squares residual is the smallest
+    ||r0 - B K_k y|| over the Krylov space K_k = span{r0, B r0, ..., B^(k-1) r0} of
+    B = P1 A M^-1 (computed here from an explicit, QR-orthonormalised Krylov basis), and
+    it equals the true deflated residual ||P1 (b - A x_k)|| of the iterate the cycle
+    returns (which checks x_k = x0 + M^-1 V u)."""
+    A, b, Z = _tiny_system(O, 23)
+    Ad = A.toarray()
+    dg = np.diag(Ad)
+    E = (Z.T @ (A @ Z)).toarray()
+    Zd = Z.toarray()
+    P1 = np.eye(Ad.shape[0]) - Ad @ Zd @ np.linalg.solve(E, Zd.T)
+    B = P1 @ Ad / dg[None, :]
+    r0 = P1 @ b
+    for k in range(1, 7):
+        Kk = np.empty((r0.size, k))
+        v = r0.copy()
+        for i in range(k):
+            Kk[:, i] = v
+            v = B @ v
+        Q, _ = np.linalg.qr(Kk)
+        y = np.linalg.lstsq(B @ Q, r0, rcond=None)[0]
+        best = np.linalg.norm(r0 - B @ Q @ y)
+        r = O.pdgmres(A, b, Z, m=k, tol=1e-300, maxit=k)
+        assert abs(r.history[k] - best) <= 1e-9 * np.linalg.norm(r0), (k, r.history[k], best)
+        true_res = np.linalg.norm(P1 @ (b - Ad @ r.xhat))
+        assert abs(true_res - r.history[k]) <= 1e-9 * np.linalg.norm(r0), (k, true_res)
+
+
+def pin_gmres_monotone(O):
+    """The residual of GMRES never grows, inside a cycle or across restarts."""
+    A, b, Z = _tiny_system(O, 24, grid=(9, 8, 5), nsub=(3, 2, 1))
+    r = O.pdgmres(A, b, Z, m=4, tol=1e-10)
+    assert r.status == "ok" and np.all(np.diff(r.history) <= 1e-12 * r.history[0])
+
+
 # ------------------------------------------------------------------ coarse E
 
 def pin_coarse_matrix(O):
@@ -469,7 +529,8 @@ def pin_jump_independence(O):
 ALL_PINS = [
     pin_row_sums, pin_symmetric_mmatrix, pin_second_difference, pin_series_resistance,
     pin_labels_bruteforce, pin_labels_layered2d, pin_components_bruteforce,
-    pin_components_ndimage, pin_coarse_matrix, pin_textbook_pcg,
+    pin_components_ndimage, pin_coarse_matrix, pin_textbook_pcg, pin_gmres_direct,
+    pin_gmres_minimal_residual, pin_gmres_monotone,
     pin_full_deflation, pin_dense_direct, pin_projectors, pin_x0_independence,
     pin_theorem21, pin_jump_independence,
 ]

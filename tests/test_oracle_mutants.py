@@ -41,6 +41,9 @@ MUTANTS = {
     "components_ignore_class": ("key = (sub * ncls + c).reshape(nz, ny, nx)",
                                 "key = (sub * ncls + 0 * c).reshape(nz, ny, nx)"),
     "components_no_z_faces": ("for axis in (2, 1, 0):", "for axis in (2, 1):"),
+    "gmres_left_preconditioned": ("w = P1(A @ (V[:, j] / dg))", "w = P1(A @ V[:, j]) / dg"),
+    "gmres_update_without_Minv": ("xm = xm + (V[:, :j_end] @ u) / dg", "xm = xm + V[:, :j_end] @ u"),
+    "gmres_no_projection_back": ("x = xm + coarse.correction(b - A @ xm)", "x = xm.copy()"),
     "components_reverse_order": ("order[np.argsort(first, kind=\"stable\")] = np.arange(ncomp)",
                                  "order[np.argsort(-first, kind=\"stable\")] = np.arange(ncomp)"),
 }
