@@ -106,6 +106,36 @@ typedef struct {
 /* Fill `o` with the defaults listed above. */
 void psl_default_opts(psl_solve_opts* o);
 
+/* Options of psl_solve_gmres. */
+typedef struct {
+  double  tol;          /* stop when ||b - A x||_2 <= tol * ||b||_2 (default 1e-8) */
+  int32_t maxit;        /* cap on Arnoldi steps over all cycles (default 10000) */
+  int32_t restart;      /* m of GMRES(m): steps per cycle, 1..200 (default 30) */
+  int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
+  int32_t reserved[3];  /* must be 0 */
+} psl_gmres_opts;
+
+/* Fill `o` with the GMRES defaults. */
+void psl_default_gmres_opts(psl_gmres_opts* o);
+
+/*
+ * psl_solve_gmres -- the paper's own solver (Algorithm 1 with the subdomain-levelset
+ * vectors formed a priori, Section 3.2): right-preconditioned restarted GMRES(m) on
+ * P1 A M^-1 y = P1 b, M = diag(A), x_hat = M^-1 y, and at convergence the projection back
+ * x = P2 x_hat + Z E^-1 Z^T b. Float64 throughout. Arnoldi runs classical Gram-Schmidt
+ * twice (the paper writes modified Gram-Schmidt; both span the same Krylov space, and
+ * the repeated classical form needs two batched passes per step instead of j dependent
+ * ones). The least-squares residual decides convergence inside a cycle; every cycle
+ * starts from a freshly formed P1 (b - A x). The host reads one column of the Hessenberg
+ * matrix per step.
+ *   ctx, b, x, st, stream  as for psl_solve; st->iters = Arnoldi steps, st->outer =
+ *   completed cycles. Work space: (m + 1) n doubles for the basis, kept on the context.
+ * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_ENONFINITE,
+ * PSL_EINVAL (options out of range), PSL_ENOMEM.
+ */
+int psl_solve_gmres(psl_ctx* ctx, const double* b, double* x, const psl_gmres_opts* o,
+                    psl_solve_stats* st, void* stream);
+
 /*
  * psl_assemble_tpfa -- face transmissibilities of the cell-centred finite-volume
  * discretisation of -div(K grad p) = q (Section 2, eqs. "pressure"/"mobility" with the

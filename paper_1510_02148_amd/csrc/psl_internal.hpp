@@ -123,6 +123,10 @@ struct psl_ctx {
   double* r64 = nullptr;              // [n] FP64 outer residual
   double* t64 = nullptr;              // [n] FP64 scratch
   double* xbest = nullptr;            // [n] best projected iterate of the current solve
+  double* gm_v = nullptr;             // deflated GMRES: gm_cap basis vectors of n doubles
+  int gm_cap = 0;
+  double* gm_part = nullptr;          // [kGmBlocks * gm_cap] per-workgroup dot partials
+  double* gm_dev = nullptr;           // [3 * gm_cap + 4] dots, norm and step coefficients
   psl::Scalars* sc = nullptr;
   psl::Scalars* h_sc = nullptr;       // pinned host mirror
   psl::VecSet<double> v64;

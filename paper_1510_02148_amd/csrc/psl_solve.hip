@@ -1788,6 +1788,268 @@ extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* s
 }
 
 // =======================================================================================
+// Deflated GMRES (the paper's own solver): right-preconditioned restarted GMRES(m) on
+// P1 A M^-1 with the a priori subdomain-levelset vectors, M = diag(A), float64. Arnoldi
+// uses classical Gram-Schmidt applied twice (two batched dot passes and two batched
+// updates per step instead of j dependent ones); the Givens rotations and the small
+// triangular solve run on the host, which reads one column of coefficients per step.
+// =======================================================================================
+namespace {
+
+constexpr int kGmBlocks = 1024;      // workgroups of the dot passes (fixed-order partials)
+constexpr int kGmChunk = 8;          // basis vectors summed per pass over w
+constexpr int kGmMaxRestart = 200;
+
+// part[i * G + blk] = this workgroup's share of (V_i, w), i < nv (V_i = V + i n)
+__global__ void __launch_bounds__(kBlock) k_gm_dots(int64_t n, const double* __restrict__ V,
+                                                    int nv, const double* __restrict__ w,
+                                                    double* part) {
+  __shared__ double lds[kGmChunk * kNW];
+  const int64_t stride = int64_t(gridDim.x) * kBlock;
+  for (int i0 = 0; i0 < nv; i0 += kGmChunk) {
+    double acc[kGmChunk];
+#pragma unroll
+    for (int u = 0; u < kGmChunk; ++u) acc[u] = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n; c += stride) {
+      const double wc = w[c];
+#pragma unroll
+      for (int u = 0; u < kGmChunk; ++u)
+        if (i0 + u < nv) acc[u] += V[int64_t(i0 + u) * n + c] * wc;
+    }
+    psl::block_sum<kGmChunk>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int u = 0; u < kGmChunk; ++u)
+        if (i0 + u < nv) part[int64_t(i0 + u) * gridDim.x + blockIdx.x] = acc[u];
+    __syncthreads();
+  }
+}
+
+// out[i] = sum over the G partials of vector i, in workgroup order (one workgroup per i)
+__global__ void __launch_bounds__(kBlock) k_gm_reduce(const double* part, int G, double* out) {
+  __shared__ double lds[kNW];
+  double acc[1] = {0.0};
+  for (int g = threadIdx.x; g < G; g += kBlock) acc[0] += part[int64_t(blockIdx.x) * G + g];
+  psl::block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
+}
+
+// w -= sum_i h[i] V_i
+__global__ void k_gm_axpys(int64_t n, const double* __restrict__ V, int nv,
+                           const double* __restrict__ h, double* __restrict__ w) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += h[i] * V[int64_t(i) * n + c];
+    w[c] -= s;
+  }
+}
+
+// z = M^-1 v
+__global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const double* __restrict__ v,
+                           double* __restrict__ z) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    z[c] = invd[c] * v[c];
+}
+
+// v = w / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted)
+__global__ void k_gm_normalize(int64_t n, const double* nrm2, double* v) {
+  const double s = nrm2[0];
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    v[c] *= inv;
+}
+
+// x += M^-1 sum_i y[i] V_i
+__global__ void k_gm_update(int64_t n, const double* __restrict__ V, int nv,
+                            const double* __restrict__ y, const double* __restrict__ invd,
+                            double* __restrict__ x) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += y[i] * V[int64_t(i) * n + c];
+    x[c] += invd[c] * s;
+  }
+}
+
+int ensure_gmres(psl_ctx* c, int m) {
+  if (c->gm_cap >= m + 1) return PSL_OK;
+  const int cap = m + 1;
+  double *v = nullptr, *part = nullptr, *dv = nullptr;
+  if (psl_ctx_alloc(c, reinterpret_cast<void**>(&v), sizeof(double) * size_t(c->n) * cap) ||
+      psl_ctx_alloc(c, reinterpret_cast<void**>(&part), sizeof(double) * size_t(kGmBlocks) * cap) ||
+      psl_ctx_alloc(c, reinterpret_cast<void**>(&dv), sizeof(double) * size_t(3 * cap + 4)))
+    return PSL_ENOMEM;
+  c->gm_v = v;
+  c->gm_part = part;
+  c->gm_dev = dv;
+  c->gm_cap = cap;
+  return PSL_OK;
+}
+
+// out[0..nv) = (V_i, w) with the fixed-order reduction
+void gm_dots(psl_ctx* c, const double* V, int nv, const double* w, double* out, hipStream_t st) {
+  const int G = int(std::min<int64_t>(kGmBlocks, (c->n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_gm_dots, dim3(G), dim3(kBlock), 0, st, c->n, V, nv, w, c->gm_part);
+  hipLaunchKernelGGL(k_gm_reduce, dim3(nv), dim3(kBlock), 0, st, c->gm_part, G, out);
+}
+
+// w = P1 A M^-1 v (z in t64): stencil (with the Z^T partials), coarse solve, A Z e on
+// the cut faces
+void gm_operator(psl_ctx* c, const double* v, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_gm_scale, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, c->n,
+                     c->invdiag, v, c->t64);
+  launch_stencil<double, 0>(c, c->t64, nullptr, w, st);
+  launch_coarse<0, 0>(c, 0, st);
+  launch_outer_deflate(c, nullptr, w, w, st);
+}
+
+}  // namespace
+
+extern "C" void psl_default_gmres_opts(psl_gmres_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->maxit = 10000;
+  o->restart = 30;
+  o->use_x0 = 0;
+}
+
+extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl_gmres_opts* o_in,
+                               psl_solve_stats* st_out, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!c || !b || !x) return PSL_EINVAL;
+  psl_gmres_opts o;
+  psl_default_gmres_opts(&o);
+  if (o_in) o = *o_in;
+  if (!(o.tol > 0.0) || o.maxit < 0 || o.restart < 1 || o.restart > kGmMaxRestart ||
+      (o.use_x0 != 0 && o.use_x0 != 1) || o.reserved[0] || o.reserved[1] || o.reserved[2])
+    return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int m = o.restart;
+  psl_solve_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  auto finish = [&](int status) {
+    stats.status = status;
+    stats.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st_out) *st_out = stats;
+    return status;
+  };
+  int rc = ensure_gmres(c, m);
+  if (rc != PSL_OK) return finish(rc);
+  const int64_t n = c->n;
+  hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), b, red(c, 1));
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->bnorm2);
+  if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+  const double bnorm = std::sqrt(c->h_sc->bnorm2);
+  stats.bnorm = bnorm;
+  if (!std::isfinite(bnorm)) return finish(PSL_ENONFINITE);
+  if (!o.use_x0 || bnorm == 0.0)
+    hipLaunchKernelGGL(k_zero, dim3(elem_grid(n)), dim3(kBlock), 0, st, x, int(n));
+  if (bnorm == 0.0) {
+    PSL_HIP(hipStreamSynchronize(st));
+    return finish(PSL_OK);
+  }
+  double* h1 = c->gm_dev;                 // first Gram-Schmidt pass
+  double* h2 = c->gm_dev + (m + 1);       // second pass
+  double* nrm2 = c->gm_dev + 2 * (m + 1);
+  double* ydev = c->gm_dev + 2 * (m + 1) + 1;
+  std::vector<double> H(size_t(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> col(2 * (m + 1) + 1);
+  int total = 0, cycles = 0;
+  int status = PSL_OK;
+  for (;;) {
+    // r0 = P1 (b - A x) into V_0 (its norm^2 into sc->rr)
+    double* V0 = c->gm_v;
+    launch_stencil<double, 1>(c, x, b, V0, st);
+    launch_coarse<0, 0>(c, 0, st);
+    launch_outer_deflate(c, nullptr, V0, V0, st);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->rr);
+    if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+    const double beta = std::sqrt(c->h_sc->rr);
+    if (!std::isfinite(beta)) {
+      status = PSL_ENONFINITE;
+      break;
+    }
+    if (beta <= o.tol * bnorm) break;
+    if (total >= o.maxit) {
+      status = PSL_EMAXIT;
+      break;
+    }
+    hipLaunchKernelGGL(k_gm_normalize, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, &c->sc->rr,
+                       V0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      const double* Vj = c->gm_v + int64_t(j) * n;
+      double* w = c->gm_v + int64_t(j + 1) * n;
+      gm_operator(c, Vj, w, st);
+      gm_dots(c, c->gm_v, j + 1, w, h1, st);
+      hipLaunchKernelGGL(k_gm_axpys, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, j + 1,
+                         h1, w);
+      gm_dots(c, c->gm_v, j + 1, w, h2, st);
+      hipLaunchKernelGGL(k_gm_axpys, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, j + 1,
+                         h2, w);
+      gm_dots(c, w, 1, w, nrm2, st);
+      hipLaunchKernelGGL(k_gm_normalize, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, nrm2, w);
+      PSL_HIP(hipMemcpyAsync(col.data(), c->gm_dev, sizeof(double) * col.size(),
+                             hipMemcpyDeviceToHost, st));
+      PSL_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = col[i] + col[(m + 1) + i];
+      const double hn = std::sqrt(std::max(0.0, col[2 * (m + 1)]));
+      H[size_t(j + 1) * m + j] = hn;
+      ++total;
+      if (!std::isfinite(hn)) {
+        status = PSL_ENONFINITE;
+        jend = 0;
+        break;
+      }
+      // earlier rotations on column j, then the rotation that zeroes h_{j+1,j}
+      for (int i = 0; i < j; ++i) {
+        const double a = H[size_t(i) * m + j], bb = H[size_t(i + 1) * m + j];
+        H[size_t(i) * m + j] = cs[i] * a + sn[i] * bb;
+        H[size_t(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[size_t(j) * m + j], bb = H[size_t(j + 1) * m + j];
+      const double rr = std::hypot(a, bb);
+      cs[j] = rr > 0.0 ? a / rr : 1.0;
+      sn[j] = rr > 0.0 ? bb / rr : 0.0;
+      H[size_t(j) * m + j] = rr;
+      H[size_t(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      jend = j + 1;
+      if (std::fabs(g[j + 1]) <= o.tol * bnorm || hn == 0.0 || total >= o.maxit) break;
+    }
+    if (status != PSL_OK) break;
+    // y = R^-1 g (back substitution), x += M^-1 V y
+    for (int i = jend - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < jend; ++k) s -= H[size_t(i) * m + k] * y[k];
+      const double d = H[size_t(i) * m + i];
+      y[i] = d != 0.0 ? s / d : 0.0;
+    }
+    PSL_HIP(hipMemcpyAsync(ydev, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gm_update, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, jend,
+                       ydev, c->invdiag, x);
+    ++cycles;
+  }
+  stats.iters = total;
+  stats.outer = cycles;
+  // projection back: x = P2 x + x* = x + Z E^-1 Z^T (b - A x)
+  enqueue_outer_step(c, b, x, st);
+  launch_stencil<double, 1>(c, x, b, c->t64, st);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
+  if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+  stats.relres_true = std::sqrt(c->h_sc->rr) / bnorm;
+  return finish(status);
+}
+
+// =======================================================================================
 // Batched solve: independent systems, each with its own context, advance together. One
 // launch of each float64 CG kernel covers the tiles of every system through a (system,
 // tile) work list and a per-system argument table; a converged system's workgroups return

@@ -64,6 +64,11 @@ class psl_solve_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class psl_gmres_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -103,12 +108,16 @@ _bench_kernel = _sig("psl_bench_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P
 _bench_copy = _sig("psl_bench_copy", ctypes.c_int, [_P, _P, ctypes.c_int64, _P])
 _status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
 _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
+_default_gmres_opts = _sig("psl_default_gmres_opts", None, [ctypes.POINTER(psl_gmres_opts)])
+_solve_gmres = _sig("psl_solve_gmres", ctypes.c_int,
+                    [_P, _P, _P, ctypes.POINTER(psl_gmres_opts), ctypes.POINTER(psl_solve_stats), _P])
 
 EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E", "psl_setup_E_ex",
             "psl_default_setup_opts", "psl_solve",
             "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
-            "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info")
+            "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info",
+            "psl_solve_gmres", "psl_default_gmres_opts")
 KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL = range(5)
 
 
@@ -277,6 +286,34 @@ def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *
                 ctypes.byref(o), ctypes.byref(st), _stream())
     if check:
         _check(rc, "psl_solve")
+    stats = st.as_dict()
+    stats["status_str"] = psl_status_str(rc)
+    return x, stats
+
+
+def psl_solve_gmres(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
+                    tol: Optional[float] = None, maxit: Optional[int] = None,
+                    restart: Optional[int] = None, use_x0: bool = False, check: bool = False):
+    """The paper's deflated right-preconditioned GMRES(m); returns (x, stats dict)."""
+    o = psl_gmres_opts()
+    _default_gmres_opts(ctypes.byref(o))
+    if tol is not None:
+        o.tol = tol
+    if maxit is not None:
+        o.maxit = maxit
+    if restart is not None:
+        o.restart = restart
+    o.use_x0 = 1 if use_x0 else 0
+    if x is None:
+        if use_x0:
+            raise ValueError("use_x0 needs x")
+        x = torch.empty_like(b)
+    st = psl_solve_stats()
+    rc = _solve_gmres(ctx.handle, _dev(b, torch.float64, ctx.n, "b"),
+                      _dev(x, torch.float64, ctx.n, "x"), ctypes.byref(o), ctypes.byref(st),
+                      _stream())
+    if check:
+        _check(rc, "psl_solve_gmres")
     stats = st.as_dict()
     stats["status_str"] = psl_status_str(rc)
     return x, stats
