@@ -342,6 +342,9 @@ def main():
     ap.add_argument("--labels", default="regions", choices=["regions", "components"],
                     help="deflation space: one vector per (subdomain, class) region, or per "
                          "connected component of each region (psl_build_Z_cc)")
+    ap.add_argument("--solver", default="dpcg", choices=["dpcg", "gmres"],
+                    help="deflated CG (default) or the paper's deflated GMRES(m), float64")
+    ap.add_argument("--restart", type=int, default=30, help="m of GMRES(m)")
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -392,7 +395,10 @@ def main():
                            components=args.labels == "components")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
+        if args.solver == "gmres":
+            x, st = psl.psl_solve_gmres(s.ctx, b, tol=prob.tol, restart=args.restart)
+        else:
+            x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return s, x, st, t1 - t0, t2 - t1
@@ -414,6 +420,8 @@ def main():
             f"outer={st['outer']} relres={st['relres_true']:.2e}")
         return s, x, rec, wall
 
+    if args.solver == "gmres":
+        args.mode = "fp64"        # the GMRES path is float64 only
     mode = psl.MIXED if args.mode == "mixed" else psl.FP64
     s, x, rec, wall = run_leg(mode, args.steps, args.warmup, args.mode)
     st = rec[-1][0]
@@ -489,12 +497,16 @@ def main():
                         else O.levelset_labels)
             lab, dd = label_fn(prob.grid, prob.K, prob.nsub, prob.thr)
             Z = O.deflation_matrix(lab, dd)
-            res = O.dpcg(A, bh, Z, tol=prob.tol)
+            if args.solver == "gmres":
+                res = O.pdgmres(A, bh, Z, m=args.restart, tol=prob.tol)
+            else:
+                res = O.dpcg(A, bh, Z, tol=prob.tol)
             cpu_s = time.perf_counter() - t0
         xg = x.cpu().numpy()
         cpu = {"value": round(cpu_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
                "sample": f"one full {args.workload} solve (assembly, {args.labels} labels, E + Cholesky, "
-                         f"DEF1-PCG to 1e-8), {res.iters} iterations, 1 thread",
+                         f"{'deflated GMRES(%d)' % args.restart if args.solver == 'gmres' else 'DEF1-PCG'}"
+                         f" to 1e-8), {res.iters} iterations, 1 thread",
                "host_cores_available": len(os.sched_getaffinity(0)),
                "gpu_vs_oracle_rel_err": float(np.linalg.norm(xg - res.x) / np.linalg.norm(res.x)),
                "gpu_relres_by_oracle": float(O.relres(A, bh, xg))}
@@ -507,7 +519,9 @@ def main():
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid),
-                   "nsub": list(prob.nsub), "d": d, "labels": args.labels, "tol": prob.tol,
+                   "nsub": list(prob.nsub), "d": d, "labels": args.labels,
+                   "solver": (f"pdgmres({args.restart})" if args.solver == "gmres" else "dpcg"),
+                   "tol": prob.tol,
                    "mode": args.mode, "seed": args.seed, "tile_cells": tiles},
         "converged": bool(ok), "iterations": st["iters"], "outer": st["outer"],
         "relres_true": st["relres_true"], "setup_s": setup_s, "solve_s": solve_s,
