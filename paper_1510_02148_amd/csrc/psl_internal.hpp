@@ -125,8 +125,10 @@ struct psl_ctx {
   double* xbest = nullptr;            // [n] best projected iterate of the current solve
   double* gm_v = nullptr;             // deflated GMRES: gm_cap basis vectors of n doubles
   int gm_cap = 0;
-  double* gm_part = nullptr;          // [kGmBlocks * gm_cap] per-workgroup dot partials
+  double* gm_part = nullptr;          // [(gm_cap + 1) * ceil(n / kBlock)] workgroup partials
   double* gm_dev = nullptr;           // [3 * gm_cap + 4] dots, norm and step coefficients
+  double* gm_host = nullptr;          // pinned: two slots of one Arnoldi column each
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};  // marks each slot's copy
   psl::Scalars* sc = nullptr;
   psl::Scalars* h_sc = nullptr;       // pinned host mirror
   psl::VecSet<double> v64;

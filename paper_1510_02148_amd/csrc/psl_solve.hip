@@ -1790,42 +1790,88 @@ extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* s
 // =======================================================================================
 // Deflated GMRES (the paper's own solver): right-preconditioned restarted GMRES(m) on
 // P1 A M^-1 with the a priori subdomain-levelset vectors, M = diag(A), float64. Arnoldi
-// uses classical Gram-Schmidt applied twice (two batched dot passes and two batched
-// updates per step instead of j dependent ones); the Givens rotations and the small
-// triangular solve run on the host, which reads one column of coefficients per step.
+// uses classical Gram-Schmidt applied twice in three passes over the basis: dots, then
+// update fused with the second dots, then update fused with the norm. The Givens rotations
+// and the small triangular solve run on the host, which reads one column of coefficients
+// per step while the device already runs the next step.
 // =======================================================================================
 namespace {
 
-constexpr int kGmBlocks = 1024;      // workgroups of the dot passes (fixed-order partials)
-constexpr int kGmChunk = 8;          // basis vectors summed per pass over w
+constexpr int kGmReg = 32;           // basis vectors one pass covers with register accumulators
+constexpr int kGmBlocks = 1024;      // workgroups of a pass (one partial each per quantity)
 constexpr int kGmMaxRestart = 200;
 
-// part[i * G + blk] = this workgroup's share of (V_i, w), i < nv (V_i = V + i n)
-__global__ void __launch_bounds__(kBlock) k_gm_dots(int64_t n, const double* __restrict__ V,
-                                                    int nv, const double* __restrict__ w,
-                                                    double* part) {
-  __shared__ double lds[kGmChunk * kNW];
-  const int64_t stride = int64_t(gridDim.x) * kBlock;
-  for (int i0 = 0; i0 < nv; i0 += kGmChunk) {
-    double acc[kGmChunk];
+// One grid-stride pass over the cells, with per-thread accumulators reduced once per
+// workgroup at the end (V_i = V + i n):
+//   AXPY: w <- w - sum_{i < nv} h[i] V_i
+//   DOTS: part[u G + blk] = this workgroup's share of (V_{i0+u}, w), u < nd <= ND, with
+//         w after the update (AXPY and DOTS together need i0 = 0 and nd = nv <= ND: the
+//         basis values loaded for the update are reused for the dots)
+//   and always part[k G + blk] = its share of (w, w), k = nd with DOTS, else 0.
+// With DOTS, a thread loads ND values per cell without branching (indices past nd repeat
+// the last vector and their products are dropped), so every load of the cell is in flight
+// before the first is used.
+template <bool AXPY, bool DOTS, int ND>
+__global__ void __launch_bounds__(kBlock) k_gm_pass(int64_t n, const double* __restrict__ V,
+                                                    int nv, int i0, int nd,
+                                                    const double* __restrict__ h,
+                                                    double* __restrict__ w,
+                                                    double* __restrict__ part) {
+  static_assert(ND % 8 == 0 || ND < 8 || !DOTS, "dots are reduced in groups of 8");
+  __shared__ double lds[8 * kNW];
+  const int64_t G = gridDim.x;
+  const double* __restrict__ Vd = V + int64_t(i0) * n;
+  constexpr int NA = ND > 0 ? ND : 1;
+  double acc[NA];
 #pragma unroll
-    for (int u = 0; u < kGmChunk; ++u) acc[u] = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n; c += stride) {
-      const double wc = w[c];
+  for (int u = 0; u < ND; ++u) acc[u] = 0.0;
+  double accn = 0.0;
+  for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n; c += G * kBlock) {
+    double wc = w[c];
+    if constexpr (DOTS) {
+      double vr[NA];
 #pragma unroll
-      for (int u = 0; u < kGmChunk; ++u)
-        if (i0 + u < nv) acc[u] += V[int64_t(i0 + u) * n + c] * wc;
+      for (int u = 0; u < ND; ++u) vr[u] = Vd[int64_t(u < nd ? u : nd - 1) * n + c];
+      if (AXPY) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < ND; ++u) s += (u < nd ? h[u < nd ? u : nd - 1] : 0.0) * vr[u];
+        wc -= s;
+        w[c] = wc;
+      }
+#pragma unroll
+      for (int u = 0; u < ND; ++u) acc[u] += vr[u] * wc;
+    } else {
+      double s = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < nv; ++i) s += h[i] * V[int64_t(i) * n + c];
+      wc -= s;
+      w[c] = wc;
     }
-    psl::block_sum<kGmChunk>(acc, lds);
-    if (threadIdx.x == 0)
-#pragma unroll
-      for (int u = 0; u < kGmChunk; ++u)
-        if (i0 + u < nv) part[int64_t(i0 + u) * gridDim.x + blockIdx.x] = acc[u];
-    __syncthreads();
+    accn += wc * wc;
   }
+  if constexpr (DOTS) {
+#pragma unroll
+    for (int u0 = 0; u0 < ND; u0 += 8) {
+      constexpr int K = ND < 8 ? NA : 8;
+      if (u0 < nd) {
+        double t[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) t[u] = acc[u0 + u];
+        psl::block_sum<K>(t, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+          for (int u = 0; u < K; ++u)
+            if (u0 + u < nd) part[(u0 + u) * G + blockIdx.x] = t[u];
+      }
+    }
+  }
+  double nn[1] = {accn};
+  psl::block_sum<1>(nn, lds);
+  if (threadIdx.x == 0) part[(DOTS ? nd : 0) * G + blockIdx.x] = nn[0];
 }
 
-// out[i] = sum over the G partials of vector i, in workgroup order (one workgroup per i)
+// out[i] = sum over the G partials of quantity i, in workgroup order (one workgroup per i)
 __global__ void __launch_bounds__(kBlock) k_gm_reduce(const double* part, int G, double* out) {
   __shared__ double lds[kNW];
   double acc[1] = {0.0};
@@ -1834,32 +1880,17 @@ __global__ void __launch_bounds__(kBlock) k_gm_reduce(const double* part, int G,
   if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
 }
 
-// w -= sum_i h[i] V_i
-__global__ void k_gm_axpys(int64_t n, const double* __restrict__ V, int nv,
-                           const double* __restrict__ h, double* __restrict__ w) {
-  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * blockDim.x) {
-    double s = 0.0;
-    for (int i = 0; i < nv; ++i) s += h[i] * V[int64_t(i) * n + c];
-    w[c] -= s;
-  }
-}
-
-// z = M^-1 v
-__global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const double* __restrict__ v,
-                           double* __restrict__ z) {
-  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * blockDim.x)
-    z[c] = invd[c] * v[c];
-}
-
-// v = w / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted)
-__global__ void k_gm_normalize(int64_t n, const double* nrm2, double* v) {
+// v <- v / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted), z = M^-1 v
+__global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const double* nrm2,
+                           double* __restrict__ v, double* __restrict__ z) {
   const double s = nrm2[0];
   const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * blockDim.x)
-    v[c] *= inv;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    const double vc = v[c] * inv;
+    v[c] = vc;
+    z[c] = invd[c] * vc;
+  }
 }
 
 // x += M^-1 sum_i y[i] V_i
@@ -1874,14 +1905,28 @@ __global__ void k_gm_update(int64_t n, const double* __restrict__ V, int nv,
   }
 }
 
+inline int gm_blocks(int64_t n) {
+  return int(std::min<int64_t>(kGmBlocks, (n + kBlock - 1) / kBlock));
+}
+
 int ensure_gmres(psl_ctx* c, int m) {
+  if (!c->gm_ev[0]) {
+    for (auto& ev : c->gm_ev)
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return PSL_EHIP;
+  }
   if (c->gm_cap >= m + 1) return PSL_OK;
   const int cap = m + 1;
   double *v = nullptr, *part = nullptr, *dv = nullptr;
   if (psl_ctx_alloc(c, reinterpret_cast<void**>(&v), sizeof(double) * size_t(c->n) * cap) ||
-      psl_ctx_alloc(c, reinterpret_cast<void**>(&part), sizeof(double) * size_t(kGmBlocks) * cap) ||
+      psl_ctx_alloc(c, reinterpret_cast<void**>(&part),
+                    sizeof(double) * size_t(gm_blocks(c->n)) * (cap + 1)) ||
       psl_ctx_alloc(c, reinterpret_cast<void**>(&dv), sizeof(double) * size_t(3 * cap + 4)))
     return PSL_ENOMEM;
+  void* host = nullptr;
+  if (hipHostMalloc(&host, sizeof(double) * size_t(2 * (2 * cap + 1))) != hipSuccess)
+    return PSL_ENOMEM;
+  if (c->gm_host) (void)hipHostFree(c->gm_host);
+  c->gm_host = static_cast<double*>(host);
   c->gm_v = v;
   c->gm_part = part;
   c->gm_dev = dv;
@@ -1889,18 +1934,58 @@ int ensure_gmres(psl_ctx* c, int m) {
   return PSL_OK;
 }
 
-// out[0..nv) = (V_i, w) with the fixed-order reduction
-void gm_dots(psl_ctx* c, const double* V, int nv, const double* w, double* out, hipStream_t st) {
-  const int G = int(std::min<int64_t>(kGmBlocks, (c->n + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(k_gm_dots, dim3(G), dim3(kBlock), 0, st, c->n, V, nv, w, c->gm_part);
-  hipLaunchKernelGGL(k_gm_reduce, dim3(nv), dim3(kBlock), 0, st, c->gm_part, G, out);
+// one pass of k_gm_pass, then the fixed-order reduction of its partials into out
+template <bool AXPY, bool DOTS, int ND>
+void gm_pass_nd(psl_ctx* c, int nv, int i0, int nd, const double* h, double* w, double* out,
+                hipStream_t st) {
+  const int G = gm_blocks(c->n);
+  hipLaunchKernelGGL((k_gm_pass<AXPY, DOTS, ND>), dim3(G), dim3(kBlock), 0, st, c->n,
+                     static_cast<const double*>(c->gm_v), nv, i0, nd, h, w, c->gm_part);
+  hipLaunchKernelGGL(k_gm_reduce, dim3(DOTS ? nd + 1 : 1), dim3(kBlock), 0, st,
+                     static_cast<const double*>(c->gm_part), G, out);
 }
 
-// w = P1 A M^-1 v (z in t64): stencil (with the Z^T partials), coarse solve, A Z e on
-// the cut faces
-void gm_operator(psl_ctx* c, const double* v, double* w, hipStream_t st) {
+// the smallest compiled vector count that covers nd (1..kGmReg)
+template <bool AXPY, bool DOTS>
+void gm_pass(psl_ctx* c, int nv, int i0, int nd, const double* h, double* w, double* out,
+             hipStream_t st) {
+  if constexpr (!DOTS) {
+    gm_pass_nd<AXPY, false, 0>(c, nv, i0, nd, h, w, out, st);
+  } else {
+    static_assert(kGmReg == 32, "compiled vector counts end at kGmReg");
+    if (nd <= 4) return gm_pass_nd<AXPY, true, 4>(c, nv, i0, nd, h, w, out, st);
+    if (nd <= 8) return gm_pass_nd<AXPY, true, 8>(c, nv, i0, nd, h, w, out, st);
+    if (nd <= 16) return gm_pass_nd<AXPY, true, 16>(c, nv, i0, nd, h, w, out, st);
+    if (nd <= 24) return gm_pass_nd<AXPY, true, 24>(c, nv, i0, nd, h, w, out, st);
+    gm_pass_nd<AXPY, true, 32>(c, nv, i0, nd, h, w, out, st);
+  }
+}
+
+// out[i] = (V_i, w) for i < nv, out[nv] = (w, w); w is not changed
+void gm_dots(psl_ctx* c, int nv, double* w, double* out, hipStream_t st) {
+  for (int i0 = 0; i0 < nv; i0 += kGmReg)
+    gm_pass<false, true>(c, 0, i0, std::min(kGmReg, nv - i0), nullptr, w, out + i0, st);
+}
+
+// classical Gram-Schmidt twice against V_0..V_{nv-1}: h1 = V^T w, w -= V h1, h2 = V^T w,
+// w -= V h2, nrm2 = (w, w); h1[nv] and h2[nv] receive (w, w) before each update
+void gm_orthogonalize(psl_ctx* c, int nv, double* w, double* h1, double* h2, double* nrm2,
+                      hipStream_t st) {
+  gm_dots(c, nv, w, h1, st);
+  if (nv <= kGmReg) {
+    gm_pass<true, true>(c, nv, 0, nv, h1, w, h2, st);
+  } else {
+    gm_pass<true, false>(c, nv, 0, 0, h1, w, h2 + nv, st);
+    gm_dots(c, nv, w, h2, st);
+  }
+  gm_pass<true, false>(c, nv, 0, 0, h2, w, nrm2, st);
+}
+
+// v <- v / |v| (nrm2 = |v|^2 on the device), then w = P1 A M^-1 v (z in t64): stencil
+// (with the Z^T partials), coarse solve, A Z e on the cut faces
+void gm_operator(psl_ctx* c, double* v, const double* nrm2, double* w, hipStream_t st) {
   hipLaunchKernelGGL(k_gm_scale, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, c->n,
-                     c->invdiag, v, c->t64);
+                     c->invdiag, nrm2, v, c->t64);
   launch_stencil<double, 0>(c, c->t64, nullptr, w, st);
   launch_coarse<0, 0>(c, 0, st);
   launch_outer_deflate(c, nullptr, w, w, st);
@@ -1953,12 +2038,24 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
     PSL_HIP(hipStreamSynchronize(st));
     return finish(PSL_OK);
   }
-  double* h1 = c->gm_dev;                 // first Gram-Schmidt pass
+  double* h1 = c->gm_dev;                 // first Gram-Schmidt pass (and |w|^2 before it)
   double* h2 = c->gm_dev + (m + 1);       // second pass
-  double* nrm2 = c->gm_dev + 2 * (m + 1);
+  double* nrm2 = c->gm_dev + 2 * (m + 1); // |w|^2 after both passes
   double* ydev = c->gm_dev + 2 * (m + 1) + 1;
+  const size_t ncol = size_t(2 * (m + 1) + 1);
   std::vector<double> H(size_t(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
-  std::vector<double> col(2 * (m + 1) + 1);
+  // Arnoldi step j: normalise V_j, w = P1 A M^-1 V_j into V_{j+1}, orthogonalise it, then
+  // copy (h1, h2, |w|^2) into host slot j % 2 and mark it with the slot's event
+  auto enqueue_step = [&](int j) -> int {
+    double* Vj = c->gm_v + int64_t(j) * n;
+    double* w = c->gm_v + int64_t(j + 1) * n;
+    gm_operator(c, Vj, j == 0 ? &c->sc->rr : nrm2, w, st);
+    gm_orthogonalize(c, j + 1, w, h1, h2, nrm2, st);
+    PSL_HIP(hipMemcpyAsync(c->gm_host + (j & 1) * ncol, c->gm_dev, sizeof(double) * ncol,
+                           hipMemcpyDeviceToHost, st));
+    PSL_HIP(hipEventRecord(c->gm_ev[j & 1], st));
+    return PSL_OK;
+  };
   int total = 0, cycles = 0;
   int status = PSL_OK;
   for (;;) {
@@ -1979,26 +2076,17 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
       status = PSL_EMAXIT;
       break;
     }
-    hipLaunchKernelGGL(k_gm_normalize, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, &c->sc->rr,
-                       V0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
+    if ((rc = enqueue_step(0)) != PSL_OK) return finish(rc);
     for (int j = 0; j < m; ++j) {
-      const double* Vj = c->gm_v + int64_t(j) * n;
-      double* w = c->gm_v + int64_t(j + 1) * n;
-      gm_operator(c, Vj, w, st);
-      gm_dots(c, c->gm_v, j + 1, w, h1, st);
-      hipLaunchKernelGGL(k_gm_axpys, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, j + 1,
-                         h1, w);
-      gm_dots(c, c->gm_v, j + 1, w, h2, st);
-      hipLaunchKernelGGL(k_gm_axpys, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, j + 1,
-                         h2, w);
-      gm_dots(c, w, 1, w, nrm2, st);
-      hipLaunchKernelGGL(k_gm_normalize, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, nrm2, w);
-      PSL_HIP(hipMemcpyAsync(col.data(), c->gm_dev, sizeof(double) * col.size(),
-                             hipMemcpyDeviceToHost, st));
-      PSL_HIP(hipStreamSynchronize(st));
+      // the device runs step j + 1 while the host finishes step j (a step past the exit is
+      // computed and discarded: it writes only V_{j+2} and the coefficient buffers)
+      if (j + 1 < m && total + 1 < o.maxit && (rc = enqueue_step(j + 1)) != PSL_OK)
+        return finish(rc);
+      PSL_HIP(hipEventSynchronize(c->gm_ev[j & 1]));
+      const double* col = c->gm_host + (j & 1) * ncol;
       for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = col[i] + col[(m + 1) + i];
       const double hn = std::sqrt(std::max(0.0, col[2 * (m + 1)]));
       H[size_t(j + 1) * m + j] = hn;
