@@ -64,6 +64,9 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
         return 12 * w * n + m_faces * (12 + w)   # read v, r, u, p, q, x, 1/diag; write 5
     if kernel == "coarse":           # read E^-1 (float64), s; write e
         return 8.0 * d * d + 4 * 8 * d
+    if kernel.startswith("gs_pass"):  # read nv basis vectors and w, write w (float64)
+        nv = int(kernel.split("_")[-1])
+        return (nv + 2) * 8.0 * n
     raise KeyError(kernel)
 
 
@@ -447,6 +450,11 @@ def main():
     stream = torch.cuda.current_stream()
     ids = {"stencil": psl.KERNEL_STENCIL, "coarse": psl.KERNEL_COARSE,
            "update": psl.KERNEL_UPDATE}
+    if args.solver == "gmres":
+        # the Gram-Schmidt pass (update fused with the dots) at the restart length's
+        # largest basis; the CG stencil stays as the SpMV bandwidth reference
+        ids = {"stencil": psl.KERNEL_STENCIL,
+               f"gs_pass_{min(args.restart, 32)}": psl.KERNEL_GMRES_PASS}
     for name, kid in ids.items():
         psl.psl_bench_kernel(s.ctx, kid, mode, 3)            # warm
         e0 = torch.cuda.Event(enable_timing=True)

@@ -315,6 +315,9 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
 #define PSL_KERNEL_UPDATE         2  /* p, q, x, r updates with A Z e   (pass 2)          */
 #define PSL_KERNEL_DIRECTION      3  /* reserved (the direction update is part of pass 2) */
 #define PSL_KERNEL_OUTER_RESIDUAL 4  /* r = b - A x in float64          (refinement step) */
+#define PSL_KERNEL_GMRES_PASS     5  /* deflated GMRES: w -= V h with the dots V^T w (fused
+                                        Gram-Schmidt pass over min(m, 32) basis vectors,
+                                        float64; needs a prior psl_solve_gmres, PSL_FP64) */
 
 /*
  * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
@@ -323,7 +326,11 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
  * precision of `mode`, so a caller can time it with events on `stream`. Call after a
  * psl_solve in the same mode (the vectors then hold a real iterate); the scalars are set
  * so that no launch exits early. The work vectors are overwritten.
- * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1), PSL_ENOMEM.
+ * PSL_KERNEL_GMRES_PASS times the Gram-Schmidt pass of psl_solve_gmres (Algorithm 1's
+ * Arnoldi step) against the first min(m, 32) basis vectors of the longest restart length m
+ * solved on this context so far; it overwrites basis vector min(m, 32).
+ * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1; GMRES pass without a
+ * prior psl_solve_gmres or in PSL_MIXED), PSL_ENOMEM.
  */
 int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
 

@@ -1733,13 +1733,21 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   return finish(status);
 }
 
+namespace {
+int gm_bench_pass(psl_ctx* c, int reps, hipStream_t st);   // with the GMRES kernels below
+}
+
 extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t reps,
                                 void* stream) {
   psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (!c || reps < 1 || (mode != PSL_FP64 && mode != PSL_MIXED) || kernel < 0 ||
-      kernel > PSL_KERNEL_OUTER_RESIDUAL)
+      kernel > PSL_KERNEL_GMRES_PASS)
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (kernel == PSL_KERNEL_GMRES_PASS) {
+    if (mode != PSL_FP64 || c->gm_cap < 2) return PSL_EINVAL;
+    return gm_bench_pass(c, reps, st);
+  }
   int rc = mode == PSL_MIXED ? ensure_sd<float>(c) : ensure_vecs<double>(c);
   if (rc != PSL_OK) return rc;
   hipLaunchKernelGGL(k_bench_prep, dim3(1), dim3(1), 0, st, c->sc);
@@ -1989,6 +1997,18 @@ void gm_operator(psl_ctx* c, double* v, const double* nrm2, double* w, hipStream
   launch_stencil<double, 0>(c, c->t64, nullptr, w, st);
   launch_coarse<0, 0>(c, 0, st);
   launch_outer_deflate(c, nullptr, w, w, st);
+}
+
+// reps fused passes (update with the dots) against min(m, kGmReg) basis vectors, updating
+// the next one, with the coefficients the last solve left in h1
+int gm_bench_pass(psl_ctx* c, int reps, hipStream_t st) {
+  const int nv = std::min(c->gm_cap - 1, kGmReg);
+  const int m = c->gm_cap - 1;
+  double* w = c->gm_v + int64_t(nv) * c->n;
+  for (int i = 0; i < reps; ++i)
+    gm_pass<true, true>(c, nv, 0, nv, c->gm_dev, w, c->gm_dev + (m + 1), st);
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
 }
 
 }  // namespace

@@ -118,7 +118,8 @@ EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
             "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info",
             "psl_solve_gmres", "psl_default_gmres_opts")
-KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL = range(5)
+(KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL,
+ KERNEL_GMRES_PASS) = range(6)
 
 
 class PslError(RuntimeError):
