@@ -312,6 +312,58 @@ def pin_gmres_direct(O):
             assert np.linalg.norm(r.x - xd) <= 1e-9 * np.linalg.norm(xd), (seed, m, ZZ.shape)
 
 
+def pin_chebyshev_closed_form(O):
+    """The Chebyshev recurrence against its closed form: with S = D^-1/2 A D^-1/2 = U L U^T,
+    k steps from y = 0 give y = D^-1/2 U diag((1 - T_k((theta - l) / delta) / T_k(theta /
+    delta)) / l) U^T D^-1/2 r (the error polynomial of the Chebyshev iteration; T_k from
+    numpy's Chebyshev basis). Also: the spectrum of D^-1 A lies in (0, 2] (Gershgorin
+    for these matrices), so with lmax = 2 the operator is symmetric positive definite."""
+    from numpy.polynomial import chebyshev as C
+    for seed in (31, 32):
+        A, _, _ = _tiny_system(O, seed)
+        Ad = A.toarray()
+        dg = np.diag(Ad)
+        s = 1.0 / np.sqrt(dg)
+        lam, U = np.linalg.eigh(Ad * s[:, None] * s[None, :])
+        assert lam.min() > 0 and lam.max() <= 2.0 + 1e-12
+        for k in (1, 2, 3, 5):
+            for lmin, lmax in ((0.25, 2.0), (0.05, 1.9), (0.5, 2.0)):
+                th, de = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+                Tk = C.Chebyshev.basis(k)
+                q = (1.0 - Tk((th - lam) / de) / Tk(th / de)) / lam
+                Qc = (s[:, None] * U) @ np.diag(q) @ (U.T * s[None, :])
+                Q = np.column_stack([O.chebyshev_apply(A, e, k, lmin, lmax)
+                                     for e in np.eye(Ad.shape[0])])
+                assert np.linalg.norm(Q - Qc) <= 1e-10 * np.linalg.norm(Qc), (seed, k, lmin)
+                if lmax >= lam.max():
+                    assert np.linalg.norm(Q - Q.T) <= 1e-12 * np.linalg.norm(Q)
+                    assert np.linalg.eigvalsh(0.5 * (Q + Q.T)).min() > 0
+
+
+def pin_poly_degree_one_is_jacobi(O):
+    """Degree 1 is Jacobi times 1/theta, a scale CG does not see: the same residual
+    history as the Jacobi-preconditioned deflated CG, step by step."""
+    for seed in (33, 34):
+        A, b, Z = _tiny_system(O, seed)
+        ref = O.dpcg(A, b, Z, tol=1e-10)
+        r = O.dpcg_poly(A, b, Z, degree=1, ratio=8.0, tol=1e-10)
+        assert r.iters == ref.iters and r.status == "ok"
+        assert np.allclose(r.history, ref.history, rtol=1e-7, atol=1e-12 * ref.history[0])
+
+
+def pin_poly_direct(O):
+    """Deflated CG with the polynomial preconditioner reaches the dense direct solution
+    for several degrees and intervals, and with no deflation vectors (d = 0)."""
+    for seed in (35, 36):
+        A, b, Z = _tiny_system(O, seed)
+        xd = np.linalg.solve(A.toarray(), b)
+        for k, ratio in ((2, 8.0), (3, 30.0), (5, 4.0)):
+            for ZZ in (Z, Z[:, :0]):
+                r = O.dpcg_poly(A, b, ZZ, degree=k, ratio=ratio, tol=1e-12)
+                assert r.status == "ok"
+                assert np.linalg.norm(r.x - xd) <= 1e-9 * np.linalg.norm(xd), (seed, k)
+
+
 def pin_gmres_minimal_residual(O):
     """After k steps of a first cycle the least-squares residual is the smallest
     ||r0 - B K_k y|| over the Krylov space K_k = span{r0, B r0, ..., B^(k-1) r0} of
@@ -530,7 +582,8 @@ ALL_PINS = [
     pin_row_sums, pin_symmetric_mmatrix, pin_second_difference, pin_series_resistance,
     pin_labels_bruteforce, pin_labels_layered2d, pin_components_bruteforce,
     pin_components_ndimage, pin_coarse_matrix, pin_textbook_pcg, pin_gmres_direct,
-    pin_gmres_minimal_residual, pin_gmres_monotone,
+    pin_gmres_minimal_residual, pin_gmres_monotone, pin_chebyshev_closed_form,
+    pin_poly_degree_one_is_jacobi, pin_poly_direct,
     pin_full_deflation, pin_dense_direct, pin_projectors, pin_x0_independence,
     pin_theorem21, pin_jump_independence,
 ]
