@@ -136,6 +136,40 @@ void psl_default_gmres_opts(psl_gmres_opts* o);
 int psl_solve_gmres(psl_ctx* ctx, const double* b, double* x, const psl_gmres_opts* o,
                     psl_solve_stats* st, void* stream);
 
+/* Options of psl_solve_poly. */
+typedef struct {
+  double  tol;          /* stop when ||P1 (b - A x_hat)||_2 <= tol * ||b||_2 (default 1e-8) */
+  double  ratio;        /* Chebyshev interval [lmax / ratio, lmax], ratio > 1 (default 8) */
+  double  lmax;         /* upper end; 2 bounds the spectrum of D^-1 A for every matrix
+                           psl_assemble_tpfa produces (Gershgorin) (default 2) */
+  int32_t degree;       /* Chebyshev steps per application, 1..16; 1 is Jacobi (default 2) */
+  int32_t maxit;        /* CG iteration cap (default 10000) */
+  int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
+  int32_t check_every;  /* iterations in the first run between host reads, 1..512
+                           (default 16; later runs follow the convergence rate) */
+  int32_t reserved[2];  /* must be 0 */
+} psl_poly_opts;
+
+/* Fill `o` with the polynomial-preconditioner defaults. */
+void psl_default_poly_opts(psl_poly_opts* o);
+
+/*
+ * psl_solve_poly -- deflated CG with a stronger preconditioner on the deflated system
+ * (Section 1 and the SPE10 experiment of Section 5 pair the subdomain-levelset deflation
+ * with AMG applied to the deflated system; AMG is not built here). M^-1 = q(D^-1 A) D^-1,
+ * D = diag(A): `degree` steps of the Chebyshev semi-iteration for A y = r on the interval
+ * [lmax / ratio, lmax], from y = 0 (symmetric positive definite for lmax at or above the
+ * spectrum of D^-1 A). The CG is the DEF1 loop of psl_solve (P1 from E = Z^T A Z, eq.
+ * "deflops"; projection back, eq. "projectback") in float64, two reductions per
+ * iteration; degree 1 gives the iterates of Jacobi-preconditioned DEF1.
+ *   ctx, b, x, st, stream  as for psl_solve; st->iters = CG iterations, st->outer = 1.
+ *   Work space: 5 n doubles kept on the context.
+ * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_EBREAKDOWN,
+ * PSL_ENONFINITE, PSL_EINVAL (options out of range), PSL_ENOMEM.
+ */
+int psl_solve_poly(psl_ctx* ctx, const double* b, double* x, const psl_poly_opts* o,
+                   psl_solve_stats* st, void* stream);
+
 /*
  * psl_assemble_tpfa -- face transmissibilities of the cell-centred finite-volume
  * discretisation of -div(K grad p) = q (Section 2, eqs. "pressure"/"mobility" with the

@@ -129,6 +129,10 @@ struct psl_ctx {
   double* gm_dev = nullptr;           // [3 * gm_cap + 4] dots, norm and step coefficients
   double* gm_host = nullptr;          // pinned: two slots of one Arnoldi column each
   hipEvent_t gm_ev[2] = {nullptr, nullptr};  // marks each slot's copy
+  double* pc_v = nullptr;             // polynomial-preconditioned CG: p, w, y, y2, d [5 n]
+  double* pc_part = nullptr;          // workgroup / tile partials of its two dot pairs
+  void* pc_sc = nullptr;              // its device scalars
+  void* pc_h = nullptr;               // pinned host mirror of them
   psl::Scalars* sc = nullptr;
   psl::Scalars* h_sc = nullptr;       // pinned host mirror
   psl::VecSet<double> v64;

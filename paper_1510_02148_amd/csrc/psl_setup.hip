@@ -1400,6 +1400,7 @@ extern "C" void psl_destroy(psl_ctx* c) {
   }
   for (void* blk : c->blocks) psl_internal_free(blk);
   psl_internal_pinned_put(c->h_sc);
+  psl_internal_pinned_put(c->pc_h);
   if (c->gm_host) (void)hipHostFree(c->gm_host);
   for (hipEvent_t ev : c->gm_ev)
     if (ev) (void)hipEventDestroy(ev);

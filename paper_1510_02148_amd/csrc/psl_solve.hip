@@ -2158,6 +2158,482 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
 }
 
 // =======================================================================================
+// Deflated CG with a Chebyshev polynomial preconditioner: M^-1 = q(D^-1 A) D^-1 is
+// `degree` steps of the Chebyshev semi-iteration for A y = r (Jacobi splitting, interval
+// [lmax / ratio, lmax] of the spectrum of D^-1 A, started from y = 0), a stronger
+// preconditioner on the deflated system in place of Jacobi. The CG is the two-reduction
+// DEF1 loop with its scalars on the device (step lengths, stop flag, counters), so the
+// host enqueues runs of iterations and reads the flag between runs; once the flag is set
+// every step length is zero and the remaining iterations leave x and r unchanged.
+// The first Chebyshev step, y_1 = D^-1 r / theta, is never stored: the next step forms it
+// for the cell and its neighbours from r and 1/diag(A), so degree 2 is one stencil pass.
+// =======================================================================================
+namespace {
+
+constexpr int kPcMaxDegree = 16;
+constexpr int kPcBlocks = 1024;     // workgroups of the (p, w) dot pass
+constexpr int kPcMaxRun = 512;      // iterations enqueued between two host reads, at most
+
+struct PcScalars {
+  double pw, ww;       // (p, w), (w, w) of the last operator pass (reduced together)
+  double ry_new, rr;   // (r, y), (r, r) of the last preconditioner pass (reduced together)
+  double ry, alpha, beta, goal2;
+  int32_t iters, done, status, maxit;
+};
+
+__global__ void k_pc_reset(PcScalars* s, double goal2, int maxit) {
+  s->pw = s->ww = s->ry_new = s->rr = 0.0;
+  s->ry = s->alpha = s->beta = 0.0;
+  s->goal2 = goal2;
+  s->iters = 0;
+  s->done = 0;
+  s->status = PSL_OK;
+  s->maxit = maxit;
+}
+
+// after the first preconditioner pass: rho = (r, y); stop at once when r is small enough
+__global__ void k_pc_init(PcScalars* s) {
+  s->ry = s->ry_new;
+  s->beta = 0.0;
+  if (!isfinite(s->rr) || !isfinite(s->ry)) {
+    s->done = 1;
+    s->status = PSL_ENONFINITE;
+  } else if (s->rr <= s->goal2) {
+    s->done = 1;
+  }
+}
+
+// alpha = rho / (p, P1 A p); the step cap and breakdown end the loop here
+__global__ void k_pc_alpha(PcScalars* s) {
+  s->alpha = 0.0;
+  if (s->done) return;
+  if (s->iters >= s->maxit) {
+    s->done = 1;
+    s->status = PSL_EMAXIT;
+    return;
+  }
+  const double pw = s->pw;
+  if (!isfinite(pw)) {
+    s->done = 1;
+    s->status = PSL_ENONFINITE;
+    return;
+  }
+  if (!(pw > 0.0)) {
+    s->done = 1;
+    s->status = PSL_EBREAKDOWN;
+    return;
+  }
+  s->alpha = s->ry / pw;
+  s->iters += 1;
+}
+
+// beta = rho_new / rho; stop when ||r||^2 <= goal2
+__global__ void k_pc_beta(PcScalars* s) {
+  s->beta = 0.0;
+  if (s->done) return;
+  const double rr = s->rr, ryn = s->ry_new;
+  if (!isfinite(rr) || !isfinite(ryn)) {
+    s->done = 1;
+    s->status = PSL_ENONFINITE;
+    return;
+  }
+  s->beta = ryn / s->ry;
+  s->ry = ryn;
+  if (rr <= s->goal2) s->done = 1;
+}
+
+// partials of (a, b) and (b, b), one pair per workgroup (part[blk], part[G + blk])
+__global__ void __launch_bounds__(kBlock) k_pc_dots(int64_t n, const PcScalars* s,
+                                                    const double* __restrict__ a,
+                                                    const double* __restrict__ b,
+                                                    double* part) {
+  __shared__ double lds[2 * kNW];
+  if (s->done) return;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * kBlock) {
+    const double bc = b[c];
+    acc[0] += a[c] * bc;
+    acc[1] += bc * bc;
+  }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = acc[0];
+    part[gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// x += alpha p, r -= alpha w
+__global__ void k_pc_update(int64_t n, const PcScalars* s, const double* __restrict__ p,
+                            const double* __restrict__ w, double* __restrict__ x,
+                            double* __restrict__ r) {
+  const double a = s->alpha;
+  if (a == 0.0) return;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    x[c] += a * p[c];
+    r[c] -= a * w[c];
+  }
+}
+
+// p = y + beta p (p = y when beta = 0: the first direction)
+__global__ void k_pc_dir(int64_t n, const PcScalars* s, const double* __restrict__ y,
+                         double* __restrict__ p) {
+  if (s->done) return;
+  const double beta = s->beta;
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    p[c] = beta == 0.0 ? y[c] : y[c] + beta * p[c];
+}
+
+// Degree 1: y = D^-1 r / theta. Partials (r, y), (r, r) per tile.
+template <int CPT>
+__global__ void __launch_bounds__(kBlock)
+    k_pc_jacobi(Geo g, const double* __restrict__ r, const double* __restrict__ invd,
+                double* __restrict__ y, double inv_theta, double* part, const PcScalars* s) {
+  __shared__ double lds[2 * kNW];
+  if (s->done) return;
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = load_tile(g.tiles, t);
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const int c = ix + g.nx * (iy + g.ny * iz);
+      const double rc = r[c];
+      const double yc = rc * invd[c] * inv_theta;
+      y[c] = yc;
+      acc[0] += rc * yc;
+      acc[1] += rc * rc;
+    }
+  }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x == 0) {
+    part[t] = acc[0];
+    part[g.ntiles + t] = acc[1];
+  }
+}
+
+// One step (s >= 1) of the Chebyshev recurrence from y_s, d_s:
+//   d_{s+1} = c1 d_s + c2 D^-1 (r - A y_s),  y_{s+1} = y_s + d_{s+1}.
+// FIRST: y_1 = d_1 = D^-1 r / theta, formed here for the cell and its neighbours.
+// LAST: store y_{s+1} only, with the partials (r, y), (r, r) per tile; else store d, y.
+template <int CPT, bool FIRST, bool LAST>
+__global__ void __launch_bounds__(kBlock)
+    k_pc_cheb(Geo g, const double* __restrict__ Tx, const double* __restrict__ Ty,
+              const double* __restrict__ Tz, const double* __restrict__ r,
+              const double* __restrict__ invd, const double* __restrict__ yin, double* d,
+              double* __restrict__ yout, double inv_theta, double c1, double c2, double* part,
+              const PcScalars* s) {
+  __shared__ double lds[2 * kNW];
+  if (s->done) return;
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = load_tile(g.tiles, t);
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int sxy = nx * ny;
+  // y_s at a cell: stored, or D^-1 r / theta for the first step
+  auto ys = [&](int c) -> double {
+    return FIRST ? r[c] * invd[c] * inv_theta : yin[c];
+  };
+  int cc[CPT];
+  double yc[CPT], yw[CPT], ye[CPT], ysn[CPT], yn[CPT], yb[CPT], yt[CPT];
+  double t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT], rc[CPT], ic[CPT], dc[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int j = threadIdx.x + k * kBlock;
+    cc[k] = -1;
+    if (j < T.ncell) {
+      int ix, iy, iz;
+      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+      const int c = ix + nx * (iy + ny * iz);
+      const int fx = c + (iy + ny * iz);
+      const int fy = c + nx * iz;
+      cc[k] = c;
+      yc[k] = ys(c);
+      yw[k] = ix > 0 ? ys(c - 1) : 0.0;
+      ye[k] = ix < nx - 1 ? ys(c + 1) : 0.0;
+      ysn[k] = iy > 0 ? ys(c - nx) : 0.0;
+      yn[k] = iy < ny - 1 ? ys(c + nx) : 0.0;
+      yb[k] = iz > 0 ? ys(c - sxy) : 0.0;
+      yt[k] = iz < nz - 1 ? ys(c + sxy) : 0.0;
+      t0[k] = Tx[fx];
+      t1[k] = Tx[fx + 1];
+      t2[k] = Ty[fy];
+      t3[k] = Ty[fy + nx];
+      t4[k] = Tz[c];
+      t5[k] = Tz[c + sxy];
+      rc[k] = r[c];
+      ic[k] = invd[c];
+      dc[k] = FIRST ? 0.0 : d[c];
+    }
+  }
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (cc[k] < 0) continue;
+    const double y0 = yc[k];
+    double ap = t0[k] * (y0 - yw[k]);
+    ap += t1[k] * (y0 - ye[k]);
+    ap += t2[k] * (y0 - ysn[k]);
+    ap += t3[k] * (y0 - yn[k]);
+    ap += t4[k] * (y0 - yb[k]);
+    ap += t5[k] * (y0 - yt[k]);
+    const double dprev = FIRST ? y0 : dc[k];
+    const double dn = c1 * dprev + c2 * ic[k] * (rc[k] - ap);
+    const double ynew = y0 + dn;
+    yout[cc[k]] = ynew;
+    if (LAST) {
+      acc[0] += rc[k] * ynew;
+      acc[1] += rc[k] * rc[k];
+    } else {
+      d[cc[k]] = dn;
+    }
+  }
+  if (LAST) {
+    psl::block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+      part[t] = acc[0];
+      part[g.ntiles + t] = acc[1];
+    }
+  }
+}
+
+struct PcPlan {
+  int degree;
+  double inv_theta;
+  double c1[kPcMaxDegree], c2[kPcMaxDegree];   // step s = 1 .. degree - 1
+};
+
+PcPlan pc_plan(int degree, double lmin, double lmax) {
+  PcPlan pl{};
+  pl.degree = degree;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  pl.inv_theta = 1.0 / theta;
+  double rho = 1.0 / sigma;
+  for (int s = 1; s < degree; ++s) {
+    const double rho_next = 1.0 / (2.0 * sigma - rho);
+    pl.c1[s] = rho_next * rho;
+    pl.c2[s] = 2.0 * rho_next / delta;
+    rho = rho_next;
+  }
+  return pl;
+}
+
+struct PcBufs {
+  double *p, *w, *y, *y2, *d, *part;
+  PcScalars* s;
+};
+
+PcBufs pc_bufs(psl_ctx* c) {
+  const int64_t n = c->n;
+  return PcBufs{c->pc_v, c->pc_v + n, c->pc_v + 2 * n, c->pc_v + 3 * n, c->pc_v + 4 * n,
+                c->pc_part, static_cast<PcScalars*>(c->pc_sc)};
+}
+
+int ensure_poly(psl_ctx* c) {
+  if (c->pc_v) return PSL_OK;
+  double *v = nullptr, *part = nullptr;
+  void* sc = nullptr;
+  const int64_t np = 2 * std::max<int64_t>(c->ntiles, kPcBlocks);
+  if (psl_ctx_alloc(c, reinterpret_cast<void**>(&v), sizeof(double) * size_t(c->n) * 5) ||
+      psl_ctx_alloc(c, reinterpret_cast<void**>(&part), sizeof(double) * size_t(np)) ||
+      psl_ctx_alloc(c, &sc, sizeof(PcScalars)))
+    return PSL_ENOMEM;
+  void* h = psl_internal_pinned_get(sizeof(PcScalars));
+  if (!h) return PSL_ENOMEM;
+  c->pc_v = v;
+  c->pc_part = part;
+  c->pc_sc = sc;
+  c->pc_h = h;
+  return PSL_OK;
+}
+
+template <bool FIRST, bool LAST>
+struct PcChebC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, const PcBufs& B, const double* r, const double* yin,
+                    double* yout, double inv_theta, double c1, double c2, hipStream_t st) {
+      hipLaunchKernelGGL((k_pc_cheb<CPT, FIRST, LAST>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), static_cast<const double*>(c->Tx),
+                         static_cast<const double*>(c->Ty), static_cast<const double*>(c->Tz),
+                         r, static_cast<const double*>(c->invdiag), yin, B.d, yout, inv_theta,
+                         c1, c2, B.part, static_cast<const PcScalars*>(B.s));
+    }
+  };
+};
+
+template <int CPT>
+struct PcJacobiF {
+  static void run(psl_ctx* c, const PcBufs& B, const double* r, double inv_theta,
+                  hipStream_t st) {
+    hipLaunchKernelGGL((k_pc_jacobi<CPT>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), r,
+                       static_cast<const double*>(c->invdiag), B.y, inv_theta, B.part,
+                       static_cast<const PcScalars*>(B.s));
+  }
+};
+
+// y = M^-1 r (into B.y) with (r, y), (r, r) reduced into s->ry_new, s->rr
+void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double* r,
+                     hipStream_t st) {
+  const int steps = pl.degree - 1;
+  if (steps == 0) {
+    with_cpt<PcJacobiF>(c->cpt, c, B, r, pl.inv_theta, st);
+  } else {
+    // step s writes B.y when (steps - s) is even, so the last step lands in B.y
+    const double* yin = nullptr;
+    for (int s = 1; s <= steps; ++s) {
+      double* yout = ((steps - s) % 2 == 0) ? B.y : B.y2;
+      const bool first = s == 1, last = s == steps;
+      if (first && last)
+        with_cpt<PcChebC<true, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                  pl.c1[s], pl.c2[s], st);
+      else if (first)
+        with_cpt<PcChebC<true, false>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                   pl.c1[s], pl.c2[s], st);
+      else if (last)
+        with_cpt<PcChebC<false, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                   pl.c1[s], pl.c2[s], st);
+      else
+        with_cpt<PcChebC<false, false>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                    pl.c1[s], pl.c2[s], st);
+      yin = yout;
+    }
+  }
+  hipLaunchKernelGGL(k_gm_reduce, dim3(2), dim3(kBlock), 0, st,
+                     static_cast<const double*>(B.part), c->ntiles, &B.s->ry_new);
+}
+
+// one CG iteration: w = P1 A p, alpha, x and r, y = M^-1 r, beta, p
+void pc_iteration(psl_ctx* c, const PcBufs& B, const PcPlan& pl, double* x, hipStream_t st) {
+  const int64_t n = c->n;
+  launch_stencil<double, 0>(c, B.p, nullptr, B.w, st);
+  launch_coarse<0, 0>(c, 0, st);
+  launch_outer_deflate(c, nullptr, B.w, B.w, st);
+  const int G = int(std::min<int64_t>(kPcBlocks, (n + kBlock - 1) / kBlock));
+  hipLaunchKernelGGL(k_pc_dots, dim3(G), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
+                     static_cast<const double*>(B.w), B.part);
+  hipLaunchKernelGGL(k_gm_reduce, dim3(2), dim3(kBlock), 0, st,
+                     static_cast<const double*>(B.part), G, &B.s->pw);
+  hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(1), 0, st, B.s);
+  hipLaunchKernelGGL(k_pc_update, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
+                     static_cast<const double*>(B.w), x, c->r64);
+  pc_precondition(c, B, pl, c->r64, st);
+  hipLaunchKernelGGL(k_pc_beta, dim3(1), dim3(1), 0, st, B.s);
+  hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
+}
+
+int pc_read(psl_ctx* c, const PcBufs& B, hipStream_t st) {
+  PSL_HIP(hipMemcpyAsync(c->pc_h, B.s, sizeof(PcScalars), hipMemcpyDeviceToHost, st));
+  PSL_HIP(hipStreamSynchronize(st));
+  return PSL_OK;
+}
+
+}  // namespace
+
+extern "C" void psl_default_poly_opts(psl_poly_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->ratio = 8.0;
+  o->lmax = 2.0;
+  o->degree = 2;
+  o->maxit = 10000;
+  o->use_x0 = 0;
+  o->check_every = 16;
+}
+
+extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_poly_opts* o_in,
+                              psl_solve_stats* st_out, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!c || !b || !x) return PSL_EINVAL;
+  psl_poly_opts o;
+  psl_default_poly_opts(&o);
+  if (o_in) o = *o_in;
+  if (!(o.tol > 0.0) || !(o.ratio > 1.0) || !std::isfinite(o.ratio) || !(o.lmax > 0.0) ||
+      !std::isfinite(o.lmax) || o.degree < 1 || o.degree > kPcMaxDegree || o.maxit < 0 ||
+      (o.use_x0 != 0 && o.use_x0 != 1) || o.check_every < 1 || o.check_every > kPcMaxRun ||
+      o.reserved[0] || o.reserved[1])
+    return PSL_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  psl_solve_stats stats;
+  std::memset(&stats, 0, sizeof(stats));
+  auto finish = [&](int status) {
+    stats.status = status;
+    stats.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st_out) *st_out = stats;
+    return status;
+  };
+  int rc = ensure_poly(c);
+  if (rc != PSL_OK) return finish(rc);
+  const int64_t n = c->n;
+  const PcBufs B = pc_bufs(c);
+  const PcPlan pl = pc_plan(o.degree, o.lmax / o.ratio, o.lmax);
+  hipLaunchKernelGGL(k_norm2, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), b, red(c, 1));
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->bnorm2);
+  if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+  const double bnorm = std::sqrt(c->h_sc->bnorm2);
+  stats.bnorm = bnorm;
+  if (!std::isfinite(bnorm)) return finish(PSL_ENONFINITE);
+  if (!o.use_x0 || bnorm == 0.0)
+    hipLaunchKernelGGL(k_zero, dim3(elem_grid(n)), dim3(kBlock), 0, st, x, int(n));
+  if (bnorm == 0.0) {
+    PSL_HIP(hipStreamSynchronize(st));
+    return finish(PSL_OK);
+  }
+  const double goal = o.tol * bnorm;
+  hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, goal * goal, int(o.maxit));
+  // rhat = P1 (b - A x) (x takes the coarse part, which the final projection recomputes)
+  enqueue_outer_step(c, b, x, st);
+  pc_precondition(c, B, pl, c->r64, st);
+  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(1), 0, st, B.s);
+  hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
+  if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
+  const PcScalars* h = static_cast<const PcScalars*>(c->pc_h);
+  // runs of iterations between host reads: check_every first, then the count the last
+  // run's convergence rate predicts (iterations after the stop are cheap no-ops)
+  int run = o.check_every;
+  double rr_prev = h->rr;
+  int it_prev = 0;
+  while (!h->done) {
+    for (int i = 0; i < run; ++i) pc_iteration(c, B, pl, x, st);
+    if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
+    if (h->done) break;
+    const int its = h->iters - it_prev;
+    if (its > 0 && h->rr > 0.0 && h->rr < rr_prev) {
+      const double per_it = std::log(h->rr / rr_prev) / its;   // < 0
+      const double need = std::log(h->goal2 / h->rr) / per_it;
+      run = int(std::min<double>(kPcMaxRun, std::max(1.0, std::ceil(need))));
+    } else {
+      run = o.check_every;
+    }
+    rr_prev = h->rr;
+    it_prev = h->iters;
+  }
+  stats.iters = h->iters;
+  stats.outer = 1;
+  const int status = h->status;
+  // projection back: x = P2 x + x* = x + Z E^-1 Z^T (b - A x)
+  enqueue_outer_step(c, b, x, st);
+  launch_stencil<double, 1>(c, x, b, c->t64, st);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
+  if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+  stats.relres_true = std::sqrt(c->h_sc->rr) / bnorm;
+  return finish(status);
+}
+
+// =======================================================================================
 // Batched solve: independent systems, each with its own context, advance together. One
 // launch of each float64 CG kernel covers the tiles of every system through a (system,
 // tile) work list and a per-system argument table; a converged system's workgroups return

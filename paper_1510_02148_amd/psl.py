@@ -69,6 +69,12 @@ class psl_gmres_opts(ctypes.Structure):
                 ("use_x0", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
+class psl_poly_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("ratio", ctypes.c_double), ("lmax", ctypes.c_double),
+                ("degree", ctypes.c_int32), ("maxit", ctypes.c_int32), ("use_x0", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I32P = ctypes.POINTER(ctypes.c_int32)
@@ -111,13 +117,17 @@ _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
 _default_gmres_opts = _sig("psl_default_gmres_opts", None, [ctypes.POINTER(psl_gmres_opts)])
 _solve_gmres = _sig("psl_solve_gmres", ctypes.c_int,
                     [_P, _P, _P, ctypes.POINTER(psl_gmres_opts), ctypes.POINTER(psl_solve_stats), _P])
+_default_poly_opts = _sig("psl_default_poly_opts", None, [ctypes.POINTER(psl_poly_opts)])
+_solve_poly = _sig("psl_solve_poly", ctypes.c_int,
+                   [_P, _P, _P, ctypes.POINTER(psl_poly_opts), ctypes.POINTER(psl_solve_stats), _P])
 
 EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E", "psl_setup_E_ex",
             "psl_default_setup_opts", "psl_solve",
             "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
             "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info",
-            "psl_solve_gmres", "psl_default_gmres_opts")
+            "psl_solve_gmres", "psl_default_gmres_opts", "psl_solve_poly",
+            "psl_default_poly_opts")
 (KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL,
  KERNEL_GMRES_PASS) = range(6)
 
@@ -315,6 +325,34 @@ def psl_solve_gmres(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = N
                       _stream())
     if check:
         _check(rc, "psl_solve_gmres")
+    stats = st.as_dict()
+    stats["status_str"] = psl_status_str(rc)
+    return x, stats
+
+
+def psl_solve_poly(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
+                   tol: Optional[float] = None, degree: Optional[int] = None,
+                   ratio: Optional[float] = None, lmax: Optional[float] = None,
+                   maxit: Optional[int] = None, check_every: Optional[int] = None,
+                   use_x0: bool = False, check: bool = False):
+    """Deflated CG with the Chebyshev polynomial preconditioner; returns (x, stats dict)."""
+    o = psl_poly_opts()
+    _default_poly_opts(ctypes.byref(o))
+    for name, val in (("tol", tol), ("degree", degree), ("ratio", ratio), ("lmax", lmax),
+                      ("maxit", maxit), ("check_every", check_every)):
+        if val is not None:
+            setattr(o, name, val)
+    o.use_x0 = 1 if use_x0 else 0
+    if x is None:
+        if use_x0:
+            raise ValueError("use_x0 needs x")
+        x = torch.empty_like(b)
+    st = psl_solve_stats()
+    rc = _solve_poly(ctx.handle, _dev(b, torch.float64, ctx.n, "b"),
+                     _dev(x, torch.float64, ctx.n, "x"), ctypes.byref(o), ctypes.byref(st),
+                     _stream())
+    if check:
+        _check(rc, "psl_solve_poly")
     stats = st.as_dict()
     stats["status_str"] = psl_status_str(rc)
     return x, stats

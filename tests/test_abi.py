@@ -52,11 +52,12 @@ def test_binding_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
         " sizeof(psl_solve_stats), offsetof(psl_solve_opts, tau_inner),"
         " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_opts, mixed_floor),"
         " offsetof(psl_solve_stats, relres_true), sizeof(psl_grid), sizeof(psl_setup_opts),"
-        " sizeof(psl_gmres_opts), offsetof(psl_gmres_opts, use_x0));"
+        " sizeof(psl_gmres_opts), offsetof(psl_gmres_opts, use_x0), sizeof(psl_poly_opts),"
+        " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every));"
         "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -67,7 +68,9 @@ def test_binding_struct_layout_matches_c(tmp_path):
             psl.psl_solve_opts.tau_inner.offset, psl.psl_solve_opts.check_every.offset,
             psl.psl_solve_opts.mixed_floor.offset, psl.psl_solve_stats.relres_true.offset,
             ctypes.sizeof(psl.psl_grid), ctypes.sizeof(psl.psl_setup_opts),
-            ctypes.sizeof(psl.psl_gmres_opts), psl.psl_gmres_opts.use_x0.offset]
+            ctypes.sizeof(psl.psl_gmres_opts), psl.psl_gmres_opts.use_x0.offset,
+            ctypes.sizeof(psl.psl_poly_opts), psl.psl_poly_opts.degree.offset,
+            psl.psl_poly_opts.check_every.offset]
     assert got == want
 
 
@@ -84,6 +87,15 @@ def test_default_gmres_opts(lib):
     psl._default_gmres_opts(ctypes.byref(o))
     assert o.tol == 1e-8 and o.maxit == 10000 and o.restart == 30 and o.use_x0 == 0
     assert list(o.reserved) == [0, 0, 0]
+
+
+def test_default_poly_opts(lib):
+    from paper_1510_02148_amd import psl
+    o = psl.psl_poly_opts()
+    psl._default_poly_opts(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.ratio == 8.0 and o.lmax == 2.0 and o.degree == 2
+    assert o.maxit == 10000 and o.use_x0 == 0 and o.check_every == 16
+    assert list(o.reserved) == [0, 0]
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):
@@ -103,6 +115,7 @@ def test_invalid_arguments_rejected_before_any_device_work(lib):
     assert rc == psl.EINVAL
     assert psl._solve(None, None, None, None, None, None) == psl.EINVAL
     assert psl._solve_gmres(None, None, None, None, None, None) == psl.EINVAL
+    assert psl._solve_poly(None, None, None, None, None, None) == psl.EINVAL
     rc = psl._build_z_cc(ctypes.byref(g), ctypes.c_void_p(16), ns, None, 0, None, 0,
                          ctypes.c_void_p(16), ctypes.byref(d), None)
     assert rc == psl.EINVAL

@@ -226,6 +226,100 @@ def test_gmres_restarts_cap_and_zero_rhs(gpu_lib):
         assert stb["status_str"] == psl.psl_status_str(psl.EINVAL)
 
 
+# deflated CG with the Chebyshev polynomial preconditioner (psl_solve_poly)
+
+POLY_CASES = [("c1", 1, 2, 8.0, False), ("c2", 4, 1, 8.0, False), ("c2", 4, 2, 8.0, False),
+              ("c2", 4, 3, 30.0, False), ("chan", 0, 2, 8.0, False), ("chan", 0, 5, 4.0, False),
+              ("chan", 0, 2, 8.0, True)]
+
+
+@pytest.mark.parametrize("name,scale,degree,ratio,comp", POLY_CASES,
+                         ids=[f"{c[0]}/{c[1]}-deg{c[2]}-ratio{c[3]:g}{'-comp' if c[4] else ''}"
+                              for c in POLY_CASES])
+def test_poly_parity(gpu_lib, name, scale, degree, ratio, comp):
+    """The polynomial-preconditioned deflated CG against the oracle's: the same solution
+    (x_ref = the oracle's Jacobi DPCG at 1e-12), a 1e-8 true residual, and the oracle's
+    iteration count for the same degree and interval (degree 1: Jacobi's)."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _op_problem(name, scale)
+    say(f"poly {name}/{scale} grid={p.grid} degree={degree} ratio={ratio} components={comp}")
+    s = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr), components=comp)
+    x, st = psl.psl_solve_poly(s.ctx, dev(p.q), degree=degree, ratio=ratio)
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    labels = O.levelset_components if comp else O.levelset_labels
+    lab, d = labels(p.grid, p.K, p.nsub, p.thr)
+    Z = O.deflation_matrix(lab, d)
+    co = O.Coarse(A, Z)
+    ref = O.dpcg_poly(A, b, Z, degree=degree, ratio=ratio, tol=1e-8, coarse=co)
+    xr = O.dpcg(A, b, Z, tol=1e-12, coarse=co).x
+    say(f"  status={st['status_str']} iters={st['iters']} (oracle {ref.iters})")
+    assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
+    assert st["relres_true"] <= 1e-8
+    assert np.linalg.norm(host(x) - xr) / np.linalg.norm(xr) <= 1e-6
+    assert abs(st["iters"] - ref.iters) <= max(2, 0.03 * ref.iters)
+    if degree == 1:
+        assert abs(st["iters"] - O.dpcg(A, b, Z, tol=1e-8, coarse=co).iters) <= 2
+
+
+def test_poly_result_independent_of_host_checks(gpu_lib):
+    """The host's read interval only changes how many launches run after the stop flag
+    (as no-ops): x and the iteration count are bit-identical for 1, 16 and 512."""
+    psl = gpu_lib
+    p = pi.config("c2", scale=4)
+    say("poly host-check independence c2/4")
+    s = _setup(psl, p)
+    b = dev(p.q)
+    runs = [psl.psl_solve_poly(s.ctx, b, check_every=k) for k in (1, 16, 512)]
+    for x, st in runs:
+        assert st["status"] == 0
+    for x, st in runs[1:]:
+        assert torch.equal(x, runs[0][0]) and st["iters"] == runs[0][1]["iters"]
+
+
+def test_poly_cap_zero_rhs_start_and_invalid(gpu_lib):
+    """The iteration cap returns PSL_EMAXIT after exactly that many iterations with the
+    projected iterate; b = 0 gives x = 0; a start vector gives the same solution; options
+    out of range are rejected."""
+    psl = gpu_lib
+    p = pi.config("c2", scale=4)
+    say("poly cap / zero rhs / x0 / invalid c2/4")
+    s = _setup(psl, p)
+    b = dev(p.q)
+    x, st = psl.psl_solve_poly(s.ctx, b)
+    assert st["status"] == 0
+    _, stc = psl.psl_solve_poly(s.ctx, b, maxit=5)
+    assert stc["status"] == psl.EMAXIT and stc["iters"] == 5 and stc["relres_true"] > 1e-8
+    x0, st0 = psl.psl_solve_poly(s.ctx, torch.zeros_like(b))
+    assert st0["status"] == 0 and torch.count_nonzero(x0) == 0
+    xs = x + 1e-3 * torch.randn_like(x)
+    xw, stw = psl.psl_solve_poly(s.ctx, b, xs.clone(), use_x0=True)
+    assert stw["status"] == 0 and stw["iters"] < st["iters"]
+    assert torch.linalg.norm(xw - x) / torch.linalg.norm(x) <= 1e-6
+    for kw in ({"degree": 0}, {"degree": 17}, {"ratio": 1.0}, {"lmax": 0.0},
+               {"check_every": 0}, {"check_every": 513}):
+        _, stb = psl.psl_solve_poly(s.ctx, b, **kw)
+        assert stb["status_str"] == psl.psl_status_str(psl.EINVAL), kw
+
+
+def test_poly_full_size(gpu_lib):
+    """128x128x64 layered (the benchmark workload) with the default degree and interval:
+    the oracle's residual of the GPU x, and the oracle's iteration count."""
+    psl = gpu_lib
+    p = pi.config("c2")
+    say(f"poly full size c2 grid={p.grid}")
+    s = _setup(psl, p)
+    x, st = psl.psl_solve_poly(s.ctx, dev(p.q))
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    lab, d = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+    Z = O.deflation_matrix(lab, d)
+    ref = O.dpcg_poly(A, b, Z, degree=2, ratio=8.0, tol=1e-8)
+    say(f"  status={st['status_str']} iters={st['iters']} (oracle {ref.iters})")
+    assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
+    assert abs(st["iters"] - ref.iters) <= max(2, 0.03 * ref.iters)
+    assert np.linalg.norm(host(x) - ref.x) / np.linalg.norm(ref.x) <= 1e-6
+
+
 # ------------------------------------------------------------------ operators
 
 def _setup(psl, p):
