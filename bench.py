@@ -64,10 +64,24 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
         return 12 * w * n + m_faces * (12 + w)   # read v, r, u, p, q, x, 1/diag; write 5
     if kernel == "coarse":           # read E^-1 (float64), s; write e
         return 8.0 * d * d + 4 * 8 * d
+    if kernel == "cheb_step":         # read y, r, 1/diag, d, T; write y (float64)
+        return 8.0 * (4 * n + faces) + 8.0 * n
     if kernel.startswith("gs_pass"):  # read nv basis vectors and w, write w (float64)
         nv = int(kernel.split("_")[-1])
         return (nv + 2) * 8.0 * n
     raise KeyError(kernel)
+
+
+SOLVER_NAMES = {
+    "dpcg": lambda a: "DEF1-PCG",
+    "gmres": lambda a: f"deflated GMRES({a.restart})",
+    "poly": lambda a: f"DEF1-PCG with Chebyshev preconditioner (degree {a.degree}, ratio {a.ratio:g})",
+}
+SOLVER_TAGS = {
+    "dpcg": lambda a: "dpcg",
+    "gmres": lambda a: f"pdgmres({a.restart})",
+    "poly": lambda a: f"dpcg-cheb(degree {a.degree}, ratio {a.ratio:g})",
+}
 
 
 def counter_traffic(kernel: str, workload: str, mode: str):
@@ -345,9 +359,13 @@ def main():
     ap.add_argument("--labels", default="regions", choices=["regions", "components"],
                     help="deflation space: one vector per (subdomain, class) region, or per "
                          "connected component of each region (psl_build_Z_cc)")
-    ap.add_argument("--solver", default="dpcg", choices=["dpcg", "gmres"],
-                    help="deflated CG (default) or the paper's deflated GMRES(m), float64")
+    ap.add_argument("--solver", default="dpcg", choices=["dpcg", "gmres", "poly"],
+                    help="deflated CG (default), the paper's deflated GMRES(m), or deflated "
+                         "CG with the Chebyshev polynomial preconditioner; the last two float64")
     ap.add_argument("--restart", type=int, default=30, help="m of GMRES(m)")
+    ap.add_argument("--degree", type=int, default=3, help="Chebyshev steps (--solver poly)")
+    ap.add_argument("--ratio", type=float, default=30.0,
+                    help="Chebyshev interval [2 / ratio, 2] (--solver poly)")
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -400,6 +418,9 @@ def main():
         t1 = time.perf_counter()
         if args.solver == "gmres":
             x, st = psl.psl_solve_gmres(s.ctx, b, tol=prob.tol, restart=args.restart)
+        elif args.solver == "poly":
+            x, st = psl.psl_solve_poly(s.ctx, b, tol=prob.tol, degree=args.degree,
+                                       ratio=args.ratio)
         else:
             x, st = psl.psl_solve(s.ctx, b, tol=prob.tol, mode=mode)
         torch.cuda.synchronize()
@@ -423,8 +444,8 @@ def main():
             f"outer={st['outer']} relres={st['relres_true']:.2e}")
         return s, x, rec, wall
 
-    if args.solver == "gmres":
-        args.mode = "fp64"        # the GMRES path is float64 only
+    if args.solver in ("gmres", "poly"):
+        args.mode = "fp64"        # the GMRES and polynomial paths are float64 only
     mode = psl.MIXED if args.mode == "mixed" else psl.FP64
     s, x, rec, wall = run_leg(mode, args.steps, args.warmup, args.mode)
     st = rec[-1][0]
@@ -455,6 +476,10 @@ def main():
         # largest basis; the CG stencil stays as the SpMV bandwidth reference
         ids = {"stencil": psl.KERNEL_STENCIL,
                f"gs_pass_{min(args.restart, 32)}": psl.KERNEL_GMRES_PASS}
+    if args.solver == "poly":
+        # the last Chebyshev step (the widest pass of a degree >= 3 application); the CG
+        # stencil stays as the SpMV bandwidth reference
+        ids = {"stencil": psl.KERNEL_STENCIL, "cheb_step": psl.KERNEL_POLY_STEP}
     for name, kid in ids.items():
         psl.psl_bench_kernel(s.ctx, kid, mode, 3)            # warm
         e0 = torch.cuda.Event(enable_timing=True)
@@ -481,7 +506,10 @@ def main():
     copy_us = e0.elapsed_time(e1) * 1e3 / 10
     copy_gbs = 2 * src.numel() * 4 / (copy_us * 1e-6) / 1e9
     del src, dst
-    dominant = max(kernels, key=lambda k: kernels[k]["us"])
+    if args.solver == "dpcg":
+        dominant = max(kernels, key=lambda k: kernels[k]["us"])
+    else:   # the solver's own pass; the CG stencil is only the SpMV reference there
+        dominant = next(k for k in kernels if k != "stencil")
     kd = kernels[dominant]
     traffic = counter_traffic(dominant, args.workload, args.mode)
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
@@ -507,13 +535,15 @@ def main():
             Z = O.deflation_matrix(lab, dd)
             if args.solver == "gmres":
                 res = O.pdgmres(A, bh, Z, m=args.restart, tol=prob.tol)
+            elif args.solver == "poly":
+                res = O.dpcg_poly(A, bh, Z, degree=args.degree, ratio=args.ratio, tol=prob.tol)
             else:
                 res = O.dpcg(A, bh, Z, tol=prob.tol)
             cpu_s = time.perf_counter() - t0
         xg = x.cpu().numpy()
         cpu = {"value": round(cpu_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
                "sample": f"one full {args.workload} solve (assembly, {args.labels} labels, E + Cholesky, "
-                         f"{'deflated GMRES(%d)' % args.restart if args.solver == 'gmres' else 'DEF1-PCG'}"
+                         f"{SOLVER_NAMES[args.solver](args)}"
                          f" to 1e-8), {res.iters} iterations, 1 thread",
                "host_cores_available": len(os.sched_getaffinity(0)),
                "gpu_vs_oracle_rel_err": float(np.linalg.norm(xg - res.x) / np.linalg.norm(res.x)),
@@ -528,7 +558,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "grid": list(prob.grid),
                    "nsub": list(prob.nsub), "d": d, "labels": args.labels,
-                   "solver": (f"pdgmres({args.restart})" if args.solver == "gmres" else "dpcg"),
+                   "solver": SOLVER_TAGS[args.solver](args),
                    "tol": prob.tol,
                    "mode": args.mode, "seed": args.seed, "tile_cells": tiles},
         "converged": bool(ok), "iterations": st["iters"], "outer": st["outer"],

@@ -139,10 +139,10 @@ int psl_solve_gmres(psl_ctx* ctx, const double* b, double* x, const psl_gmres_op
 /* Options of psl_solve_poly. */
 typedef struct {
   double  tol;          /* stop when ||P1 (b - A x_hat)||_2 <= tol * ||b||_2 (default 1e-8) */
-  double  ratio;        /* Chebyshev interval [lmax / ratio, lmax], ratio > 1 (default 8) */
+  double  ratio;        /* Chebyshev interval [lmax / ratio, lmax], ratio > 1 (default 30) */
   double  lmax;         /* upper end; 2 bounds the spectrum of D^-1 A for every matrix
                            psl_assemble_tpfa produces (Gershgorin) (default 2) */
-  int32_t degree;       /* Chebyshev steps per application, 1..16; 1 is Jacobi (default 2) */
+  int32_t degree;       /* Chebyshev steps per application, 1..16; 1 is Jacobi (default 3) */
   int32_t maxit;        /* CG iteration cap (default 10000) */
   int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
   int32_t check_every;  /* iterations in the first run between host reads, 1..512
@@ -352,6 +352,10 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
 #define PSL_KERNEL_GMRES_PASS     5  /* deflated GMRES: w -= V h with the dots V^T w (fused
                                         Gram-Schmidt pass over min(m, 32) basis vectors,
                                         float64; needs a prior psl_solve_gmres, PSL_FP64) */
+#define PSL_KERNEL_POLY_STEP      6  /* psl_solve_poly: the last Chebyshev step of a degree >= 3
+                                        preconditioner application (stencil on y with the
+                                        d, y updates and the (r, y), (r, r) partials; needs a
+                                        prior psl_solve_poly, PSL_FP64) */
 
 /*
  * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
@@ -363,8 +367,11 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
  * PSL_KERNEL_GMRES_PASS times the Gram-Schmidt pass of psl_solve_gmres (Algorithm 1's
  * Arnoldi step) against the first min(m, 32) basis vectors of the longest restart length m
  * solved on this context so far; it overwrites basis vector min(m, 32).
- * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1; GMRES pass without a
- * prior psl_solve_gmres or in PSL_MIXED), PSL_ENOMEM.
+ * PSL_KERNEL_POLY_STEP times the last Chebyshev step of psl_solve_poly's preconditioner
+ * (degree >= 3) on its work vectors and overwrites them.
+ * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1; GMRES pass or
+ * Chebyshev step without a prior psl_solve_gmres / psl_solve_poly, or in PSL_MIXED),
+ * PSL_ENOMEM.
  */
 int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
 

@@ -1735,18 +1735,23 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
 
 namespace {
 int gm_bench_pass(psl_ctx* c, int reps, hipStream_t st);   // with the GMRES kernels below
+int pc_bench_step(psl_ctx* c, int reps, hipStream_t st);   // with the polynomial CG below
 }
 
 extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t reps,
                                 void* stream) {
   psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (!c || reps < 1 || (mode != PSL_FP64 && mode != PSL_MIXED) || kernel < 0 ||
-      kernel > PSL_KERNEL_GMRES_PASS)
+      kernel > PSL_KERNEL_POLY_STEP)
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (kernel == PSL_KERNEL_GMRES_PASS) {
     if (mode != PSL_FP64 || c->gm_cap < 2) return PSL_EINVAL;
     return gm_bench_pass(c, reps, st);
+  }
+  if (kernel == PSL_KERNEL_POLY_STEP) {
+    if (mode != PSL_FP64 || !c->pc_v) return PSL_EINVAL;
+    return pc_bench_step(c, reps, st);
   }
   int rc = mode == PSL_MIXED ? ensure_sd<float>(c) : ensure_vecs<double>(c);
   if (rc != PSL_OK) return rc;
@@ -2532,6 +2537,20 @@ void pc_iteration(psl_ctx* c, const PcBufs& B, const PcPlan& pl, double* x, hipS
                      static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
 }
 
+// reps launches of the last Chebyshev step (y2, d -> y with the dot partials), the pass
+// every degree >= 3 application ends with; the stop flag is cleared first
+int pc_bench_step(psl_ctx* c, int reps, hipStream_t st) {
+  const PcBufs B = pc_bufs(c);
+  hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, 0.0, 0);
+  const PcPlan pl = pc_plan(3, 2.0 / 30.0, 2.0);
+  for (int i = 0; i < reps; ++i)
+    with_cpt<PcChebC<false, true>::template F>(c->cpt, c, B, static_cast<const double*>(c->r64),
+                                               static_cast<const double*>(B.y2), B.y,
+                                               pl.inv_theta, pl.c1[2], pl.c2[2], st);
+  PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
 int pc_read(psl_ctx* c, const PcBufs& B, hipStream_t st) {
   PSL_HIP(hipMemcpyAsync(c->pc_h, B.s, sizeof(PcScalars), hipMemcpyDeviceToHost, st));
   PSL_HIP(hipStreamSynchronize(st));
@@ -2544,9 +2563,9 @@ extern "C" void psl_default_poly_opts(psl_poly_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
   o->tol = 1e-8;
-  o->ratio = 8.0;
+  o->ratio = 30.0;
   o->lmax = 2.0;
-  o->degree = 2;
+  o->degree = 3;
   o->maxit = 10000;
   o->use_x0 = 0;
   o->check_every = 16;

@@ -129,7 +129,7 @@ EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E",
             "psl_solve_gmres", "psl_default_gmres_opts", "psl_solve_poly",
             "psl_default_poly_opts")
 (KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL,
- KERNEL_GMRES_PASS) = range(6)
+ KERNEL_GMRES_PASS, KERNEL_POLY_STEP) = range(7)
 
 
 class PslError(RuntimeError):

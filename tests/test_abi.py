@@ -93,7 +93,7 @@ def test_default_poly_opts(lib):
     from paper_1510_02148_amd import psl
     o = psl.psl_poly_opts()
     psl._default_poly_opts(ctypes.byref(o))
-    assert o.tol == 1e-8 and o.ratio == 8.0 and o.lmax == 2.0 and o.degree == 2
+    assert o.tol == 1e-8 and o.ratio == 30.0 and o.lmax == 2.0 and o.degree == 3
     assert o.maxit == 10000 and o.use_x0 == 0 and o.check_every == 16
     assert list(o.reserved) == [0, 0]
 

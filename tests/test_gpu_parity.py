@@ -303,17 +303,17 @@ def test_poly_cap_zero_rhs_start_and_invalid(gpu_lib):
 
 
 def test_poly_full_size(gpu_lib):
-    """128x128x64 layered (the benchmark workload) with the default degree and interval:
+    """128x128x64 layered (the benchmark workload) with the default degree 3 on [2/30, 2]:
     the oracle's residual of the GPU x, and the oracle's iteration count."""
     psl = gpu_lib
     p = pi.config("c2")
     say(f"poly full size c2 grid={p.grid}")
     s = _setup(psl, p)
-    x, st = psl.psl_solve_poly(s.ctx, dev(p.q))
+    x, st = psl.psl_solve_poly(s.ctx, dev(p.q), degree=3, ratio=30.0)
     A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
     lab, d = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
     Z = O.deflation_matrix(lab, d)
-    ref = O.dpcg_poly(A, b, Z, degree=2, ratio=8.0, tol=1e-8)
+    ref = O.dpcg_poly(A, b, Z, degree=3, ratio=30.0, tol=1e-8)
     say(f"  status={st['status_str']} iters={st['iters']} (oracle {ref.iters})")
     assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
     assert abs(st["iters"] - ref.iters) <= max(2, 0.03 * ref.iters)
