@@ -2176,18 +2176,17 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
 namespace {
 
 constexpr int kPcMaxDegree = 16;
-constexpr int kPcBlocks = 1024;     // workgroups of the (p, w) dot pass
 constexpr int kPcMaxRun = 512;      // iterations enqueued between two host reads, at most
 
 struct PcScalars {
-  double pw, ww;       // (p, w), (w, w) of the last operator pass (reduced together)
+  double pw, spare;    // (p, P1 A p) of the last step
   double ry_new, rr;   // (r, y), (r, r) of the last preconditioner pass (reduced together)
   double ry, alpha, beta, goal2;
   int32_t iters, done, status, maxit;
 };
 
 __global__ void k_pc_reset(PcScalars* s, double goal2, int maxit) {
-  s->pw = s->ww = s->ry_new = s->rr = 0.0;
+  s->pw = s->spare = s->ry_new = s->rr = 0.0;
   s->ry = s->alpha = s->beta = 0.0;
   s->goal2 = goal2;
   s->iters = 0;
@@ -2208,16 +2207,30 @@ __global__ void k_pc_init(PcScalars* s) {
   }
 }
 
-// alpha = rho / (p, P1 A p); the step cap and breakdown end the loop here
-__global__ void k_pc_alpha(PcScalars* s) {
+// alpha = rho / (p, P1 A p) with (p, P1 A p) = (p, A p) - s^T E^-1 s, s = Z^T A p (A
+// symmetric): the per-tile (p, A p) partials of the stencil pass minus the per-workgroup
+// s^T e partials of the coarse pass, summed in a fixed order by one workgroup. The step
+// cap and breakdown end the loop here.
+__global__ void __launch_bounds__(kBlock) k_pc_alpha(PcScalars* s, const double* red0,
+                                                     int ntiles, const double* cpart, int G) {
+  __shared__ double lds[2 * kNW];
+  const bool done = s->done != 0;
+  double acc[2] = {0.0, 0.0};
+  if (!done) {
+    for (int t = threadIdx.x; t < ntiles; t += kBlock) acc[0] += red0[t];
+    for (int g = threadIdx.x; g < G; g += kBlock) acc[1] += cpart[g];
+  }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x != 0) return;
   s->alpha = 0.0;
-  if (s->done) return;
+  if (done) return;
   if (s->iters >= s->maxit) {
     s->done = 1;
     s->status = PSL_EMAXIT;
     return;
   }
-  const double pw = s->pw;
+  const double pw = acc[0] - acc[1];
+  s->pw = pw;
   if (!isfinite(pw)) {
     s->done = 1;
     s->status = PSL_ENONFINITE;
@@ -2247,37 +2260,28 @@ __global__ void k_pc_beta(PcScalars* s) {
   if (rr <= s->goal2) s->done = 1;
 }
 
-// partials of (a, b) and (b, b), one pair per workgroup (part[blk], part[G + blk])
-__global__ void __launch_bounds__(kBlock) k_pc_dots(int64_t n, const PcScalars* s,
-                                                    const double* __restrict__ a,
-                                                    const double* __restrict__ b,
-                                                    double* part) {
-  __shared__ double lds[2 * kNW];
-  if (s->done) return;
-  double acc[2] = {0.0, 0.0};
-  for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * kBlock) {
-    const double bc = b[c];
-    acc[0] += a[c] * bc;
-    acc[1] += bc * bc;
-  }
-  psl::block_sum<2>(acc, lds);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = acc[0];
-    part[gridDim.x + blockIdx.x] = acc[1];
-  }
-}
-
-// x += alpha p, r -= alpha w
-__global__ void k_pc_update(int64_t n, const PcScalars* s, const double* __restrict__ p,
-                            const double* __restrict__ w, double* __restrict__ x,
-                            double* __restrict__ r) {
+// x += alpha p, r -= alpha (w - A Z e): w = A p from the stencil pass, A Z e applied on the
+// tile's cut faces from LDS (the deflation step of w = P1 A p, fused into the update)
+__global__ void __launch_bounds__(kBlock)
+    k_pc_update(Geo g, const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
+                const int32_t* az_oth, const double* az_t, const double* __restrict__ e,
+                const PcScalars* s, const double* __restrict__ p, const double* __restrict__ w,
+                double* __restrict__ x, double* __restrict__ r) {
+  __shared__ double corr[kTileMax];
   const double a = s->alpha;
   if (a == 0.0) return;
-  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
-       c += int64_t(gridDim.x) * blockDim.x) {
+  const int t = tile_of_block(blockIdx.x, g.ntiles);
+  const Tile T = load_tile(g.tiles, t);
+  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
+                  static_cast<const double*>(nullptr), corr, corr);
+  const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+    int ix, iy, iz;
+    cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+    const int c = ix + g.nx * (iy + g.ny * iz);
+    const double wf = w[c] - corr[j];
     x[c] += a * p[c];
-    r[c] -= a * w[c];
+    r[c] -= a * wf;
   }
 }
 
@@ -2445,7 +2449,7 @@ int ensure_poly(psl_ctx* c) {
   if (c->pc_v) return PSL_OK;
   double *v = nullptr, *part = nullptr;
   void* sc = nullptr;
-  const int64_t np = 2 * std::max<int64_t>(c->ntiles, kPcBlocks);
+  const int64_t np = 2 * int64_t(c->ntiles);
   if (psl_ctx_alloc(c, reinterpret_cast<void**>(&v), sizeof(double) * size_t(c->n) * 5) ||
       psl_ctx_alloc(c, reinterpret_cast<void**>(&part), sizeof(double) * size_t(np)) ||
       psl_ctx_alloc(c, &sc, sizeof(PcScalars)))
@@ -2515,20 +2519,19 @@ void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double
                      static_cast<const double*>(B.part), c->ntiles, &B.s->ry_new);
 }
 
-// one CG iteration: w = P1 A p, alpha, x and r, y = M^-1 r, beta, p
+// one CG iteration: A p (with Z^T A p and (p, A p)), e = E^-1 Z^T A p (with s^T e), alpha,
+// x and r with w = P1 A p formed on the fly, y = M^-1 r, beta, p
 void pc_iteration(psl_ctx* c, const PcBufs& B, const PcPlan& pl, double* x, hipStream_t st) {
   const int64_t n = c->n;
   launch_stencil<double, 0>(c, B.p, nullptr, B.w, st);
   launch_coarse<0, 0>(c, 0, st);
-  launch_outer_deflate(c, nullptr, B.w, B.w, st);
-  const int G = int(std::min<int64_t>(kPcBlocks, (n + kBlock - 1) / kBlock));
-  hipLaunchKernelGGL(k_pc_dots, dim3(G), dim3(kBlock), 0, st, n,
-                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
-                     static_cast<const double*>(B.w), B.part);
-  hipLaunchKernelGGL(k_gm_reduce, dim3(2), dim3(kBlock), 0, st,
-                     static_cast<const double*>(B.part), G, &B.s->pw);
-  hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(1), 0, st, B.s);
-  hipLaunchKernelGGL(k_pc_update, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+  hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(kBlock), 0, st, B.s,
+                     static_cast<const double*>(red(c, 0)), c->ntiles,
+                     static_cast<const double*>(c->cpart), c->coarse_blocks);
+  hipLaunchKernelGGL(k_pc_update, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
+                     static_cast<const int32_t*>(c->az_ptr), static_cast<const int32_t*>(c->az_cell),
+                     static_cast<const int32_t*>(c->az_lab), static_cast<const int32_t*>(c->az_oth),
+                     static_cast<const double*>(c->az_t), static_cast<const double*>(c->e),
                      static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
                      static_cast<const double*>(B.w), x, c->r64);
   pc_precondition(c, B, pl, c->r64, st);
