@@ -2195,8 +2195,29 @@ __global__ void k_pc_reset(PcScalars* s, double goal2, int maxit) {
   s->maxit = maxit;
 }
 
+// (r, y) and (r, r) from the preconditioner's per-tile partials (part[t], part[G + t]),
+// summed in a fixed order by one workgroup into s->ry_new, s->rr
+__device__ inline bool pc_sum_ry(PcScalars* s, const double* part, int G, double* lds) {
+  const bool done = s->done != 0;
+  double acc[2] = {0.0, 0.0};
+  if (!done)
+    for (int t = threadIdx.x; t < G; t += kBlock) {
+      acc[0] += part[t];
+      acc[1] += part[G + t];
+    }
+  psl::block_sum<2>(acc, lds);
+  if (threadIdx.x == 0 && !done) {
+    s->ry_new = acc[0];
+    s->rr = acc[1];
+  }
+  return done;
+}
+
 // after the first preconditioner pass: rho = (r, y); stop at once when r is small enough
-__global__ void k_pc_init(PcScalars* s) {
+__global__ void __launch_bounds__(kBlock) k_pc_init(PcScalars* s, const double* part, int G) {
+  __shared__ double lds[2 * kNW];
+  pc_sum_ry(s, part, G, lds);
+  if (threadIdx.x != 0) return;
   s->ry = s->ry_new;
   s->beta = 0.0;
   if (!isfinite(s->rr) || !isfinite(s->ry)) {
@@ -2246,9 +2267,12 @@ __global__ void __launch_bounds__(kBlock) k_pc_alpha(PcScalars* s, const double*
 }
 
 // beta = rho_new / rho; stop when ||r||^2 <= goal2
-__global__ void k_pc_beta(PcScalars* s) {
+__global__ void __launch_bounds__(kBlock) k_pc_beta(PcScalars* s, const double* part, int G) {
+  __shared__ double lds[2 * kNW];
+  const bool done = pc_sum_ry(s, part, G, lds);
+  if (threadIdx.x != 0) return;
   s->beta = 0.0;
-  if (s->done) return;
+  if (done) return;
   const double rr = s->rr, ryn = s->ry_new;
   if (!isfinite(rr) || !isfinite(ryn)) {
     s->done = 1;
@@ -2488,7 +2512,7 @@ struct PcJacobiF {
   }
 };
 
-// y = M^-1 r (into B.y) with (r, y), (r, r) reduced into s->ry_new, s->rr
+// y = M^-1 r (into B.y) with the per-tile partials of (r, y), (r, r) in B.part
 void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double* r,
                      hipStream_t st) {
   const int steps = pl.degree - 1;
@@ -2515,8 +2539,6 @@ void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double
       yin = yout;
     }
   }
-  hipLaunchKernelGGL(k_gm_reduce, dim3(2), dim3(kBlock), 0, st,
-                     static_cast<const double*>(B.part), c->ntiles, &B.s->ry_new);
 }
 
 // one CG iteration: A p (with Z^T A p and (p, A p)), e = E^-1 Z^T A p (with s^T e), alpha,
@@ -2535,7 +2557,8 @@ void pc_iteration(psl_ctx* c, const PcBufs& B, const PcPlan& pl, double* x, hipS
                      static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
                      static_cast<const double*>(B.w), x, c->r64);
   pc_precondition(c, B, pl, c->r64, st);
-  hipLaunchKernelGGL(k_pc_beta, dim3(1), dim3(1), 0, st, B.s);
+  hipLaunchKernelGGL(k_pc_beta, dim3(1), dim3(kBlock), 0, st, B.s,
+                     static_cast<const double*>(B.part), c->ntiles);
   hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
                      static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
 }
@@ -2618,7 +2641,8 @@ extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_
   // rhat = P1 (b - A x) (x takes the coarse part, which the final projection recomputes)
   enqueue_outer_step(c, b, x, st);
   pc_precondition(c, B, pl, c->r64, st);
-  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(1), 0, st, B.s);
+  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(kBlock), 0, st, B.s,
+                     static_cast<const double*>(B.part), c->ntiles);
   hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
                      static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
   if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
