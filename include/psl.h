@@ -164,8 +164,9 @@ void psl_default_poly_opts(psl_poly_opts* o);
  * iteration; degree 1 gives the iterates of Jacobi-preconditioned DEF1.
  *   ctx, b, x, st, stream  as for psl_solve; st->iters = CG iterations, st->outer = 1.
  *   Work space: 5 n doubles kept on the context.
- * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_EBREAKDOWN,
- * PSL_ENONFINITE, PSL_EINVAL (options out of range), PSL_ENOMEM.
+ * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_ESTAGNATION (||P1 r||
+ * not halved within 512 iterations, the rounding floor above tol; x = the projected last
+ * iterate), PSL_EBREAKDOWN, PSL_ENONFINITE, PSL_EINVAL (options out of range), PSL_ENOMEM.
  */
 int psl_solve_poly(psl_ctx* ctx, const double* b, double* x, const psl_poly_opts* o,
                    psl_solve_stats* st, void* stream);

@@ -2652,10 +2652,21 @@ extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_
   int run = o.check_every;
   double rr_prev = h->rr;
   int it_prev = 0;
+  // stagnation: ||r|| not halved within kStallWindow iterations (the rounding floor)
+  double rr_mark = h->rr;
+  int it_mark = 0;
+  int stalled = 0;
   while (!h->done) {
     for (int i = 0; i < run; ++i) pc_iteration(c, B, pl, x, st);
     if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
     if (h->done) break;
+    if (h->rr <= 0.25 * rr_mark) {
+      rr_mark = h->rr;
+      it_mark = h->iters;
+    } else if (h->iters - it_mark > kStallWindow) {
+      stalled = 1;
+      break;
+    }
     const int its = h->iters - it_prev;
     if (its > 0 && h->rr > 0.0 && h->rr < rr_prev) {
       const double per_it = std::log(h->rr / rr_prev) / its;   // < 0
@@ -2669,7 +2680,7 @@ extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_
   }
   stats.iters = h->iters;
   stats.outer = 1;
-  const int status = h->status;
+  const int status = stalled ? PSL_ESTAGNATION : h->status;
   // projection back: x = P2 x + x* = x + Z E^-1 Z^T (b - A x)
   enqueue_outer_step(c, b, x, st);
   launch_stencil<double, 1>(c, x, b, c->t64, st);

@@ -302,6 +302,28 @@ def test_poly_cap_zero_rhs_start_and_invalid(gpu_lib):
         assert stb["status_str"] == psl.psl_status_str(psl.EINVAL), kw
 
 
+def test_poly_below_the_rounding_floor(gpu_lib):
+    """A tolerance under the float64 rounding floor: once the deflated residual has reached
+    the floor (about 1e-14 relative here) the CG recursion loses it again and ends with a
+    breakdown, in the oracle as on the GPU, at about the same step. The GPU call returns
+    (PSL_EBREAKDOWN, or PSL_ESTAGNATION when the residual only stalls) instead of running
+    to the iteration cap."""
+    psl = gpu_lib
+    p = pi.config("c2", scale=4)
+    say("poly below the floor c2/4 tol 1e-18")
+    s = _setup(psl, p)
+    x, st = psl.psl_solve_poly(s.ctx, dev(p.q), tol=1e-18)
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    lab, d = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+    ref = O.dpcg_poly(A, b, O.deflation_matrix(lab, d), degree=3, ratio=30.0, tol=1e-18,
+                      maxit=2000)
+    say(f"  status={st['status_str']} iters={st['iters']} (oracle {ref.status} {ref.iters})")
+    assert st["status"] in (psl.ESTAGNATION, psl.EBREAKDOWN) and st["iters"] < 2000
+    if ref.status == "breakdown":
+        assert st["status"] == psl.EBREAKDOWN and abs(st["iters"] - ref.iters) <= 5
+    assert np.isfinite(host(x)).all()
+
+
 def test_poly_full_size(gpu_lib):
     """128x128x64 layered (the benchmark workload) with the default degree 3 on [2/30, 2]:
     the oracle's residual of the GPU x, and the oracle's iteration count."""
