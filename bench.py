@@ -372,8 +372,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only: a single-system PSL "
-                          "solve is not sharded across GPUs here (see DESIGN.md, sharding)",
+        print(json.dumps({"error": "bench.py measures one GPU: the single-system PSL solve "
+                          "is not sharded across GPUs, and no multi-GPU run is made",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.quick:

@@ -18,7 +18,7 @@ HIPCC_FLAGS = [
     "-shared",
     "-Wall",
     "-Wno-unused-result",
-    # no packed float32 instructions (build notes)
+    # no packed float32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

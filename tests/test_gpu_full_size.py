@@ -100,3 +100,88 @@ def test_channelized_full_size(gpu_lib, mode, solver, components):
         f"(device {st['relres_true']:.2e})")
     assert st["status"] == 0 and rel <= 1e-8
     assert abs(rel - st["relres_true"]) <= 1e-3 * rel + 1e-15
+
+
+def test_batched_full_size(gpu_lib):
+    """The benchmark's batch of 64 uneven systems (sides 32..96) with its tuned tile sizes:
+    every system's x meets 1e-8 in the oracle's own matrix, and four sampled systems (the
+    smallest, the largest, two between) agree with their single-system float64 solves to
+    the 1e-6 bar within two iterations. At this size a batch of several systems is not
+    bit-reproducible from run to run (last bits, an iteration more or less for some
+    systems), while one system batched alone equals its single solve bit for bit; the
+    cause is not found."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import autotune, pipeline
+    probs = pi.batch(nsys=64, seed=0)
+    say(f"full size batch: 64 systems, {sum(p.n for p in probs)} cells")
+    tiles = autotune.tiles_for([p.grid for p in probs], autotune.load_table())
+    setups = [pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr),
+                             tile_cells=t) for p, t in zip(probs, tiles)]
+    bs = [dev(p.q) for p in probs]
+    xs, stats, rc = psl.psl_solve_batched([s.ctx for s in setups], bs)
+    assert rc == 0
+    worst = 0.0
+    for p, x, st in zip(probs, xs, stats):
+        A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+        r = O.relres(A, b, host(x))
+        worst = max(worst, r)
+        assert st["status"] == 0 and r <= 1e-8, (p.grid, st["status_str"], r)
+    say(f"  worst relres {worst:.2e}, iterations {min(s['iters'] for s in stats)}.."
+        f"{max(s['iters'] for s in stats)}")
+    order = sorted(range(len(probs)), key=lambda i: probs[i].n)
+    for i in (order[0], order[21], order[42], order[-1]):
+        x1, st1 = psl.psl_solve(setups[i].ctx, bs[i], mode=psl.FP64)
+        d = float(torch.linalg.norm(x1 - xs[i]) / torch.linalg.norm(x1))
+        say(f"  system {i} grid={probs[i].grid}: iters {st1['iters']} single, "
+            f"{stats[i]['iters']} batched; relative difference {d:.2e}")
+        assert abs(st1["iters"] - stats[i]["iters"]) <= 2 and d <= 1e-6, probs[i].grid
+
+
+def test_conv3_full_resolution_sampled(gpu_lib):
+    """The network's widest convolution (48 -> 16 channels, ReLU) on the full 128x128x64
+    grid in one launch, checked at 256 sampled cells (corners, faces, interior) against the
+    oracle's convolution of each cell's 3x3x3 neighbourhood (zero outside the grid)."""
+    from oracle import x0net_oracle as N
+    from paper_1510_02148_amd import nn
+    grid = (128, 128, 64)
+    nx, ny, nz = grid
+    cin, cout = 48, 16
+    say(f"conv3 full resolution {cin}->{cout} grid={grid}")
+    g = np.random.Generator(np.random.PCG64(77))
+    x = N.bf16_round(g.normal(size=(nz, ny, nx, cin)).astype(np.float32).astype(np.float64))
+    w3 = N.bf16_round(g.normal(size=(cout, 27, cin)) / np.sqrt(27 * cin))
+    b = g.normal(size=cout).astype(np.float32).astype(np.float64)
+    # operands: bf16 bit patterns, weights packed by the Adam kernel's repack at t = 0
+    xr = x.astype(np.float32).reshape(-1, cin)
+    xbits = torch.from_numpy(np.ascontiguousarray(
+        (xr.view(np.uint32) >> 16).astype(np.uint16).view(np.int16))).cuda()
+    p = torch.tensor(w3.reshape(cout, -1), dtype=torch.float32, device="cuda")
+    zero = torch.zeros_like(p)
+    pb = torch.zeros(cout, dtype=torch.float32, device="cuda")
+    w = nn.bf16_empty(cout, nn.kp(cin), zero=True)
+    wt = nn.bf16_empty(cin, nn.kp(cout), zero=True)
+    nn.adam_conv(cout, cin, p, zero.clone(), zero.clone(), pb, pb.clone(), pb.clone(), None, 0,
+                 0.0, w, wt)
+    n = nx * ny * nz
+    y = nn.bf16_empty(n, cout)
+    yf = torch.empty(n, cout, dtype=torch.float32, device="cuda")
+    nn.conv3(grid, xbits, cin, w, cout, torch.tensor(b, dtype=torch.float32, device="cuda"),
+             True, y, yf)
+    got = yf.cpu().numpy().astype(np.float64).reshape(nz, ny, nx, cout)
+    cells = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, 0), (nz - 1, 0, nx - 1)]
+    cells += [tuple(int(v) for v in c) for c in
+              zip(g.integers(0, nz, 252), g.integers(0, ny, 252), g.integers(0, nx, 252))]
+    worst = 0.0
+    for (z, yy, xx) in cells:
+        patch = np.zeros((3, 3, 3, cin))
+        for dz in range(3):
+            for dy in range(3):
+                for dx in range(3):
+                    zz, y2, x2 = z + dz - 1, yy + dy - 1, xx + dx - 1
+                    if 0 <= zz < nz and 0 <= y2 < ny and 0 <= x2 < nx:
+                        patch[dz, dy, dx] = x[zz, y2, x2]
+        ref = N.relu(N.conv3d(patch, w3, b))[1, 1, 1]
+        scale = max(np.abs(ref).max(), 1.0)
+        worst = max(worst, np.abs(got[z, yy, xx] - ref).max() / scale)
+    say(f"  max error over {len(cells)} cells {worst:.2e} (relative to max(|ref|, 1))")
+    assert worst <= 2e-6
