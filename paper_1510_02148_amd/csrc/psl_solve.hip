@@ -424,18 +424,20 @@ __global__ void __launch_bounds__(kBlock)
 
 // Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other)
 // (v_other = 0 across an outer face; 0 on cells without a cut face). Two coarse vectors
-// at once: corr1 from e1, corr2 from e2 (skipped when e2 is null).
+// at once: corr1 from e1, corr2 from e2 (skipped when e2 is null). A wave with skip set
+// does no work but takes both barriers (it only publishes a stop decision).
 template <typename CT, typename ST>
 __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_ptr,
                                        const int32_t* az_cell, const int32_t* az_lab,
                                        const int32_t* az_oth, const CT* az_t, const double* e1,
-                                       const double* e2, ST* corr1, ST* corr2) {
-  for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
+                                       const double* e2, ST* corr1, ST* corr2,
+                                       bool skip = false) {
+  for (int j = threadIdx.x; j < T.ncell && !skip; j += kBlock) {
     corr1[j] = ST(0);
     if (e2) corr2[j] = ST(0);
   }
   __syncthreads();
-  const int a = az_ptr[t], b = az_ptr[t + 1];
+  const int a = az_ptr[t], b = skip ? a : az_ptr[t + 1];
   for (int k = a + threadIdx.x; k < b; k += kBlock) {
     const int32_t cw = az_cell[k];
     if (cw >= 0) continue;  // not the first face of its cell
@@ -506,11 +508,15 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
       dv[k] = ld(invd, c);
     }
   }
-  if (stop) return;
+  // The flag is raised inside this launch only by the lead workgroup's stop decision,
+  // which every workgroup reaches from the same partials, but the waves of a workgroup
+  // read it at different times: a wave that sees it leaves, except wave 0, which stays to
+  // publish the decision the others read (otherwise they would read a stale coef[]).
+  if (stop && threadIdx.x >= psl::kWave) return;
   if (threadIdx.x < psl::kWave) {
     // one wave reduces the coarse partials (fixed order) and decides the step
-    double alpha_d = 1e-3, beta_d = 0.5, go = 1.0;
-    if (!bench) {
+    double alpha_d = 1e-3, beta_d = 0.5, go = stop ? 0.0 : 1.0;
+    if (!bench && !stop) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       for (int i = threadIdx.x; i < G; i += psl::kWave) {
         s0 += cpart[i];           // s^T e
@@ -571,7 +577,7 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
     }
   }
   tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, RP ? er : nullptr, corr,
-                  corr2);   // ends with a barrier, after which coef[] is visible
+                  corr2, stop);   // ends with a barrier, after which coef[] is visible
   if (coef[2] == 0.0) return;
   const R alpha = R(coef[0]), beta = R(coef[1]);
 #pragma unroll
@@ -790,11 +796,13 @@ __global__ void __launch_bounds__(kBlock)
         dv[k] = ld(invd, c);
       }
     }
-    if (stop) return;
+    // a wave that sees the stop flag leaves, except wave 0, which publishes the decision
+    // (the flag is raised inside this launch only together with a stop decision)
+    if (stop && threadIdx.x >= psl::kWave) return;
     if (first && threadIdx.x < psl::kWave) {
       // one wave reduces the coarse partials (fixed order) and takes the step decision
-      double alpha_d = 1e-3, go = 1.0;
-      if (!bench) {
+      double alpha_d = 1e-3, go = stop ? 0.0 : 1.0;
+      if (!bench && !stop) {
         double s0 = 0.0, s1 = 0.0;
         for (int i = threadIdx.x; i < G; i += psl::kWave) {
           s0 += cpart[i];       // s^T e
@@ -823,7 +831,7 @@ __global__ void __launch_bounds__(kBlock)
       }
     }
     tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
-                    static_cast<const double*>(nullptr), corr, corr);  // ends with a barrier
+                    static_cast<const double*>(nullptr), corr, corr, stop);  // ends with a barrier
     if (coef[1] == 0.0) return;
     const R alpha = R(coef[0]);
 #pragma unroll
