@@ -74,12 +74,15 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
 
 SOLVER_NAMES = {
     "dpcg": lambda a: "DEF1-PCG",
-    "gmres": lambda a: f"deflated GMRES({a.restart})",
+    "gmres": lambda a: (f"deflated GMRES({a.restart})" +
+                        (f" with Chebyshev preconditioner (degree {a.gmres_degree})"
+                         if a.gmres_degree >= 2 else "")),
     "poly": lambda a: f"DEF1-PCG with Chebyshev preconditioner (degree {a.degree}, ratio {a.ratio:g})",
 }
 SOLVER_TAGS = {
     "dpcg": lambda a: "dpcg",
-    "gmres": lambda a: f"pdgmres({a.restart})",
+    "gmres": lambda a: (f"pdgmres({a.restart})" +
+                        (f"-cheb(degree {a.gmres_degree}, ratio 30)" if a.gmres_degree >= 2 else "")),
     "poly": lambda a: f"dpcg-cheb(degree {a.degree}, ratio {a.ratio:g})",
 }
 
@@ -363,6 +366,8 @@ def main():
                     help="deflated CG (default), the paper's deflated GMRES(m), or deflated "
                          "CG with the Chebyshev polynomial preconditioner; the last two float64")
     ap.add_argument("--restart", type=int, default=30, help="m of GMRES(m)")
+    ap.add_argument("--gmres-degree", type=int, default=0,
+                    help="GMRES preconditioner: 0 diag(A), 2..16 Chebyshev steps")
     ap.add_argument("--degree", type=int, default=3, help="Chebyshev steps (--solver poly)")
     ap.add_argument("--ratio", type=float, default=30.0,
                     help="Chebyshev interval [2 / ratio, 2] (--solver poly)")
@@ -417,7 +422,8 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if args.solver == "gmres":
-            x, st = psl.psl_solve_gmres(s.ctx, b, tol=prob.tol, restart=args.restart)
+            x, st = psl.psl_solve_gmres(s.ctx, b, tol=prob.tol, restart=args.restart,
+                                        degree=args.gmres_degree)
         elif args.solver == "poly":
             x, st = psl.psl_solve_poly(s.ctx, b, tol=prob.tol, degree=args.degree,
                                        ratio=args.ratio)
@@ -534,7 +540,7 @@ def main():
             lab, dd = label_fn(prob.grid, prob.K, prob.nsub, prob.thr)
             Z = O.deflation_matrix(lab, dd)
             if args.solver == "gmres":
-                res = O.pdgmres(A, bh, Z, m=args.restart, tol=prob.tol)
+                res = O.pdgmres(A, bh, Z, m=args.restart, tol=prob.tol, degree=args.gmres_degree)
             elif args.solver == "poly":
                 res = O.dpcg_poly(A, bh, Z, degree=args.degree, ratio=args.ratio, tol=prob.tol)
             else:

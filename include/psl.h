@@ -112,7 +112,10 @@ typedef struct {
   int32_t maxit;        /* cap on Arnoldi steps over all cycles (default 10000) */
   int32_t restart;      /* m of GMRES(m): steps per cycle, 1..200 (default 30) */
   int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
-  int32_t reserved[3];  /* must be 0 */
+  int32_t degree;       /* preconditioner: 0 or 1 M = diag(A) (default 0); 2..16 the
+                           Chebyshev polynomial of psl_solve_poly with that many steps on
+                           [2/30, 2] (a stronger preconditioner on the deflated system) */
+  int32_t reserved[2];  /* must be 0 */
 } psl_gmres_opts;
 
 /* Fill `o` with the GMRES defaults. */
@@ -127,9 +130,11 @@ void psl_default_gmres_opts(psl_gmres_opts* o);
  * the repeated classical form needs two batched passes per step instead of j dependent
  * ones). The least-squares residual decides convergence inside a cycle; every cycle
  * starts from a freshly formed P1 (b - A x). The host reads one column of the Hessenberg
- * matrix per step.
+ * matrix per step. With degree >= 2, M^-1 is the Chebyshev polynomial preconditioner
+ * (as in psl_solve_poly), applied to every basis vector and to the cycle's update.
  *   ctx, b, x, st, stream  as for psl_solve; st->iters = Arnoldi steps, st->outer =
- *   completed cycles. Work space: (m + 1) n doubles for the basis, kept on the context.
+ *   completed cycles. Work space: (m + 1) n doubles for the basis, kept on the context
+ *   (and psl_solve_poly's 5 n with degree >= 2).
  * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_ENONFINITE,
  * PSL_EINVAL (options out of range), PSL_ENOMEM.
  */

@@ -442,7 +442,8 @@ def dpcg_poly(A, b, Z, degree: int = 3, ratio: float = 30.0, lmax: float = 2.0, 
 
 
 def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000,
-            coarse: Optional[Coarse] = None) -> Result:
+            coarse: Optional[Coarse] = None, degree: int = 1, ratio: float = 30.0,
+            lmax: float = 2.0) -> Result:
     """Right-preconditioned restarted GMRES(m) on the deflated system with a priori
     subdomain-levelset vectors (Algorithm 1 with Z, E, P1, P2 and x* formed before the
     iteration, Section 3.2), M = diag(A):
@@ -454,7 +455,10 @@ def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000
       at convergence x = P2 x_m + x* = x_m + Z E^-1 Z^T (b - A x_m).
 
     ``iters`` counts products with A inside the cycles; ``history`` holds the least-
-    squares residual after every step (starting with ||r0||).
+    squares residual after every step (starting with ||r0||). degree >= 2 replaces
+    M^-1 = diag(A)^-1 by the Chebyshev polynomial preconditioner ``chebyshev_apply`` on
+    [lmax / ratio, lmax] (a stronger preconditioner on the deflated system, as the paper
+    pairs the deflation with AMG).
     """
     n = A.shape[0]
     b = np.asarray(b, dtype=np.float64)
@@ -470,6 +474,11 @@ def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000
 
     def P1(v):
         return v - A @ coarse.correction(v)
+
+    def Minv(v):
+        if degree <= 1:
+            return v / dg
+        return chebyshev_apply(A, v, degree, lmax / ratio, lmax)
 
     xm = x0.copy()
     it = 0
@@ -491,7 +500,7 @@ def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000
         u = np.zeros(0)
         j_end = 0
         for j in range(m):
-            w = P1(A @ (V[:, j] / dg))
+            w = P1(A @ Minv(V[:, j]))
             for i in range(j + 1):
                 H[i, j] = w @ V[:, i]
                 w = w - H[i, j] * V[:, i]
@@ -506,7 +515,7 @@ def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000
             if H[j + 1, j] == 0.0 or res <= tol * bnorm or it >= maxit:
                 break
             V[:, j + 1] = w / H[j + 1, j]
-        xm = xm + (V[:, :j_end] @ u) / dg
+        xm = xm + Minv(V[:, :j_end] @ u)
         if hist[-1] <= tol * bnorm:
             break
     x = xm + coarse.correction(b - A @ xm)

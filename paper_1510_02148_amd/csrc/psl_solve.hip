@@ -1821,6 +1821,11 @@ namespace {
 constexpr int kGmReg = 32;           // basis vectors one pass covers with register accumulators
 constexpr int kGmBlocks = 1024;      // workgroups of a pass (one partial each per quantity)
 constexpr int kGmMaxRestart = 200;
+constexpr int kGmMaxDegree = 16;      // Chebyshev steps of the optional polynomial preconditioner
+
+// y = q(D^-1 A) D^-1 r with `degree` Chebyshev steps on [2/30, 2] (the polynomial
+// preconditioner of psl_solve_poly, defined with it below); *y is its output buffer.
+int pc_apply(psl_ctx* c, int degree, const double* r, const double** y, hipStream_t st);
 
 // One grid-stride pass over the cells, with per-thread accumulators reduced once per
 // workgroup at the end (V_i = V + i n):
@@ -2004,12 +2009,36 @@ void gm_orthogonalize(psl_ctx* c, int nv, double* w, double* h1, double* h2, dou
 
 // v <- v / |v| (nrm2 = |v|^2 on the device), then w = P1 A M^-1 v (z in t64): stencil
 // (with the Z^T partials), coarse solve, A Z e on the cut faces
-void gm_operator(psl_ctx* c, double* v, const double* nrm2, double* w, hipStream_t st) {
+int gm_operator(psl_ctx* c, int degree, double* v, const double* nrm2, double* w,
+                hipStream_t st) {
   hipLaunchKernelGGL(k_gm_scale, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, c->n,
                      c->invdiag, nrm2, v, c->t64);
-  launch_stencil<double, 0>(c, c->t64, nullptr, w, st);
+  const double* z = c->t64;
+  if (degree >= 2) {
+    const int rc = pc_apply(c, degree, v, &z, st);
+    if (rc != PSL_OK) return rc;
+  }
+  launch_stencil<double, 0>(c, z, nullptr, w, st);
   launch_coarse<0, 0>(c, 0, st);
   launch_outer_deflate(c, nullptr, w, w, st);
+  return PSL_OK;
+}
+
+// x += sum_i y[i] V_i (the polynomial preconditioner's update: M^-1 applied to the sum)
+__global__ void k_gm_combine(int64_t n, const double* __restrict__ V, int nv,
+                             const double* __restrict__ y, double* __restrict__ out) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += y[i] * V[int64_t(i) * n + c];
+    out[c] = s;
+  }
+}
+
+__global__ void k_gm_add(int64_t n, const double* __restrict__ y, double* __restrict__ x) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    x[c] += y[c];
 }
 
 // reps fused passes (update with the dots) against min(m, kGmReg) basis vectors, updating
@@ -2044,7 +2073,8 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
   psl_default_gmres_opts(&o);
   if (o_in) o = *o_in;
   if (!(o.tol > 0.0) || o.maxit < 0 || o.restart < 1 || o.restart > kGmMaxRestart ||
-      (o.use_x0 != 0 && o.use_x0 != 1) || o.reserved[0] || o.reserved[1] || o.reserved[2])
+      (o.use_x0 != 0 && o.use_x0 != 1) || o.degree < 0 || o.degree > kGmMaxDegree ||
+      o.reserved[0] || o.reserved[1])
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int m = o.restart;
@@ -2082,7 +2112,8 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
   auto enqueue_step = [&](int j) -> int {
     double* Vj = c->gm_v + int64_t(j) * n;
     double* w = c->gm_v + int64_t(j + 1) * n;
-    gm_operator(c, Vj, j == 0 ? &c->sc->rr : nrm2, w, st);
+    const int orc = gm_operator(c, o.degree, Vj, j == 0 ? &c->sc->rr : nrm2, w, st);
+    if (orc != PSL_OK) return orc;
     gm_orthogonalize(c, j + 1, w, h1, h2, nrm2, st);
     PSL_HIP(hipMemcpyAsync(c->gm_host + (j & 1) * ncol, c->gm_dev, sizeof(double) * ncol,
                            hipMemcpyDeviceToHost, st));
@@ -2155,8 +2186,17 @@ extern "C" int psl_solve_gmres(psl_ctx* c, const double* b, double* x, const psl
       y[i] = d != 0.0 ? s / d : 0.0;
     }
     PSL_HIP(hipMemcpyAsync(ydev, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gm_update, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v, jend,
-                       ydev, c->invdiag, x);
+    if (o.degree >= 2) {
+      hipLaunchKernelGGL(k_gm_combine, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                         static_cast<const double*>(c->gm_v), jend,
+                         static_cast<const double*>(ydev), c->t64);
+      const double* z = nullptr;
+      if ((rc = pc_apply(c, o.degree, c->t64, &z, st)) != PSL_OK) return finish(rc);
+      hipLaunchKernelGGL(k_gm_add, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, z, x);
+    } else {
+      hipLaunchKernelGGL(k_gm_update, dim3(elem_grid(n)), dim3(kBlock), 0, st, n, c->gm_v,
+                         jend, ydev, c->invdiag, x);
+    }
     ++cycles;
   }
   stats.iters = total;
@@ -2582,6 +2622,17 @@ int pc_bench_step(psl_ctx* c, int reps, hipStream_t st) {
                                                static_cast<const double*>(B.y2), B.y,
                                                pl.inv_theta, pl.c1[2], pl.c2[2], st);
   PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
+int pc_apply(psl_ctx* c, int degree, const double* r, const double** y, hipStream_t st) {
+  const int rc = ensure_poly(c);
+  if (rc != PSL_OK) return rc;
+  const PcBufs B = pc_bufs(c);
+  // the stop flag gates the Chebyshev kernels; clear it (the dot partials go unused)
+  hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, 0.0, 0);
+  pc_precondition(c, B, pc_plan(degree, 2.0 / 30.0, 2.0), r, st);
+  *y = B.y;
   return PSL_OK;
 }
 

@@ -66,7 +66,8 @@ class psl_solve_stats(ctypes.Structure):
 
 class psl_gmres_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("use_x0", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("use_x0", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class psl_poly_opts(ctypes.Structure):
@@ -304,8 +305,10 @@ def psl_solve(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *
 
 def psl_solve_gmres(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = None, *,
                     tol: Optional[float] = None, maxit: Optional[int] = None,
-                    restart: Optional[int] = None, use_x0: bool = False, check: bool = False):
-    """The paper's deflated right-preconditioned GMRES(m); returns (x, stats dict)."""
+                    restart: Optional[int] = None, use_x0: bool = False, degree: int = 0,
+                    check: bool = False):
+    """The paper's deflated right-preconditioned GMRES(m) (degree >= 2: with the Chebyshev
+    polynomial preconditioner); returns (x, stats dict)."""
     o = psl_gmres_opts()
     _default_gmres_opts(ctypes.byref(o))
     if tol is not None:
@@ -314,6 +317,7 @@ def psl_solve_gmres(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = N
         o.maxit = maxit
     if restart is not None:
         o.restart = restart
+    o.degree = int(degree)
     o.use_x0 = 1 if use_x0 else 0
     if x is None:
         if use_x0:

@@ -86,7 +86,7 @@ def test_default_gmres_opts(lib):
     o = psl.psl_gmres_opts()
     psl._default_gmres_opts(ctypes.byref(o))
     assert o.tol == 1e-8 and o.maxit == 10000 and o.restart == 30 and o.use_x0 == 0
-    assert list(o.reserved) == [0, 0, 0]
+    assert o.degree == 0 and list(o.reserved) == [0, 0]
 
 
 def test_default_poly_opts(lib):

@@ -176,26 +176,32 @@ def test_components_solve(gpu_lib):
 
 # deflated GMRES (psl_solve_gmres)
 
-@pytest.mark.parametrize("name,scale,m,comp", [("c1", 1, 30, False), ("c2", 4, 30, False),
-                                               ("chan", 0, 100, False), ("chan", 0, 30, True)],
-                         ids=["c1-m30", "c2/4-m30", "chan-m100", "chan-components-m30"])
-def test_gmres_parity(gpu_lib, name, scale, m, comp):
+GMRES_CASES = [("c1", 1, 30, False, 0), ("c2", 4, 30, False, 0), ("chan", 0, 100, False, 0),
+               ("chan", 0, 30, True, 0), ("c2", 4, 30, False, 3), ("chan", 0, 30, True, 3),
+               ("chan", 0, 30, False, 3), ("c1", 1, 10, False, 2)]
+
+
+@pytest.mark.parametrize("name,scale,m,comp,degree", GMRES_CASES,
+                         ids=[f"{c[0]}/{c[1]}-m{c[2]}{'-components' if c[3] else ''}"
+                              f"{'-cheb%d' % c[4] if c[4] else ''}" for c in GMRES_CASES])
+def test_gmres_parity(gpu_lib, name, scale, m, comp, degree):
     """The paper's deflated GMRES(m) on the GPU against the oracle's: same solution, a
     1e-8 true residual, and about the oracle's step count (classical Gram-Schmidt twice on
     the GPU, modified Gram-Schmidt in the oracle). On the contrast-1e6 channel field
     GMRES(30) stagnates with one vector per region (as the paper's GMRES(20) does on its
-    sandwich case), so that case runs GMRES(100), and GMRES(30) with component vectors."""
+    sandwich case), so that case runs GMRES(100), and GMRES(30) with component vectors.
+    degree >= 2: the Chebyshev polynomial preconditioner in place of diag(A)."""
     psl = gpu_lib
     from paper_1510_02148_amd import pipeline
     p = _op_problem(name, scale)
-    say(f"gmres {name}/{scale} grid={p.grid} m={m} components={comp}")
+    say(f"gmres {name}/{scale} grid={p.grid} m={m} components={comp} degree={degree}")
     s = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr), components=comp)
-    x, st = psl.psl_solve_gmres(s.ctx, dev(p.q), restart=m)
+    x, st = psl.psl_solve_gmres(s.ctx, dev(p.q), restart=m, degree=degree)
     A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
     labels = O.levelset_components if comp else O.levelset_labels
     lab, d = labels(p.grid, p.K, p.nsub, p.thr)
     Z = O.deflation_matrix(lab, d)
-    ref = O.pdgmres(A, b, Z, m=m, tol=1e-8)
+    ref = O.pdgmres(A, b, Z, m=m, tol=1e-8, degree=degree, ratio=30.0)
     xr = O.dpcg(A, b, Z, tol=1e-12).x
     say(f"  status={st['status_str']} iters={st['iters']} (oracle {ref.iters}) cycles={st['outer']}")
     assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
@@ -223,6 +229,9 @@ def test_gmres_restarts_cap_and_zero_rhs(gpu_lib):
     assert st0["status"] == 0 and torch.count_nonzero(x0) == 0
     for bad in (0, 201):
         _, stb = psl.psl_solve_gmres(s.ctx, b, restart=bad)
+        assert stb["status_str"] == psl.psl_status_str(psl.EINVAL)
+    for bad in (-1, 17):
+        _, stb = psl.psl_solve_gmres(s.ctx, b, degree=bad)
         assert stb["status_str"] == psl.psl_status_str(psl.EINVAL)
 
 

@@ -41,13 +41,15 @@ MUTANTS = {
     "components_ignore_class": ("key = (sub * ncls + c).reshape(nz, ny, nx)",
                                 "key = (sub * ncls + 0 * c).reshape(nz, ny, nx)"),
     "components_no_z_faces": ("for axis in (2, 1, 0):", "for axis in (2, 1):"),
-    "gmres_left_preconditioned": ("w = P1(A @ (V[:, j] / dg))", "w = P1(A @ V[:, j]) / dg"),
-    "gmres_update_without_Minv": ("xm = xm + (V[:, :j_end] @ u) / dg", "xm = xm + V[:, :j_end] @ u"),
+    "gmres_left_preconditioned": ("w = P1(A @ Minv(V[:, j]))", "w = Minv(P1(A @ V[:, j]))"),
+    "gmres_update_without_Minv": ("xm = xm + Minv(V[:, :j_end] @ u)", "xm = xm + V[:, :j_end] @ u"),
     "gmres_no_projection_back": ("x = xm + coarse.correction(b - A @ xm)", "x = xm.copy()"),
     "cheb_rho_sign": ("rho_next = 1.0 / (2.0 * sigma - rho)", "rho_next = 1.0 / (2.0 * sigma + rho)"),
     "cheb_step_without_jacobi": ("(2.0 * rho_next / delta) * (res / dg)", "(2.0 * rho_next / delta) * res"),
     "cheb_residual_of_d": ("res = r - A @ y", "res = r - A @ d"),
     "poly_beta_inverted": ("p = y + (rho_new / rho) * p", "p = y + (rho / rho_new) * p"),
+    "gmres_poly_degree_ignored": ("        if degree <= 1:\n            return v / dg\n",
+                                  "        if True:\n            return v / dg\n"),
     "components_reverse_order": ("order[np.argsort(first, kind=\"stable\")] = np.arange(ncomp)",
                                  "order[np.argsort(-first, kind=\"stable\")] = np.arange(ncomp)"),
 }
