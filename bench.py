@@ -467,6 +467,19 @@ def main():
                 "solve_s": float(np.median([r[2] for r in rec64])), "iters": st64["iters"],
                 "relres_true": st64["relres_true"], "status": st64["status_str"]}
         del s64, x64
+    # the same workload with the Chebyshev polynomial preconditioner (float64), for context
+    cheb = None
+    if not args.no_fp64 and args.solver == "dpcg":
+        args.solver = "poly"
+        sp, xp, recp, wallp = run_leg(psl.FP64, args.steps, min(args.warmup, 1),
+                                      "chebyshev fp64")
+        args.solver = "dpcg"
+        stp = recp[-1][0]
+        cheb = {"s_per_step": wallp, "setup_s": float(np.median([r[1] for r in recp])),
+                "solve_s": float(np.median([r[2] for r in recp])), "iters": stp["iters"],
+                "relres_true": stp["relres_true"], "status": stp["status_str"],
+                "degree": args.degree, "ratio": args.ratio}
+        del sp, xp
 
     # ---- per-kernel durations with events on the stream the kernels run on ----------
     w = 4 if mode == psl.MIXED else 8
@@ -572,6 +585,7 @@ def main():
         "spmv_gbs": spmv_gbs, "ctx_info": info, "kernels": kernels, "roofline": roofline,
         "fp64_plain": fp64,
         "speedup_vs_fp64": (round(fp64["s_per_step"] / wall, 3) if fp64 else None),
+        "chebyshev_fp64": cheb,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
