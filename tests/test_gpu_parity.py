@@ -608,6 +608,65 @@ def test_single_cell_and_single_label(gpu_lib):
     assert s.d == 1 and st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
 
 
+OTHER_SOLVERS = [("gmres", 0), ("gmres", 3), ("poly", 1), ("poly", 3)]
+
+
+def _other_solve(psl, ctx, b, solver, degree, **kw):
+    if solver == "gmres":
+        return psl.psl_solve_gmres(ctx, b, degree=degree, **kw)
+    return psl.psl_solve_poly(ctx, b, degree=degree, **kw)
+
+
+@pytest.mark.parametrize("solver,degree", OTHER_SOLVERS,
+                         ids=[f"{s}-deg{d}" for s, d in OTHER_SOLVERS])
+def test_other_solvers_edge_cases(gpu_lib, solver, degree):
+    """Deflated GMRES and the polynomial-preconditioned CG on the degenerate cases: d = n
+    (E = A: the projection alone is exact, no step), one cell, one region for a whole 3D
+    problem (d = 1), and a ragged grid (37x29x11, uneven subdomains) against the oracle's
+    solver with the same options."""
+    psl = gpu_lib
+    say(f"edge cases {solver} degree {degree}")
+    grid, n = (6, 5, 4), 120
+    K = lognormal(n, 31)
+    Tx, Ty, Tz = psl.psl_assemble_tpfa(grid, dev(K), 1)
+    ctx = psl.psl_setup_E(grid, Tx, Ty, Tz, dev(np.arange(n, dtype=np.int32), torch.int32), n)
+    q = np.random.Generator(np.random.PCG64(2)).standard_normal(n)
+    x, st = _other_solve(psl, ctx, dev(q), solver, degree)
+    A, b = O.assemble(K, grid, 1, q)
+    xr = np.linalg.solve(A.toarray(), b)
+    assert st["status"] == 0 and st["iters"] == 0
+    assert np.linalg.norm(host(x) - xr) <= 1e-9 * np.linalg.norm(xr)
+    # one cell
+    g1 = (1, 1, 1)
+    Tx, Ty, Tz = psl.psl_assemble_tpfa(g1, dev([3.0]), 1)
+    lab, d = psl.psl_build_Z(g1, dev([3.0]), (1, 1, 1), [])
+    ctx1 = psl.psl_setup_E(g1, Tx, Ty, Tz, lab, d, nsub=(1, 1, 1))
+    x, st = _other_solve(psl, ctx1, dev([2.0]), solver, degree)
+    assert st["status"] == 0 and abs(host(x)[0] - 2.0 / 6.0) <= 1e-15
+    from paper_1510_02148_amd import pipeline
+    # one region for a whole 3D problem
+    p = pi.layered3d(20, 12, 10, contrast=1e3, nsub=(1, 1, 1), seed=4)
+    p.thr = np.array([])
+    s1 = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr))
+    x, st = _other_solve(psl, s1.ctx, dev(p.q), solver, degree)
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    assert s1.d == 1 and st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
+    # ragged grid against the oracle
+    p = _problem("ragged", 0, {})
+    s2 = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr))
+    x, st = _other_solve(psl, s2.ctx, dev(p.q), solver, degree)
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    lab, d = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+    Z = O.deflation_matrix(lab, d)
+    if solver == "gmres":
+        ref = O.pdgmres(A, b, Z, m=30, tol=1e-8, degree=degree, ratio=30.0)
+    else:
+        ref = O.dpcg_poly(A, b, Z, degree=degree, ratio=30.0, tol=1e-8)
+    say(f"  ragged: status={st['status_str']} iters={st['iters']} (oracle {ref.iters})")
+    assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8
+    assert abs(st["iters"] - ref.iters) <= max(3, 0.05 * ref.iters)
+
+
 def test_setup_errors(gpu_lib):
     psl = gpu_lib
     say("edge setup errors")
