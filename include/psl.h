@@ -152,7 +152,10 @@ typedef struct {
   int32_t use_x0;       /* 1: x holds the start vector on entry; 0: start from x = 0 */
   int32_t check_every;  /* iterations in the first run between host reads, 1..512
                            (default 16; later runs follow the convergence rate) */
-  int32_t reserved[2];  /* must be 0 */
+  int32_t mixed;        /* 1: float32 CG (float32 T, 1/diag, vectors; float64 partials)
+                           inside float64 iterative refinement, each inner solve to 1e-5
+                           relative (or what tol still needs); 0: float64 (default) */
+  int32_t reserved[1];  /* must be 0 */
 } psl_poly_opts;
 
 /* Fill `o` with the polynomial-preconditioner defaults. */
@@ -167,8 +170,9 @@ void psl_default_poly_opts(psl_poly_opts* o);
  * spectrum of D^-1 A). The CG is the DEF1 loop of psl_solve (P1 from E = Z^T A Z, eq.
  * "deflops"; projection back, eq. "projectback") in float64, two reductions per
  * iteration; degree 1 gives the iterates of Jacobi-preconditioned DEF1.
- *   ctx, b, x, st, stream  as for psl_solve; st->iters = CG iterations, st->outer = 1.
- *   Work space: 5 n doubles kept on the context.
+ *   ctx, b, x, st, stream  as for psl_solve; st->iters = CG iterations (all inner solves
+ *   with mixed = 1), st->outer = 1 (float64) or the refinement steps (mixed).
+ *   Work space: 5 n doubles kept on the context (and 7 n floats with mixed = 1).
  * Returns PSL_OK, PSL_EMAXIT (x = the projected last iterate), PSL_ESTAGNATION (||P1 r||
  * not halved within 512 iterations, the rounding floor above tol; x = the projected last
  * iterate), PSL_EBREAKDOWN, PSL_ENONFINITE, PSL_EINVAL (options out of range), PSL_ENOMEM.
@@ -361,7 +365,8 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
 #define PSL_KERNEL_POLY_STEP      6  /* psl_solve_poly: the last Chebyshev step of a degree >= 3
                                         preconditioner application (stencil on y with the
                                         d, y updates and the (r, y), (r, r) partials; needs a
-                                        prior psl_solve_poly, PSL_FP64) */
+                                        prior psl_solve_poly; PSL_MIXED times the float32
+                                        step after a mixed solve) */
 
 /*
  * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
@@ -375,9 +380,9 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
  * solved on this context so far; it overwrites basis vector min(m, 32).
  * PSL_KERNEL_POLY_STEP times the last Chebyshev step of psl_solve_poly's preconditioner
  * (degree >= 3) on its work vectors and overwrites them.
- * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1; GMRES pass or
- * Chebyshev step without a prior psl_solve_gmres / psl_solve_poly, or in PSL_MIXED),
- * PSL_ENOMEM.
+ * Errors: PSL_EINVAL (bad or reserved kernel id, mode or reps < 1; GMRES pass without a
+ * prior psl_solve_gmres or in PSL_MIXED; Chebyshev step without a prior psl_solve_poly in
+ * that precision), PSL_ENOMEM.
  */
 int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
 

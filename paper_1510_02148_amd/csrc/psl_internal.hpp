@@ -130,6 +130,7 @@ struct psl_ctx {
   double* gm_host = nullptr;          // pinned: two slots of one Arnoldi column each
   hipEvent_t gm_ev[2] = {nullptr, nullptr};  // marks each slot's copy
   double* pc_v = nullptr;             // polynomial-preconditioned CG: p, w, y, y2, d [5 n]
+  float* pc_v32 = nullptr;            // its float32 inner solve: p, w, y, y2, d, r, xi [7 n]
   double* pc_part = nullptr;          // workgroup / tile partials of its two dot pairs
   void* pc_sc = nullptr;              // its device scalars
   void* pc_h = nullptr;               // pinned host mirror of them

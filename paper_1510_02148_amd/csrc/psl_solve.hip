@@ -1743,7 +1743,7 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
 
 namespace {
 int gm_bench_pass(psl_ctx* c, int reps, hipStream_t st);   // with the GMRES kernels below
-int pc_bench_step(psl_ctx* c, int reps, hipStream_t st);   // with the polynomial CG below
+int pc_bench_step(psl_ctx* c, int mode, int reps, hipStream_t st);   // polynomial CG below
 }
 
 extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t reps,
@@ -1758,8 +1758,8 @@ extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_
     return gm_bench_pass(c, reps, st);
   }
   if (kernel == PSL_KERNEL_POLY_STEP) {
-    if (mode != PSL_FP64 || !c->pc_v) return PSL_EINVAL;
-    return pc_bench_step(c, reps, st);
+    if (!c->pc_v || (mode == PSL_MIXED && !c->pc_v32)) return PSL_EINVAL;
+    return pc_bench_step(c, mode, reps, st);
   }
   int rc = mode == PSL_MIXED ? ensure_sd<float>(c) : ensure_vecs<double>(c);
   if (rc != PSL_OK) return rc;
@@ -2225,6 +2225,8 @@ namespace {
 
 constexpr int kPcMaxDegree = 16;
 constexpr int kPcMaxRun = 512;      // iterations enqueued between two host reads, at most
+constexpr double kPcTauInner = 1e-5; // float32 inner solve: relative residual reduction
+constexpr int kPcMaxOuter = 30;      // float64 refinement steps, at most
 
 struct PcScalars {
   double pw, spare;    // (p, P1 A p) of the last step
@@ -2334,14 +2336,16 @@ __global__ void __launch_bounds__(kBlock) k_pc_beta(PcScalars* s, const double* 
 
 // x += alpha p, r -= alpha (w - A Z e): w = A p from the stencil pass, A Z e applied on the
 // tile's cut faces from LDS (the deflation step of w = P1 A p, fused into the update)
+template <typename R>
 __global__ void __launch_bounds__(kBlock)
     k_pc_update(Geo g, const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
-                const int32_t* az_oth, const double* az_t, const double* __restrict__ e,
-                const PcScalars* s, const double* __restrict__ p, const double* __restrict__ w,
-                double* __restrict__ x, double* __restrict__ r) {
-  __shared__ double corr[kTileMax];
-  const double a = s->alpha;
-  if (a == 0.0) return;
+                const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
+                const PcScalars* s, const R* __restrict__ p, const R* __restrict__ w,
+                R* __restrict__ x, R* __restrict__ r) {
+  __shared__ R corr[kTileMax];
+  const double ad = s->alpha;
+  if (ad == 0.0) return;
+  const R a = R(ad);
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
   tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
@@ -2351,32 +2355,35 @@ __global__ void __launch_bounds__(kBlock)
     int ix, iy, iz;
     cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
     const int c = ix + g.nx * (iy + g.ny * iz);
-    const double wf = w[c] - corr[j];
+    const R wf = w[c] - corr[j];
     x[c] += a * p[c];
     r[c] -= a * wf;
   }
 }
 
 // p = y + beta p (p = y when beta = 0: the first direction)
-__global__ void k_pc_dir(int64_t n, const PcScalars* s, const double* __restrict__ y,
-                         double* __restrict__ p) {
+template <typename R>
+__global__ void k_pc_dir(int64_t n, const PcScalars* s, const R* __restrict__ y,
+                         R* __restrict__ p) {
   if (s->done) return;
-  const double beta = s->beta;
+  const double bd = s->beta;
+  const R beta = R(bd);
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
        c += int64_t(gridDim.x) * blockDim.x)
-    p[c] = beta == 0.0 ? y[c] : y[c] + beta * p[c];
+    p[c] = bd == 0.0 ? y[c] : y[c] + beta * p[c];
 }
 
-// Degree 1: y = D^-1 r / theta. Partials (r, y), (r, r) per tile.
-template <int CPT>
+// Degree 1: y = D^-1 r / theta. Partials (r, y), (r, r) per tile (float64).
+template <typename R, int CPT>
 __global__ void __launch_bounds__(kBlock)
-    k_pc_jacobi(Geo g, const double* __restrict__ r, const double* __restrict__ invd,
-                double* __restrict__ y, double inv_theta, double* part, const PcScalars* s) {
+    k_pc_jacobi(Geo g, const R* __restrict__ r, const R* __restrict__ invd,
+                R* __restrict__ y, double inv_theta, double* part, const PcScalars* s) {
   __shared__ double lds[2 * kNW];
   if (s->done) return;
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+  const R it = R(inv_theta);
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
@@ -2385,11 +2392,11 @@ __global__ void __launch_bounds__(kBlock)
       int ix, iy, iz;
       cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
       const int c = ix + g.nx * (iy + g.ny * iz);
-      const double rc = r[c];
-      const double yc = rc * invd[c] * inv_theta;
+      const R rc = r[c];
+      const R yc = rc * invd[c] * it;
       y[c] = yc;
-      acc[0] += rc * yc;
-      acc[1] += rc * rc;
+      acc[0] += double(rc) * double(yc);
+      acc[1] += double(rc) * double(rc);
     }
   }
   psl::block_sum<2>(acc, lds);
@@ -2403,12 +2410,13 @@ __global__ void __launch_bounds__(kBlock)
 //   d_{s+1} = c1 d_s + c2 D^-1 (r - A y_s),  y_{s+1} = y_s + d_{s+1}.
 // FIRST: y_1 = d_1 = D^-1 r / theta, formed here for the cell and its neighbours.
 // LAST: store y_{s+1} only, with the partials (r, y), (r, r) per tile; else store d, y.
-template <int CPT, bool FIRST, bool LAST>
+// Arithmetic in R; the partials in float64.
+template <typename R, int CPT, bool FIRST, bool LAST>
 __global__ void __launch_bounds__(kBlock)
-    k_pc_cheb(Geo g, const double* __restrict__ Tx, const double* __restrict__ Ty,
-              const double* __restrict__ Tz, const double* __restrict__ r,
-              const double* __restrict__ invd, const double* __restrict__ yin, double* d,
-              double* __restrict__ yout, double inv_theta, double c1, double c2, double* part,
+    k_pc_cheb(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
+              const R* __restrict__ Tz, const R* __restrict__ r,
+              const R* __restrict__ invd, const R* __restrict__ yin, R* d,
+              R* __restrict__ yout, double inv_theta, double c1d, double c2d, double* part,
               const PcScalars* s) {
   __shared__ double lds[2 * kNW];
   if (s->done) return;
@@ -2417,13 +2425,12 @@ __global__ void __launch_bounds__(kBlock)
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int sxy = nx * ny;
+  const R it = R(inv_theta), c1 = R(c1d), c2 = R(c2d);
   // y_s at a cell: stored, or D^-1 r / theta for the first step
-  auto ys = [&](int c) -> double {
-    return FIRST ? r[c] * invd[c] * inv_theta : yin[c];
-  };
+  auto ys = [&](int c) -> R { return FIRST ? r[c] * invd[c] * it : yin[c]; };
   int cc[CPT];
-  double yc[CPT], yw[CPT], ye[CPT], ysn[CPT], yn[CPT], yb[CPT], yt[CPT];
-  double t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT], rc[CPT], ic[CPT], dc[CPT];
+  R yc[CPT], yw[CPT], ye[CPT], ysn[CPT], yn[CPT], yb[CPT], yt[CPT];
+  R t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT], rc[CPT], ic[CPT], dc[CPT];
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int j = threadIdx.x + k * kBlock;
@@ -2436,12 +2443,12 @@ __global__ void __launch_bounds__(kBlock)
       const int fy = c + nx * iz;
       cc[k] = c;
       yc[k] = ys(c);
-      yw[k] = ix > 0 ? ys(c - 1) : 0.0;
-      ye[k] = ix < nx - 1 ? ys(c + 1) : 0.0;
-      ysn[k] = iy > 0 ? ys(c - nx) : 0.0;
-      yn[k] = iy < ny - 1 ? ys(c + nx) : 0.0;
-      yb[k] = iz > 0 ? ys(c - sxy) : 0.0;
-      yt[k] = iz < nz - 1 ? ys(c + sxy) : 0.0;
+      yw[k] = ix > 0 ? ys(c - 1) : R(0);
+      ye[k] = ix < nx - 1 ? ys(c + 1) : R(0);
+      ysn[k] = iy > 0 ? ys(c - nx) : R(0);
+      yn[k] = iy < ny - 1 ? ys(c + nx) : R(0);
+      yb[k] = iz > 0 ? ys(c - sxy) : R(0);
+      yt[k] = iz < nz - 1 ? ys(c + sxy) : R(0);
       t0[k] = Tx[fx];
       t1[k] = Tx[fx + 1];
       t2[k] = Ty[fy];
@@ -2450,27 +2457,27 @@ __global__ void __launch_bounds__(kBlock)
       t5[k] = Tz[c + sxy];
       rc[k] = r[c];
       ic[k] = invd[c];
-      dc[k] = FIRST ? 0.0 : d[c];
+      dc[k] = FIRST ? R(0) : d[c];
     }
   }
   double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     if (cc[k] < 0) continue;
-    const double y0 = yc[k];
-    double ap = t0[k] * (y0 - yw[k]);
+    const R y0 = yc[k];
+    R ap = t0[k] * (y0 - yw[k]);
     ap += t1[k] * (y0 - ye[k]);
     ap += t2[k] * (y0 - ysn[k]);
     ap += t3[k] * (y0 - yn[k]);
     ap += t4[k] * (y0 - yb[k]);
     ap += t5[k] * (y0 - yt[k]);
-    const double dprev = FIRST ? y0 : dc[k];
-    const double dn = c1 * dprev + c2 * ic[k] * (rc[k] - ap);
-    const double ynew = y0 + dn;
+    const R dprev = FIRST ? y0 : dc[k];
+    const R dn = c1 * dprev + c2 * ic[k] * (rc[k] - ap);
+    const R ynew = y0 + dn;
     yout[cc[k]] = ynew;
     if (LAST) {
-      acc[0] += rc[k] * ynew;
-      acc[1] += rc[k] * rc[k];
+      acc[0] += double(rc[k]) * double(ynew);
+      acc[1] += double(rc[k]) * double(rc[k]);
     } else {
       d[cc[k]] = dn;
     }
@@ -2482,6 +2489,27 @@ __global__ void __launch_bounds__(kBlock)
       part[g.ntiles + t] = acc[1];
     }
   }
+}
+
+// float32 refinement: r = r64 / ||r64|| (||r64||^2 in *rr), xi = 0; and x += ||r64|| xi
+template <typename R>
+__global__ void k_pc_scale_in(int64_t n, const double* __restrict__ r64, const double* rr,
+                              R* __restrict__ r, R* __restrict__ xi) {
+  const double inv = 1.0 / sqrt(*rr);
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x) {
+    r[c] = R(r64[c] * inv);
+    xi[c] = R(0);
+  }
+}
+
+template <typename R>
+__global__ void k_pc_accum(int64_t n, const double* rr, const R* __restrict__ xi,
+                           double* __restrict__ x) {
+  const double scale = sqrt(*rr);
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
+       c += int64_t(gridDim.x) * blockDim.x)
+    x[c] += scale * double(xi[c]);
 }
 
 struct PcPlan {
@@ -2506,15 +2534,25 @@ PcPlan pc_plan(int degree, double lmin, double lmax) {
   return pl;
 }
 
-struct PcBufs {
-  double *p, *w, *y, *y2, *d, *part;
+template <typename R>
+struct PcBufsT {
+  R *p, *w, *y, *y2, *d, *r, *xi;   // r: CG residual; xi: CG iterate (float32 inner only)
+  double* part;
   PcScalars* s;
 };
+using PcBufs = PcBufsT<double>;
 
 PcBufs pc_bufs(psl_ctx* c) {
   const int64_t n = c->n;
   return PcBufs{c->pc_v, c->pc_v + n, c->pc_v + 2 * n, c->pc_v + 3 * n, c->pc_v + 4 * n,
-                c->pc_part, static_cast<PcScalars*>(c->pc_sc)};
+                c->r64, nullptr, c->pc_part, static_cast<PcScalars*>(c->pc_sc)};
+}
+
+PcBufsT<float> pc_bufs32(psl_ctx* c) {
+  const int64_t n = c->n;
+  float* v = c->pc_v32;
+  return PcBufsT<float>{v, v + n, v + 2 * n, v + 3 * n, v + 4 * n, v + 5 * n, v + 6 * n,
+                        c->pc_part, static_cast<PcScalars*>(c->pc_sc)};
 }
 
 int ensure_poly(psl_ctx* c) {
@@ -2535,55 +2573,68 @@ int ensure_poly(psl_ctx* c) {
   return PSL_OK;
 }
 
-template <bool FIRST, bool LAST>
+int ensure_poly32(psl_ctx* c) {
+  int rc = ensure_poly(c);
+  if (rc != PSL_OK || c->pc_v32) return rc;
+  float* v = nullptr;
+  if (psl_ctx_alloc(c, reinterpret_cast<void**>(&v), sizeof(float) * size_t(c->n) * 7))
+    return PSL_ENOMEM;
+  c->pc_v32 = v;
+  return PSL_OK;
+}
+
+template <typename R, bool FIRST, bool LAST>
 struct PcChebC {
   template <int CPT>
   struct F {
-    static void run(psl_ctx* c, const PcBufs& B, const double* r, const double* yin,
-                    double* yout, double inv_theta, double c1, double c2, hipStream_t st) {
-      hipLaunchKernelGGL((k_pc_cheb<CPT, FIRST, LAST>), dim3(c->ntiles), dim3(kBlock), 0, st,
-                         geo(c), static_cast<const double*>(c->Tx),
-                         static_cast<const double*>(c->Ty), static_cast<const double*>(c->Tz),
-                         r, static_cast<const double*>(c->invdiag), yin, B.d, yout, inv_theta,
-                         c1, c2, B.part, static_cast<const PcScalars*>(B.s));
+    static void run(psl_ctx* c, const PcBufsT<R>& B, const R* r, const R* yin, R* yout,
+                    double inv_theta, double c1, double c2, hipStream_t st) {
+      hipLaunchKernelGGL((k_pc_cheb<R, CPT, FIRST, LAST>), dim3(c->ntiles), dim3(kBlock), 0, st,
+                         geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
+                         r, Prec<R>::invd(c), yin, B.d, yout, inv_theta, c1, c2, B.part,
+                         static_cast<const PcScalars*>(B.s));
     }
   };
 };
 
-template <int CPT>
-struct PcJacobiF {
-  static void run(psl_ctx* c, const PcBufs& B, const double* r, double inv_theta,
-                  hipStream_t st) {
-    hipLaunchKernelGGL((k_pc_jacobi<CPT>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), r,
-                       static_cast<const double*>(c->invdiag), B.y, inv_theta, B.part,
-                       static_cast<const PcScalars*>(B.s));
-  }
+template <typename R>
+struct PcJacobiC {
+  template <int CPT>
+  struct F {
+    static void run(psl_ctx* c, const PcBufsT<R>& B, const R* r, double inv_theta,
+                    hipStream_t st) {
+      hipLaunchKernelGGL((k_pc_jacobi<R, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c), r,
+                         Prec<R>::invd(c), B.y, inv_theta, B.part,
+                         static_cast<const PcScalars*>(B.s));
+    }
+  };
 };
 
 // y = M^-1 r (into B.y) with the per-tile partials of (r, y), (r, r) in B.part
-void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double* r,
+template <typename R>
+void pc_precondition(psl_ctx* c, const PcBufsT<R>& B, const PcPlan& pl, const R* r,
                      hipStream_t st) {
   const int steps = pl.degree - 1;
   if (steps == 0) {
-    with_cpt<PcJacobiF>(c->cpt, c, B, r, pl.inv_theta, st);
+    with_cpt<PcJacobiC<R>::template F>(c->cpt, c, B, r, pl.inv_theta, st);
   } else {
     // step s writes B.y when (steps - s) is even, so the last step lands in B.y
-    const double* yin = nullptr;
+    const R* yin = nullptr;
     for (int s = 1; s <= steps; ++s) {
-      double* yout = ((steps - s) % 2 == 0) ? B.y : B.y2;
+      R* yout = ((steps - s) % 2 == 0) ? B.y : B.y2;
       const bool first = s == 1, last = s == steps;
       if (first && last)
-        with_cpt<PcChebC<true, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
-                                                  pl.c1[s], pl.c2[s], st);
+        with_cpt<PcChebC<R, true, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                     pl.c1[s], pl.c2[s], st);
       else if (first)
-        with_cpt<PcChebC<true, false>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
-                                                   pl.c1[s], pl.c2[s], st);
+        with_cpt<PcChebC<R, true, false>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                      pl.c1[s], pl.c2[s], st);
       else if (last)
-        with_cpt<PcChebC<false, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
-                                                   pl.c1[s], pl.c2[s], st);
+        with_cpt<PcChebC<R, false, true>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
+                                                      pl.c1[s], pl.c2[s], st);
       else
-        with_cpt<PcChebC<false, false>::template F>(c->cpt, c, B, r, yin, yout, pl.inv_theta,
-                                                    pl.c1[s], pl.c2[s], st);
+        with_cpt<PcChebC<R, false, false>::template F>(c->cpt, c, B, r, yin, yout,
+                                                       pl.inv_theta, pl.c1[s], pl.c2[s], st);
       yin = yout;
     }
   }
@@ -2591,36 +2642,49 @@ void pc_precondition(psl_ctx* c, const PcBufs& B, const PcPlan& pl, const double
 
 // one CG iteration: A p (with Z^T A p and (p, A p)), e = E^-1 Z^T A p (with s^T e), alpha,
 // x and r with w = P1 A p formed on the fly, y = M^-1 r, beta, p
-void pc_iteration(psl_ctx* c, const PcBufs& B, const PcPlan& pl, double* x, hipStream_t st) {
+template <typename R>
+void pc_iteration(psl_ctx* c, const PcBufsT<R>& B, const PcPlan& pl, R* x, hipStream_t st) {
   const int64_t n = c->n;
-  launch_stencil<double, 0>(c, B.p, nullptr, B.w, st);
+  launch_stencil<R, 0>(c, B.p, nullptr, B.w, st);
   launch_coarse<0, 0>(c, 0, st);
   hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(kBlock), 0, st, B.s,
                      static_cast<const double*>(red(c, 0)), c->ntiles,
                      static_cast<const double*>(c->cpart), c->coarse_blocks);
-  hipLaunchKernelGGL(k_pc_update, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
+  hipLaunchKernelGGL((k_pc_update<R>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
                      static_cast<const int32_t*>(c->az_ptr), static_cast<const int32_t*>(c->az_cell),
                      static_cast<const int32_t*>(c->az_lab), static_cast<const int32_t*>(c->az_oth),
-                     static_cast<const double*>(c->az_t), static_cast<const double*>(c->e),
-                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.p),
-                     static_cast<const double*>(B.w), x, c->r64);
-  pc_precondition(c, B, pl, c->r64, st);
+                     Prec<R>::azt(c), static_cast<const double*>(c->e),
+                     static_cast<const PcScalars*>(B.s), static_cast<const R*>(B.p),
+                     static_cast<const R*>(B.w), x, B.r);
+  pc_precondition<R>(c, B, pl, B.r, st);
   hipLaunchKernelGGL(k_pc_beta, dim3(1), dim3(kBlock), 0, st, B.s,
                      static_cast<const double*>(B.part), c->ntiles);
-  hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
-                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
+  hipLaunchKernelGGL((k_pc_dir<R>), dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const R*>(B.y), B.p);
 }
 
 // reps launches of the last Chebyshev step (y2, d -> y with the dot partials), the pass
 // every degree >= 3 application ends with; the stop flag is cleared first
-int pc_bench_step(psl_ctx* c, int reps, hipStream_t st) {
+int pc_bench_step(psl_ctx* c, int mode, int reps, hipStream_t st) {
   const PcBufs B = pc_bufs(c);
   hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, 0.0, 0);
   const PcPlan pl = pc_plan(3, 2.0 / 30.0, 2.0);
+  if (mode == PSL_MIXED) {   // the float32 step of the mixed solve
+    const PcBufsT<float> B32 = pc_bufs32(c);
+    for (int i = 0; i < reps; ++i)
+      with_cpt<PcChebC<float, false, true>::template F>(c->cpt, c, B32,
+                                                        static_cast<const float*>(B32.r),
+                                                        static_cast<const float*>(B32.y2),
+                                                        B32.y, pl.inv_theta, pl.c1[2],
+                                                        pl.c2[2], st);
+    PSL_HIP(hipGetLastError());
+    return PSL_OK;
+  }
   for (int i = 0; i < reps; ++i)
-    with_cpt<PcChebC<false, true>::template F>(c->cpt, c, B, static_cast<const double*>(c->r64),
-                                               static_cast<const double*>(B.y2), B.y,
-                                               pl.inv_theta, pl.c1[2], pl.c2[2], st);
+    with_cpt<PcChebC<double, false, true>::template F>(c->cpt, c, B,
+                                                       static_cast<const double*>(c->r64),
+                                                       static_cast<const double*>(B.y2), B.y,
+                                                       pl.inv_theta, pl.c1[2], pl.c2[2], st);
   PSL_HIP(hipGetLastError());
   return PSL_OK;
 }
@@ -2631,14 +2695,64 @@ int pc_apply(psl_ctx* c, int degree, const double* r, const double** y, hipStrea
   const PcBufs B = pc_bufs(c);
   // the stop flag gates the Chebyshev kernels; clear it (the dot partials go unused)
   hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, 0.0, 0);
-  pc_precondition(c, B, pc_plan(degree, 2.0 / 30.0, 2.0), r, st);
+  pc_precondition<double>(c, B, pc_plan(degree, 2.0 / 30.0, 2.0), r, st);
   *y = B.y;
   return PSL_OK;
 }
 
-int pc_read(psl_ctx* c, const PcBufs& B, hipStream_t st) {
-  PSL_HIP(hipMemcpyAsync(c->pc_h, B.s, sizeof(PcScalars), hipMemcpyDeviceToHost, st));
+int pc_read(psl_ctx* c, PcScalars* s, hipStream_t st) {
+  PSL_HIP(hipMemcpyAsync(c->pc_h, s, sizeof(PcScalars), hipMemcpyDeviceToHost, st));
   PSL_HIP(hipStreamSynchronize(st));
+  return PSL_OK;
+}
+
+// The CG loop on the deflated residual in B.r (already P1 r), iterate x (B.r's precision):
+// runs of iterations between host reads, check_every first, then the count the last run's
+// convergence rate predicts (iterations after the stop are cheap no-ops); stagnation when
+// ||r|| is not halved within kStallWindow iterations (the rounding floor).
+template <typename R>
+int pc_run(psl_ctx* c, const PcBufsT<R>& B, const PcPlan& pl, R* x, double goal2, int maxit,
+           int check_every, hipStream_t st, int* iters, int* status) {
+  const int64_t n = c->n;
+  hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, goal2, maxit);
+  pc_precondition<R>(c, B, pl, B.r, st);
+  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(kBlock), 0, st, B.s,
+                     static_cast<const double*>(B.part), c->ntiles);
+  hipLaunchKernelGGL((k_pc_dir<R>), dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                     static_cast<const PcScalars*>(B.s), static_cast<const R*>(B.y), B.p);
+  int rc = pc_read(c, B.s, st);
+  if (rc != PSL_OK) return rc;
+  const PcScalars* h = static_cast<const PcScalars*>(c->pc_h);
+  int run = check_every;
+  double rr_prev = h->rr;
+  int it_prev = 0;
+  double rr_mark = h->rr;
+  int it_mark = 0;
+  int stalled = 0;
+  while (!h->done) {
+    for (int i = 0; i < run; ++i) pc_iteration<R>(c, B, pl, x, st);
+    if ((rc = pc_read(c, B.s, st)) != PSL_OK) return rc;
+    if (h->done) break;
+    if (h->rr <= 0.25 * rr_mark) {
+      rr_mark = h->rr;
+      it_mark = h->iters;
+    } else if (h->iters - it_mark > kStallWindow) {
+      stalled = 1;
+      break;
+    }
+    const int its = h->iters - it_prev;
+    if (its > 0 && h->rr > 0.0 && h->rr < rr_prev) {
+      const double per_it = std::log(h->rr / rr_prev) / its;   // < 0
+      const double need = std::log(h->goal2 / h->rr) / per_it;
+      run = int(std::min<double>(kPcMaxRun, std::max(1.0, std::ceil(need))));
+    } else {
+      run = check_every;
+    }
+    rr_prev = h->rr;
+    it_prev = h->iters;
+  }
+  *iters = h->iters;
+  *status = stalled ? PSL_ESTAGNATION : h->status;
   return PSL_OK;
 }
 
@@ -2667,7 +2781,7 @@ extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_
   if (!(o.tol > 0.0) || !(o.ratio > 1.0) || !std::isfinite(o.ratio) || !(o.lmax > 0.0) ||
       !std::isfinite(o.lmax) || o.degree < 1 || o.degree > kPcMaxDegree || o.maxit < 0 ||
       (o.use_x0 != 0 && o.use_x0 != 1) || o.check_every < 1 || o.check_every > kPcMaxRun ||
-      o.reserved[0] || o.reserved[1])
+      (o.mixed != 0 && o.mixed != 1) || o.reserved[0])
     return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   psl_solve_stats stats;
@@ -2696,52 +2810,68 @@ extern "C" int psl_solve_poly(psl_ctx* c, const double* b, double* x, const psl_
     return finish(PSL_OK);
   }
   const double goal = o.tol * bnorm;
-  hipLaunchKernelGGL(k_pc_reset, dim3(1), dim3(1), 0, st, B.s, goal * goal, int(o.maxit));
-  // rhat = P1 (b - A x) (x takes the coarse part, which the final projection recomputes)
-  enqueue_outer_step(c, b, x, st);
-  pc_precondition(c, B, pl, c->r64, st);
-  hipLaunchKernelGGL(k_pc_init, dim3(1), dim3(kBlock), 0, st, B.s,
-                     static_cast<const double*>(B.part), c->ntiles);
-  hipLaunchKernelGGL(k_pc_dir, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
-                     static_cast<const PcScalars*>(B.s), static_cast<const double*>(B.y), B.p);
-  if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
-  const PcScalars* h = static_cast<const PcScalars*>(c->pc_h);
-  // runs of iterations between host reads: check_every first, then the count the last
-  // run's convergence rate predicts (iterations after the stop are cheap no-ops)
-  int run = o.check_every;
-  double rr_prev = h->rr;
-  int it_prev = 0;
-  // stagnation: ||r|| not halved within kStallWindow iterations (the rounding floor)
-  double rr_mark = h->rr;
-  int it_mark = 0;
-  int stalled = 0;
-  while (!h->done) {
-    for (int i = 0; i < run; ++i) pc_iteration(c, B, pl, x, st);
-    if ((rc = pc_read(c, B, st)) != PSL_OK) return finish(rc);
-    if (h->done) break;
-    if (h->rr <= 0.25 * rr_mark) {
-      rr_mark = h->rr;
-      it_mark = h->iters;
-    } else if (h->iters - it_mark > kStallWindow) {
-      stalled = 1;
-      break;
+  int status = PSL_OK;
+  if (!o.mixed) {
+    // rhat = P1 (b - A x) (x takes the coarse part, which the final projection recomputes)
+    enqueue_outer_step(c, b, x, st);
+    int its = 0;
+    if ((rc = pc_run<double>(c, B, pl, x, goal * goal, o.maxit, o.check_every, st, &its,
+                             &status)) != PSL_OK)
+      return finish(rc);
+    stats.iters = its;
+    stats.outer = 1;
+    // projection back: x = P2 x + x* = x + Z E^-1 Z^T (b - A x)
+    enqueue_outer_step(c, b, x, st);
+  } else {
+    // float64 refinement around the float32 polynomial CG: r64 = P1 (b - A x) (with x
+    // projected), the inner solve on r64 / ||r64|| to kPcTauInner (or to what the
+    // tolerance still needs), x += ||r64|| xi
+    if ((rc = ensure_poly32(c)) != PSL_OK) return finish(rc);
+    const PcBufsT<float> B32 = pc_bufs32(c);
+    enqueue_outer_step(c, b, x, st);
+    if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+    double rnorm = std::sqrt(c->h_sc->rr);
+    int total = 0, outer = 0;
+    for (;;) {
+      if (!std::isfinite(rnorm)) {
+        status = PSL_ENONFINITE;
+        break;
+      }
+      if (rnorm <= goal) break;
+      if (total >= o.maxit) {
+        status = PSL_EMAXIT;
+        break;
+      }
+      if (outer >= kPcMaxOuter) {
+        status = PSL_ESTAGNATION;
+        break;
+      }
+      hipLaunchKernelGGL(k_pc_scale_in<float>, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                         static_cast<const double*>(c->r64),
+                         static_cast<const double*>(&c->sc->rr), B32.r, B32.xi);
+      const double tau = std::max(kPcTauInner, 0.5 * goal / rnorm);
+      int its = 0, ist = PSL_OK;
+      if ((rc = pc_run<float>(c, B32, pl, B32.xi, tau * tau, o.maxit - total, o.check_every,
+                              st, &its, &ist)) != PSL_OK)
+        return finish(rc);
+      total += its;
+      ++outer;
+      hipLaunchKernelGGL(k_pc_accum<float>, dim3(elem_grid(n)), dim3(kBlock), 0, st, n,
+                         static_cast<const double*>(&c->sc->rr),
+                         static_cast<const float*>(B32.xi), x);
+      enqueue_outer_step(c, b, x, st);
+      if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
+      const double rnew = std::sqrt(c->h_sc->rr);
+      if (std::isfinite(rnew) && rnew > goal && !(rnew < 0.9 * rnorm)) {
+        status = ist == PSL_ENONFINITE ? PSL_ENONFINITE : PSL_ESTAGNATION;
+        rnorm = rnew;
+        break;
+      }
+      rnorm = rnew;
     }
-    const int its = h->iters - it_prev;
-    if (its > 0 && h->rr > 0.0 && h->rr < rr_prev) {
-      const double per_it = std::log(h->rr / rr_prev) / its;   // < 0
-      const double need = std::log(h->goal2 / h->rr) / per_it;
-      run = int(std::min<double>(kPcMaxRun, std::max(1.0, std::ceil(need))));
-    } else {
-      run = o.check_every;
-    }
-    rr_prev = h->rr;
-    it_prev = h->iters;
+    stats.iters = total;
+    stats.outer = outer;
   }
-  stats.iters = h->iters;
-  stats.outer = 1;
-  const int status = stalled ? PSL_ESTAGNATION : h->status;
-  // projection back: x = P2 x + x* = x + Z E^-1 Z^T (b - A x)
-  enqueue_outer_step(c, b, x, st);
   launch_stencil<double, 1>(c, x, b, c->t64, st);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
   if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);

@@ -73,7 +73,8 @@ class psl_gmres_opts(ctypes.Structure):
 class psl_poly_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("ratio", ctypes.c_double), ("lmax", ctypes.c_double),
                 ("degree", ctypes.c_int32), ("maxit", ctypes.c_int32), ("use_x0", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("check_every", ctypes.c_int32), ("mixed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 _P = ctypes.c_void_p
@@ -338,8 +339,9 @@ def psl_solve_poly(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = No
                    tol: Optional[float] = None, degree: Optional[int] = None,
                    ratio: Optional[float] = None, lmax: Optional[float] = None,
                    maxit: Optional[int] = None, check_every: Optional[int] = None,
-                   use_x0: bool = False, check: bool = False):
-    """Deflated CG with the Chebyshev polynomial preconditioner; returns (x, stats dict)."""
+                   use_x0: bool = False, mixed: bool = False, check: bool = False):
+    """Deflated CG with the Chebyshev polynomial preconditioner (mixed: float32 inner
+    solves in float64 refinement); returns (x, stats dict)."""
     o = psl_poly_opts()
     _default_poly_opts(ctypes.byref(o))
     for name, val in (("tol", tol), ("degree", degree), ("ratio", ratio), ("lmax", lmax),
@@ -347,6 +349,7 @@ def psl_solve_poly(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = No
         if val is not None:
             setattr(o, name, val)
     o.use_x0 = 1 if use_x0 else 0
+    o.mixed = 1 if mixed else 0
     if x is None:
         if use_x0:
             raise ValueError("use_x0 needs x")

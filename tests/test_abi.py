@@ -94,8 +94,8 @@ def test_default_poly_opts(lib):
     o = psl.psl_poly_opts()
     psl._default_poly_opts(ctypes.byref(o))
     assert o.tol == 1e-8 and o.ratio == 30.0 and o.lmax == 2.0 and o.degree == 3
-    assert o.maxit == 10000 and o.use_x0 == 0 and o.check_every == 16
-    assert list(o.reserved) == [0, 0]
+    assert o.maxit == 10000 and o.use_x0 == 0 and o.check_every == 16 and o.mixed == 0
+    assert list(o.reserved) == [0]
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):

@@ -43,11 +43,12 @@ def _solve(psl, s, b, solver, mode):
     if solver == "gmres":
         return psl.psl_solve_gmres(s.ctx, b, tol=1e-8, restart=30)
     if solver == "poly":
-        return psl.psl_solve_poly(s.ctx, b, tol=1e-8)
+        return psl.psl_solve_poly(s.ctx, b, tol=1e-8, mixed=mode == "mixed")
     return psl.psl_solve(s.ctx, b, tol=1e-8, mode=psl.MIXED if mode == "mixed" else psl.FP64)
 
 
-C2_CASES = [("fp64", "dpcg"), ("mixed", "dpcg"), ("fp64", "poly"), ("fp64", "gmres")]
+C2_CASES = [("fp64", "dpcg"), ("mixed", "dpcg"), ("fp64", "poly"), ("mixed", "poly"),
+            ("fp64", "gmres")]
 
 
 @pytest.mark.parametrize("mode,solver", C2_CASES, ids=[f"{s}-{m}" for m, s in C2_CASES])
@@ -74,11 +75,15 @@ def test_layered_full_size(gpu_lib, mode, solver):
         f"relres={O.relres(A, b, xg):.2e}")
     assert st["status"] == 0 and O.relres(A, b, xg) <= 1e-8
     assert np.linalg.norm(xg - xr) / np.linalg.norm(xr) <= 1e-6
-    assert abs(st["iters"] - ref.iters) <= max(2, 0.03 * ref.iters)
+    if solver == "poly" and mode == "mixed":   # float32 inner solves restart the recursion
+        assert st["outer"] >= 1 and st["iters"] <= 2 * ref.iters
+    else:
+        assert abs(st["iters"] - ref.iters) <= max(2, 0.03 * ref.iters)
 
 
 C3_CASES = [("fp64", "dpcg", False), ("mixed", "dpcg", False), ("mixed", "dpcg", True),
-            ("fp64", "poly", True), ("fp64", "poly", False), ("fp64", "gmres", True)]
+            ("fp64", "poly", True), ("fp64", "poly", False), ("mixed", "poly", True),
+            ("mixed", "poly", False), ("fp64", "gmres", True)]
 
 
 @pytest.mark.parametrize("mode,solver,components", C3_CASES,

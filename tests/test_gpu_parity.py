@@ -271,6 +271,33 @@ def test_poly_parity(gpu_lib, name, scale, degree, ratio, comp):
         assert abs(st["iters"] - O.dpcg(A, b, Z, tol=1e-8, coarse=co).iters) <= 2
 
 
+POLY_MIXED_CASES = [("c1", 1, False), ("c2", 4, False), ("chan", 0, False), ("chan", 0, True)]
+
+
+@pytest.mark.parametrize("name,scale,comp", POLY_MIXED_CASES,
+                         ids=[f"{c[0]}/{c[1]}{'-comp' if c[2] else ''}" for c in POLY_MIXED_CASES])
+def test_poly_mixed(gpu_lib, name, scale, comp):
+    """The polynomial-preconditioned CG in float32 inside float64 refinement: the oracle's
+    accuracy bar (1e-8 true residual in the oracle's matrix, 1e-6 against the 1e-12
+    solution) and at most twice the float64 solve's iterations."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _op_problem(name, scale)
+    say(f"poly mixed {name}/{scale} grid={p.grid} components={comp}")
+    s = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr), components=comp)
+    x, st = psl.psl_solve_poly(s.ctx, dev(p.q), mixed=True)
+    _, st64 = psl.psl_solve_poly(s.ctx, dev(p.q))
+    A, b = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    labels = O.levelset_components if comp else O.levelset_labels
+    lab, d = labels(p.grid, p.K, p.nsub, p.thr)
+    xr = O.dpcg(A, b, O.deflation_matrix(lab, d), tol=1e-12).x
+    say(f"  status={st['status_str']} iters={st['iters']} outer={st['outer']} "
+        f"(float64 {st64['iters']})")
+    assert st["status"] == 0 and O.relres(A, b, host(x)) <= 1e-8 and st["relres_true"] <= 1e-8
+    assert np.linalg.norm(host(x) - xr) / np.linalg.norm(xr) <= 1e-6
+    assert st["outer"] >= 1 and st["iters"] <= 2 * st64["iters"]
+
+
 def test_poly_result_independent_of_host_checks(gpu_lib):
     """The host's read interval only changes how many launches run after the stop flag
     (as no-ops): x and the iteration count are bit-identical for 1, 16 and 512."""
