@@ -52,12 +52,13 @@ def test_binding_struct_layout_matches_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "psl.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(psl_solve_opts),"
         " sizeof(psl_solve_stats), offsetof(psl_solve_opts, tau_inner),"
         " offsetof(psl_solve_opts, check_every), offsetof(psl_solve_opts, mixed_floor),"
         " offsetof(psl_solve_stats, relres_true), sizeof(psl_grid), sizeof(psl_setup_opts),"
         " sizeof(psl_gmres_opts), offsetof(psl_gmres_opts, use_x0), sizeof(psl_poly_opts),"
-        " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every));"
+        " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every),"
+        " offsetof(psl_poly_opts, mixed), offsetof(psl_gmres_opts, degree));"
         "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -70,7 +71,8 @@ def test_binding_struct_layout_matches_c(tmp_path):
             ctypes.sizeof(psl.psl_grid), ctypes.sizeof(psl.psl_setup_opts),
             ctypes.sizeof(psl.psl_gmres_opts), psl.psl_gmres_opts.use_x0.offset,
             ctypes.sizeof(psl.psl_poly_opts), psl.psl_poly_opts.degree.offset,
-            psl.psl_poly_opts.check_every.offset]
+            psl.psl_poly_opts.check_every.offset, psl.psl_poly_opts.mixed.offset,
+            psl.psl_gmres_opts.degree.offset]
     assert got == want
 
 
