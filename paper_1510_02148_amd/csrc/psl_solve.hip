@@ -1906,7 +1906,7 @@ __global__ void __launch_bounds__(kBlock) k_gm_reduce(const double* part, int G,
   if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
 }
 
-// v <- v / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted), z = M^-1 v
+// v <- v / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted), z = D^-1 v
 __global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const double* nrm2,
                            double* __restrict__ v, double* __restrict__ z) {
   const double s = nrm2[0];
@@ -2024,7 +2024,8 @@ int gm_operator(psl_ctx* c, int degree, double* v, const double* nrm2, double* w
   return PSL_OK;
 }
 
-// x += sum_i y[i] V_i (the polynomial preconditioner's update: M^-1 applied to the sum)
+// out = sum_i y[i] V_i (with the polynomial preconditioner the cycle's update is
+// x += M^-1 out, M^-1 applied once to the combination)
 __global__ void k_gm_combine(int64_t n, const double* __restrict__ V, int nv,
                              const double* __restrict__ y, double* __restrict__ out) {
   for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n;
