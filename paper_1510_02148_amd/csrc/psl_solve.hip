@@ -1906,7 +1906,8 @@ __global__ void __launch_bounds__(kBlock) k_gm_reduce(const double* part, int G,
   if (threadIdx.x == 0) out[blockIdx.x] = acc[0];
 }
 
-// v <- v / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted), z = D^-1 v
+// v <- v / sqrt(nrm2[0]) (0 when the norm is 0: the Krylov space is exhausted), and
+// z = D^-1 v unless z is null (the polynomial preconditioner forms its own)
 __global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const double* nrm2,
                            double* __restrict__ v, double* __restrict__ z) {
   const double s = nrm2[0];
@@ -1915,7 +1916,7 @@ __global__ void k_gm_scale(int64_t n, const double* __restrict__ invd, const dou
        c += int64_t(gridDim.x) * blockDim.x) {
     const double vc = v[c] * inv;
     v[c] = vc;
-    z[c] = invd[c] * vc;
+    if (z) z[c] = invd[c] * vc;
   }
 }
 
@@ -2012,7 +2013,7 @@ void gm_orthogonalize(psl_ctx* c, int nv, double* w, double* h1, double* h2, dou
 int gm_operator(psl_ctx* c, int degree, double* v, const double* nrm2, double* w,
                 hipStream_t st) {
   hipLaunchKernelGGL(k_gm_scale, dim3(elem_grid(c->n)), dim3(kBlock), 0, st, c->n,
-                     c->invdiag, nrm2, v, c->t64);
+                     c->invdiag, nrm2, v, degree >= 2 ? nullptr : c->t64);
   const double* z = c->t64;
   if (degree >= 2) {
     const int rc = pc_apply(c, degree, v, &z, st);

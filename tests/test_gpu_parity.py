@@ -694,6 +694,31 @@ def test_other_solvers_edge_cases(gpu_lib, solver, degree):
     assert abs(st["iters"] - ref.iters) <= max(3, 0.05 * ref.iters)
 
 
+def test_bench_kernel_ids_need_their_solver(gpu_lib):
+    """The GMRES pass and the Chebyshev step can only be timed after a solve of that kind
+    (and the Chebyshev step's float32 form after a mixed one); afterwards they run."""
+    psl = gpu_lib
+    say("bench kernel ids")
+    s = _setup(psl, pi.config("c2", scale=4))
+    for kid, mode in ((psl.KERNEL_GMRES_PASS, psl.FP64), (psl.KERNEL_POLY_STEP, psl.FP64),
+                      (psl.KERNEL_POLY_STEP, psl.MIXED)):
+        with pytest.raises(psl.PslError) as e:
+            psl.psl_bench_kernel(s.ctx, kid, mode, 2)
+        assert e.value.status == psl.EINVAL
+    b = dev(pi.config("c2", scale=4).q)
+    psl.psl_solve_gmres(s.ctx, b)
+    psl.psl_solve_poly(s.ctx, b)
+    psl.psl_bench_kernel(s.ctx, psl.KERNEL_GMRES_PASS, psl.FP64, 2)
+    psl.psl_bench_kernel(s.ctx, psl.KERNEL_POLY_STEP, psl.FP64, 2)
+    with pytest.raises(psl.PslError):
+        psl.psl_bench_kernel(s.ctx, psl.KERNEL_POLY_STEP, psl.MIXED, 2)
+    with pytest.raises(psl.PslError):
+        psl.psl_bench_kernel(s.ctx, psl.KERNEL_GMRES_PASS, psl.MIXED, 2)
+    psl.psl_solve_poly(s.ctx, b, mixed=True)
+    psl.psl_bench_kernel(s.ctx, psl.KERNEL_POLY_STEP, psl.MIXED, 2)
+    torch.cuda.synchronize()
+
+
 def test_setup_errors(gpu_lib):
     psl = gpu_lib
     say("edge setup errors")
