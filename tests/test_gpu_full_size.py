@@ -192,3 +192,27 @@ def test_conv3_full_resolution_sampled(gpu_lib):
         worst = max(worst, np.abs(got[z, yy, xx] - ref).max() / scale)
     say(f"  max error over {len(cells)} cells {worst:.2e} (relative to max(|ref|, 1))")
     assert worst <= 2e-6
+
+
+DET_CASES = [("dpcg", "fp64"), ("dpcg", "mixed"), ("poly", "fp64"), ("poly", "mixed"),
+             ("gmres", "fp64")]
+
+
+@pytest.mark.parametrize("solver,mode", DET_CASES, ids=[f"{s}-{m}" for s, m in DET_CASES])
+def test_full_size_bit_reproducible(gpu_lib, solver, mode):
+    """128x128x64 in the benchmark's configuration: two solves on one context and one on a
+    fresh context give the same x bit for bit and the same iteration count (every
+    reduction has a fixed order; no result depends on workgroup timing)."""
+    psl = gpu_lib
+    p = pi.config("c2")
+    say(f"bit reproducibility c2 {solver} {mode}")
+    prec = "f32" if mode == "mixed" else "f64"
+    s = _setup(psl, p, prec, False)
+    b = dev(p.q)
+    x1, st1 = _solve(psl, s, b, solver, mode)
+    x1 = x1.clone()
+    x2, st2 = _solve(psl, s, b, solver, mode)
+    s2 = _setup(psl, p, prec, False)
+    x3, st3 = _solve(psl, s2, b, solver, mode)
+    assert st1["status"] == 0 and st1["iters"] == st2["iters"] == st3["iters"]
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
