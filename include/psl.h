@@ -49,7 +49,7 @@ extern "C" {
 #define PSL_EBREAKDOWN   -6  /* (p, P1 A p) <= 0 inside CG */
 #define PSL_ENONFINITE   -7  /* NaN/Inf in b, x0 or an iterate */
 #define PSL_ESTAGNATION  -8  /* refinement stopped reducing the FP64 residual */
-#define PSL_ENOTSUP      -9  /* valid request this build does not support (limit given) */
+#define PSL_ENOTSUP      -9  /* valid request the library does not support (limit given) */
 
 /* ---- Dirichlet face mask for psl_assemble_tpfa ----------------------------------- */
 #define PSL_DIRICHLET_X_LO  1u
@@ -63,7 +63,7 @@ extern "C" {
 #define PSL_FP64   0  /* CG vectors and stencil in float64 */
 #define PSL_MIXED  1  /* CG vectors and stencil in float32 inside float64 refinement */
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define PSL_MAX_THRESHOLDS   15     /* levelset thresholds per call (classes <= 16) */
 #define PSL_MAX_DENSE_D      8192   /* coarse dimension d (E and E^-1 are held dense) */
 #define PSL_MAX_TILE_LABELS  16     /* distinct labels inside one work tile */

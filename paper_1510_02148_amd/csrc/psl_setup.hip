@@ -31,7 +31,7 @@ extern "C" const char* psl_status_str(int s) {
     case PSL_EBREAKDOWN: return "CG breakdown (p^T P1 A p <= 0)";
     case PSL_ENONFINITE: return "non-finite value in input or iterate";
     case PSL_ESTAGNATION: return "refinement stagnated";
-    case PSL_ENOTSUP: return "not supported by this build";
+    case PSL_ENOTSUP: return "not supported by the library";
     default: return "unknown status";
   }
 }
@@ -51,7 +51,7 @@ extern "C" void psl_default_opts(psl_solve_opts* o) {
 
 // Device memory comes from the device's stream-ordered pool, which keeps freed blocks
 // (release threshold raised once per device), so building and destroying contexts
-// repeatedly does not go back to the driver. Blocks are ordered on the stream of the
+// repeatedly does not return memory to the HIP runtime. Blocks are ordered on the stream of the
 // entry point that asks for them; psl_destroy waits for the device before freeing.
 thread_local hipStream_t psl_alloc_stream = nullptr;
 
