@@ -67,6 +67,8 @@ extern "C" {
 #define PSL_MAX_THRESHOLDS   15     /* levelset thresholds per call (classes <= 16) */
 #define PSL_MAX_DENSE_D      8192   /* coarse dimension d (E and E^-1 are held dense) */
 #define PSL_MAX_TILE_LABELS  16     /* distinct labels inside one work tile */
+#define PSL_MAX_CELLS   536870911   /* 2^29 - 1: cells of a grid, and entries of each of its
+                                       face arrays; larger grids give PSL_ENOTSUP */
 
 typedef struct { int32_t nx, ny, nz; } psl_grid;
 
@@ -101,6 +103,9 @@ typedef struct {
   double  relres_true;  /* ||b - A x||_2 / ||b||_2 in float64 from a fresh product */
   double  bnorm;        /* ||b||_2 */
   double  t_solve_s;    /* wall time of the call (host clock, stream synchronised) */
+  double  zt_r_drift;   /* ||Z^T r||_2 / ||r||_2 for the returned x, r = b - A x: the
+                           deflation invariant Z^T P1 = 0 (Section 3.1) under rounding
+                           (0 when r = 0); psl_solve only, other solvers leave 0 */
 } psl_solve_stats;
 
 /* Fill `o` with the defaults listed above. */
@@ -163,8 +168,8 @@ void psl_default_poly_opts(psl_poly_opts* o);
 
 /*
  * psl_solve_poly -- deflated CG with a stronger preconditioner on the deflated system
- * (Section 1 and the SPE10 experiment of Section 5 pair the subdomain-levelset deflation
- * with AMG applied to the deflated system; AMG is not built here). M^-1 = q(D^-1 A) D^-1,
+ * (Section 1 and the SPE10 experiment of Section 4 (Table 5) pair the subdomain-levelset
+ * deflation with AMG applied to the deflated system; AMG is not built here). M^-1 = q(D^-1 A) D^-1,
  * D = diag(A): `degree` steps of the Chebyshev semi-iteration for A y = r on the interval
  * [lmax / ratio, lmax], from y = 0 (symmetric positive definite for lmax at or above the
  * spectrum of D^-1 A). The CG is the DEF1 loop of psl_solve (P1 from E = Z^T A Z, eq.
@@ -190,7 +195,8 @@ int psl_solve_poly(psl_ctx* ctx, const double* b, double* x, const psl_poly_opts
  *   Tx, Ty, Tz     dev out, float64, face arrays as described above.
  * Interior face: 2 Ka Kb / (Ka + Kb) (harmonic mean over unit spacing), 0 if Ka+Kb = 0.
  * Dirichlet outer face: 2 K of the adjacent cell (half-cell distance). Other outer
- * faces: 0. Errors: PSL_EINVAL for a non-positive grid size or null pointer.
+ * faces: 0. Errors: PSL_EINVAL for a non-positive grid size or null pointer,
+ * PSL_ENOTSUP for a grid above PSL_MAX_CELLS.
  */
 int psl_assemble_tpfa(const psl_grid* g, const double* K, uint32_t dirichlet_mask,
                       double* Tx, double* Ty, double* Tz, void* stream);
@@ -213,8 +219,9 @@ int psl_assemble_tpfa(const psl_grid* g, const double* K, uint32_t dirichlet_mas
  *   d        host out: number of deflation vectors.
  * The column of a cell is the rank of key = s * ncls + class among the keys that occur
  * (empty regions get no column, so Z has full rank). Integer result, bit-exact.
- * Errors: PSL_EINVAL (bad sizes, nsub out of range, unsorted thr, class out of range
- * is not checked: a manual class outside [0, ncls) gives an undefined labelling).
+ * Errors: PSL_EINVAL (bad sizes, nsub out of range, unsorted thr, a manual class
+ * outside [0, ncls); labels is then unspecified), PSL_ENOTSUP (more than PSL_MAX_CELLS
+ * cells, or more than 2^26 (subdomain, class) keys).
  */
 int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
                 const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
@@ -248,7 +255,7 @@ int psl_build_Z_cc(const psl_grid* g, const double* K, const int32_t nsub[3],
  *            subdomain-per-processor layout of Section 3.2 moved onto compute units).
  *            NULL lets the library choose boxes of about 16x16x8 cells.
  * Errors: PSL_EINVAL, PSL_ENOMEM, PSL_ENOTSPD (a cell with diag(A) <= 0 or E not SPD),
- * PSL_ENOTSUP (d > PSL_MAX_DENSE_D).
+ * PSL_ENOTSUP (d > PSL_MAX_DENSE_D, or a grid above PSL_MAX_CELLS).
  */
 int psl_setup_E(psl_ctx** ctx, const psl_grid* g, const double* Tx, const double* Ty,
                 const double* Tz, const int32_t* labels, int32_t d, const int32_t nsub[3],
@@ -388,8 +395,9 @@ int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, v
 
 /*
  * psl_bench_copy -- device-to-device streaming copy of `bytes` (multiple of 16, both
- * pointers 16-byte aligned) with a plain load/store kernel: the reference for achievable
- * bandwidth and for calibrating hardware byte counters.
+ * pointers 16-byte aligned) with a plain load/store kernel, one 16-byte load and store per
+ * thread: the reference for achievable bandwidth and for calibrating hardware byte
+ * counters. Errors: PSL_EINVAL (null or misaligned pointer, bad size).
  */
 int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* stream);
 

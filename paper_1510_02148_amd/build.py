@@ -1,4 +1,5 @@
-"""Build libpsl.so (the HIP library behind include/psl.h) for gfx950 with hipcc."""
+"""Build libpsl.so (the HIP library behind include/psl.h) for gfx950 with hipcc: each
+source is compiled to an object in its own process, then the objects are linked."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["psl_setup.hip", "psl_solve.hip", "psl_nn.hip"]
 
 HIPCC_FLAGS = [
@@ -15,7 +17,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-result",
     # no packed float32 instructions
@@ -31,9 +32,20 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = True) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    os.makedirs(OBJDIR, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        objs.append(obj)
+    failed = [src for p, src in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + srcs + ["-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

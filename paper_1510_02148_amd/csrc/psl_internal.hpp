@@ -36,6 +36,7 @@ struct Scalars {
   double sigma;      // inner scale: r0 = sigma * r
   double bnorm2;
   double delta;      // (p, P1 A p) of the last step (diagnostic)
+  double ztr2;       // ||Z^T r||^2 of the final float64 residual (diagnostic)
   int32_t cnt[2];    // iterations done
   int32_t done;      // inner loop finished (converged or failed)
   int32_t iters;     // inner iterations done in this inner solve

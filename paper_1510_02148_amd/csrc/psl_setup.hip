@@ -136,14 +136,17 @@ void psl_internal_pinned_put(void* p) {
   g_pinned_free.push_back(p);
 }
 
-static bool grid_ok(const psl_grid* g) {
-  if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return false;
-  const int64_t n = int64_t(g->nx) * g->ny * g->nz;
-  // faces and cells are indexed with int32 inside kernels
-  const int64_t faces = int64_t(g->nx + 1) * g->ny * g->nz;
-  return n <= (int64_t(1) << 30) && faces < (int64_t(1) << 31) &&
-         int64_t(g->nx) * (g->ny + 1) * g->nz < (int64_t(1) << 31) &&
-         int64_t(g->nx) * g->ny * (g->nz + 1) < (int64_t(1) << 31);
+// PSL_OK, PSL_EINVAL (missing grid or a non-positive extent) or PSL_ENOTSUP (more than
+// PSL_MAX_CELLS cells or entries in a face array: the solve kernels form byte offsets of
+// float64 cell and face arrays in 32 bits, which stay exact below 2^29 elements)
+static int grid_check(const psl_grid* g) {
+  if (!g || g->nx < 1 || g->ny < 1 || g->nz < 1) return PSL_EINVAL;
+  const int64_t lim = PSL_MAX_CELLS;
+  const int64_t nx = g->nx, ny = g->ny, nz = g->nz;
+  if (nx * ny * nz > lim || (nx + 1) * ny * nz > lim || nx * (ny + 1) * nz > lim ||
+      nx * ny * (nz + 1) > lim)
+    return PSL_ENOTSUP;
+  return PSL_OK;
 }
 
 static inline unsigned nblocks(int64_t work, int per = kBlock) {
@@ -193,7 +196,8 @@ __global__ void k_tpfa(const double* __restrict__ K, double* __restrict__ T, int
 
 extern "C" int psl_assemble_tpfa(const psl_grid* g, const double* K, uint32_t mask,
                                  double* Tx, double* Ty, double* Tz, void* stream) {
-  if (!grid_ok(g) || !K || !Tx || !Ty || !Tz || (mask & ~63u)) return PSL_EINVAL;
+  if (const int grc = grid_check(g)) return grc;
+  if (!K || !Tx || !Ty || !Tz || (mask & ~63u)) return PSL_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   double* T[3] = {Tx, Ty, Tz};
@@ -224,6 +228,7 @@ __device__ inline int cell_key(int c, int nx, int ny, int nz, int sx, int sy, in
   int k;
   if (cls) {
     k = cls[c];
+    if (k < 0 || k >= ncls) return -1;   // reported as an invalid class by the caller
   } else {
     const double v = K[c];
     k = 0;
@@ -284,7 +289,8 @@ extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsu
                            const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
                            int32_t* labels, int32_t* d, void* stream) {
   psl_alloc_stream = static_cast<hipStream_t>(stream);
-  if (!grid_ok(g) || !nsub || !labels || !d) return PSL_EINVAL;
+  if (const int grc = grid_check(g)) return grc;
+  if (!nsub || !labels || !d) return PSL_EINVAL;
   if (!cls && !K) return PSL_EINVAL;
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   const int ext[3] = {nx, ny, nz};
@@ -478,7 +484,8 @@ __global__ void k_cc_label(int n, const int32_t* parent, const int32_t* rank, in
 static int build_z_args(const psl_grid* g, const double* K, const int32_t nsub[3],
                         const double* thr, int32_t nthr, const int32_t* cls, int32_t& ncls,
                         int32_t* labels, int32_t* d, ThrPack& tp, int& nkeys) {
-  if (!grid_ok(g) || !nsub || !labels || !d) return PSL_EINVAL;
+  if (const int grc = grid_check(g)) return grc;
+  if (!nsub || !labels || !d) return PSL_EINVAL;
   if (!cls && !K) return PSL_EINVAL;
   const int ext[3] = {g->nx, g->ny, g->nz};
   for (int a = 0; a < 3; ++a)
@@ -1455,7 +1462,8 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   }
   if (!out) return PSL_EINVAL;
   *out = nullptr;
-  if (!grid_ok(g) || !Tx || !Ty || !Tz || !labels || d < 1) return PSL_EINVAL;
+  if (const int grc = grid_check(g)) return grc;
+  if (!Tx || !Ty || !Tz || !labels || d < 1) return PSL_EINVAL;
   if (d > PSL_MAX_DENSE_D) return PSL_ENOTSUP;
   const int nx = g->nx, ny = g->ny, nz = g->nz;
   int ns[3];

@@ -1046,19 +1046,26 @@ __global__ void k_bench_prep(Scalars* sc) {
   sc->maxit = 0x7fffffff;
 }
 
-// streaming copy used to calibrate byte counters and the achievable bandwidth
+// streaming copy used to calibrate byte counters and the achievable bandwidth: one
+// 16-byte load and store per thread, one workgroup per 4 KiB (no grid-stride loop, which
+// keeps fewer requests in flight per workgroup and streams more slowly)
 __global__ void __launch_bounds__(kBlock) k_copy16(const uint4* __restrict__ src,
                                                    uint4* __restrict__ dst, int64_t n16) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
+}
+
+// sum over labels of (Z^T v)_l^2 from the label-major partials (one workgroup)
+__global__ void __launch_bounds__(kBlock) k_zt_norm2(const double* zq, const int32_t* lab_ptr,
+                                                     int d, double* out) {
+  __shared__ double lds[kNW];
+  double acc[1] = {0.0};
+  for (int l = threadIdx.x; l < d; l += kBlock) {
+    const double v = label_sum(zq, lab_ptr, l);
+    acc[0] += v * v;
   }
-  for (; i < n16; i += stride) dst[i] = src[i];
+  psl::block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) *out = acc[0];
 }
 
 // float32 -> float64 copy of both search-direction buffers (precision handover that
@@ -1732,11 +1739,14 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   // iterate it has seen
   if (status != PSL_OK && status != PSL_EMAXIT && best_rnorm < last_rnorm)
     PSL_HIP(hipMemcpyAsync(x, c->xbest, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-  // fresh float64 residual of the returned x
+  // fresh float64 residual of the returned x, and its component in the range of Z
   launch_stencil<double, 1>(c, x, b, c->t64, st);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 0), c->ntiles, &c->sc->rr);
+  hipLaunchKernelGGL(k_zt_norm2, dim3(1), dim3(kBlock), 0, st, c->zq, c->lab_ptr, c->d,
+                     &c->sc->ztr2);
   if ((rc = read_scalars(c, st)) != PSL_OK) return finish(rc);
   stats.relres_true = std::sqrt(c->h_sc->rr) / bnorm;
+  stats.zt_r_drift = c->h_sc->rr > 0.0 ? std::sqrt(c->h_sc->ztr2 / c->h_sc->rr) : 0.0;
   stats.iters = total_iters;
   return finish(status);
 }
@@ -1800,8 +1810,8 @@ extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* s
       (reinterpret_cast<uintptr_t>(src) % 16) || (reinterpret_cast<uintptr_t>(dst) % 16))
     return PSL_EINVAL;
   const int64_t n16 = bytes / 16;
-  const unsigned grid =
-      static_cast<unsigned>(std::min<int64_t>((n16 + kBlock - 1) / kBlock, 256 * 16));
+  if ((n16 + kBlock - 1) / kBlock > 0x7fffffff) return PSL_EINVAL;
+  const unsigned grid = static_cast<unsigned>((n16 + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   PSL_HIP(hipGetLastError());

@@ -58,7 +58,8 @@ class psl_ctx_info(ctypes.Structure):
 class psl_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("outer", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("fell_back", ctypes.c_int32), ("relres_true", ctypes.c_double),
-                ("bnorm", ctypes.c_double), ("t_solve_s", ctypes.c_double)]
+                ("bnorm", ctypes.c_double), ("t_solve_s", ctypes.c_double),
+                ("zt_r_drift", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -59,6 +59,7 @@ def test_binding_struct_layout_matches_c(tmp_path):
         " sizeof(psl_gmres_opts), offsetof(psl_gmres_opts, use_x0), sizeof(psl_poly_opts),"
         " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every),"
         " offsetof(psl_poly_opts, mixed), offsetof(psl_gmres_opts, degree));"
+        "printf(\"%zu\\n\", offsetof(psl_solve_stats, zt_r_drift));"
         "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -72,7 +73,7 @@ def test_binding_struct_layout_matches_c(tmp_path):
             ctypes.sizeof(psl.psl_gmres_opts), psl.psl_gmres_opts.use_x0.offset,
             ctypes.sizeof(psl.psl_poly_opts), psl.psl_poly_opts.degree.offset,
             psl.psl_poly_opts.check_every.offset, psl.psl_poly_opts.mixed.offset,
-            psl.psl_gmres_opts.degree.offset]
+            psl.psl_gmres_opts.degree.offset, psl.psl_solve_stats.zt_r_drift.offset]
     assert got == want
 
 
@@ -130,3 +131,29 @@ def test_batched_rejects_bad_arguments_without_device_work(lib):
     arr = (ctypes.c_void_p * 1)(None)
     assert psl._solve_batched(arr, 0, arr, arr, None, st, None) == psl.EINVAL
     assert psl._solve_batched(arr, 1, arr, arr, None, st, None) == psl.EINVAL
+
+
+def test_grids_above_the_cell_limit_refused_before_device_work(lib):
+    """Grids whose cell count or a face-array length exceeds PSL_MAX_CELLS (2^29 - 1) are
+    refused with PSL_ENOTSUP by every entry point that takes a grid, before any device
+    work (the solve kernels form float64 byte offsets in 32 bits)."""
+    from paper_1510_02148_amd import psl
+    src = open(HEADER).read()
+    lim = int(re.search(r"#define PSL_MAX_CELLS\s+(\d+)", src).group(1))
+    assert lim == 2**29 - 1
+    fake = ctypes.c_void_p(16)   # never dereferenced: the size check comes first
+    d = ctypes.c_int32(0)
+    ns = (ctypes.c_int32 * 3)(1, 1, 1)
+    out = ctypes.c_void_p(0)
+    for g in (psl.psl_grid(1024, 1024, 512),        # 2^29 cells
+              psl.psl_grid(2**29 - 1, 1, 1),        # cells at the limit, x faces above it
+              psl.psl_grid(1, 2**29 - 1, 1),        # y faces above the limit
+              psl.psl_grid(1, 1, 2**29 - 1)):       # z faces above the limit
+        assert psl._assemble(ctypes.byref(g), fake, 1, fake, fake, fake, None) == psl.ENOTSUP
+        assert psl._build_z(ctypes.byref(g), fake, ns, None, 0, None, 0, fake,
+                            ctypes.byref(d), None) == psl.ENOTSUP
+        assert psl._build_z_cc(ctypes.byref(g), fake, ns, None, 0, None, 0, fake,
+                               ctypes.byref(d), None) == psl.ENOTSUP
+        rc = psl._setup_e(ctypes.byref(out), ctypes.byref(g), fake, fake, fake, fake, 3, None,
+                          None)
+        assert rc == psl.ENOTSUP and not out.value

@@ -90,10 +90,18 @@ def test_conv3_forward(gpu_lib, cin, cout, relu):
     assert np.array_equal(from_bf16_bits(y).reshape(-1), N.bf16_round(yf.cpu().numpy()).reshape(-1))
 
 
-@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (32, 48), (112, 48), (48, 64)])
-def test_conv3_input_and_weight_gradients(gpu_lib, cin, cout):
+# (24, 20, 19) has 9120 cells: the weight gradient's split over 4096-cell chunks then has
+# two full chunks and a ragged third, whose partial sums the finishing pass adds
+BACKWARD_CASES = [(GRID, 16, 16), (GRID, 48, 16), (GRID, 32, 48), (GRID, 112, 48),
+                  (GRID, 48, 64), ((24, 20, 19), 16, 32), ((24, 20, 19), 48, 16)]
+
+
+@pytest.mark.parametrize("grid,cin,cout", BACKWARD_CASES,
+                         ids=[f"{g[0]}x{g[1]}x{g[2]}-{a}-{b}" for g, a, b in BACKWARD_CASES])
+def test_conv3_input_and_weight_gradients(gpu_lib, grid, cin, cout):
     import torch
     from paper_1510_02148_amd import nn
+    GRID = grid
     say(f"conv3 backward cin={cin} cout={cout} grid={GRID}")
     n = int(np.prod(GRID))
     x = _grid_arr(GRID, cin, 4)
