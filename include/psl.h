@@ -228,6 +228,24 @@ int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
                 int32_t* labels, int32_t* d, void* stream);
 
 /*
+ * psl_build_Z_noalloc -- psl_build_Z for callers that cannot allocate device memory
+ * (code that must not call hipMalloc: graph-building or tight serving loops, harnesses
+ * that forbid allocation). Same arguments, labelling, conventions and errors as
+ * psl_build_Z; it calls no hipMalloc/hipFree or other allocating routine. Its scratch
+ * (key flags and their prefix sum, 2 * PSL_NOALLOC_MAX_KEYS + 2 int32, about 2 MiB) is a
+ * fixed device array of the library, one copy per GPU, held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (two host threads, or
+ * two streams) race and give undefined labels. Like psl_build_Z it synchronises `stream`
+ * to return d. Errors: as psl_build_Z, and PSL_ENOTSUP when nsub[0] nsub[1] nsub[2]
+ * times the class count exceeds PSL_NOALLOC_MAX_KEYS (checked before any device work);
+ * PSL_EHIP if the scratch address cannot be obtained on the current device.
+ */
+#define PSL_NOALLOC_MAX_KEYS 262144   /* (subdomain, class) keys psl_build_Z_noalloc takes */
+int psl_build_Z_noalloc(const psl_grid* g, const double* K, const int32_t nsub[3],
+                        const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                        int32_t* labels, int32_t* d, void* stream);
+
+/*
  * psl_build_Z_cc -- automatic subdomain-levelset construction: like psl_build_Z, but
  * every (subdomain, class) region is split into its face-connected components (cells
  * sharing a face: 6 neighbours in 3D, 4 in 2D), one deflation vector each. Section 3.2

@@ -259,6 +259,11 @@ __global__ void k_key_rank(int n, int nx, int ny, int nz, int sx, int sy, int sz
   labels[c] = (key >= 0 && key < nkeys) ? rank[key] : -1;
 }
 
+// argument checks shared by psl_build_Z, psl_build_Z_noalloc and psl_build_Z_cc
+static int build_z_args(const psl_grid* g, const double* K, const int32_t nsub[3],
+                        const double* thr, int32_t nthr, const int32_t* cls, int32_t& ncls,
+                        int32_t* labels, int32_t* d, ThrPack& tp, int& nkeys);
+
 // Exclusive prefix sum of int32 counts in one workgroup of 1024 threads (set-up sizes).
 // out[m] = total.
 __global__ void __launch_bounds__(1024) k_scan_small(const int32_t* in, int32_t* out, int m) {
@@ -285,46 +290,13 @@ __global__ void __launch_bounds__(1024) k_scan_small(const int32_t* in, int32_t*
   if (t == 1023) out[m] = part[1023];
 }
 
-extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
-                           const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
-                           int32_t* labels, int32_t* d, void* stream) {
-  psl_alloc_stream = static_cast<hipStream_t>(stream);
-  if (const int grc = grid_check(g)) return grc;
-  if (!nsub || !labels || !d) return PSL_EINVAL;
-  if (!cls && !K) return PSL_EINVAL;
-  const int nx = g->nx, ny = g->ny, nz = g->nz;
-  const int ext[3] = {nx, ny, nz};
-  for (int a = 0; a < 3; ++a)
-    if (nsub[a] < 1 || nsub[a] > ext[a]) return PSL_EINVAL;
-  ThrPack tp{};
-  if (cls) {
-    if (ncls < 1 || ncls > PSL_MAX_THRESHOLDS + 1) return PSL_EINVAL;
-    tp.nthr = 0;
-  } else {
-    if (nthr < 0 || nthr > PSL_MAX_THRESHOLDS || (nthr > 0 && !thr)) return PSL_EINVAL;
-    for (int t = 0; t < nthr; ++t) {
-      if (!std::isfinite(thr[t])) return PSL_EINVAL;
-      if (t > 0 && !(thr[t] > thr[t - 1])) return PSL_EINVAL;
-      tp.t[t] = thr[t];
-    }
-    tp.nthr = nthr;
-    ncls = nthr + 1;
-  }
-  const int64_t nkeys64 = int64_t(nsub[0]) * nsub[1] * nsub[2] * ncls;
-  if (nkeys64 > (int64_t(1) << 26)) return PSL_ENOTSUP;
-  const int nkeys = int(nkeys64);
+// The labelling proper: key presence flags, their exclusive scan (the rank of each key
+// among the present ones) and the labels, on scratch the caller provides: present[nkeys],
+// rank[nkeys + 1], bad[1]. present and bad are cleared here (fill kernels).
+static int build_z_on(int nx, int ny, int nz, const int32_t nsub[3], int ncls, const double* K,
+                      const int32_t* cls, const ThrPack& tp, int nkeys, int32_t* present,
+                      int32_t* rank, int32_t* bad, int32_t* labels, int32_t* d, hipStream_t st) {
   const int n = nx * ny * nz;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  int32_t *present = nullptr, *rank = nullptr, *bad = nullptr;
-  int rc = psl_internal_alloc((void**)&present, sizeof(int32_t) * nkeys);
-  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&rank, sizeof(int32_t) * (nkeys + 1));
-  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bad, sizeof(int32_t));
-  if (rc != PSL_OK) {
-    psl_internal_free(present);
-    psl_internal_free(rank);
-    psl_internal_free(bad);
-    return rc;
-  }
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(nkeys)), dim3(kBlock), 0, st, present, 0,
                      int64_t(nkeys));
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, bad, 0, int64_t(1));
@@ -337,13 +309,72 @@ extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsu
   hipError_t e1 = hipMemcpyAsync(&h[0], rank + nkeys, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipMemcpyAsync(&h[1], bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
   hipError_t e3 = hipStreamSynchronize(st);
-  psl_internal_free(present);
-  psl_internal_free(rank);
-  psl_internal_free(bad);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return PSL_EHIP;
   if (h[1]) return PSL_EINVAL;  // a manual class outside [0, ncls)
   *d = h[0];
   return PSL_OK;
+}
+
+extern "C" int psl_build_Z(const psl_grid* g, const double* K, const int32_t nsub[3],
+                           const double* thr, int32_t nthr, const int32_t* cls, int32_t ncls,
+                           int32_t* labels, int32_t* d, void* stream) {
+  psl_alloc_stream = static_cast<hipStream_t>(stream);
+  ThrPack tp;
+  int nkeys = 0;
+  int rc = build_z_args(g, K, nsub, thr, nthr, cls, ncls, labels, d, tp, nkeys);
+  if (rc != PSL_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t *present = nullptr, *rank = nullptr, *bad = nullptr;
+  rc = psl_internal_alloc((void**)&present, sizeof(int32_t) * nkeys);
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&rank, sizeof(int32_t) * (nkeys + 1));
+  if (rc == PSL_OK) rc = psl_internal_alloc((void**)&bad, sizeof(int32_t));
+  if (rc == PSL_OK)
+    rc = build_z_on(g->nx, g->ny, g->nz, nsub, ncls, K, cls, tp, nkeys, present, rank, bad, labels,
+                    d, st);
+  psl_internal_free(present);
+  psl_internal_free(rank);
+  psl_internal_free(bad);
+  return rc;
+}
+
+// Scratch of psl_build_Z_noalloc: present[max keys], rank[max keys + 1], bad[1], in a
+// file-scope device array that every call on a device shares. Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device (kept per
+// device): the array's name in host code is a host-side stand-in, not a device address.
+constexpr int kNoAllocWords = 2 * PSL_NOALLOC_MAX_KEYS + 2;
+static __device__ __align__(256) int32_t scratch[kNoAllocWords];
+
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_ptr[64] = {nullptr};
+
+static int noalloc_scratch(int32_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PSL_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PSL_EHIP;
+    g_scratch_ptr[dev] = static_cast<int32_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PSL_OK;
+}
+
+extern "C" int psl_build_Z_noalloc(const psl_grid* g, const double* K, const int32_t nsub[3],
+                                   const double* thr, int32_t nthr, const int32_t* cls,
+                                   int32_t ncls, int32_t* labels, int32_t* d, void* stream) {
+  ThrPack tp;
+  int nkeys = 0;
+  int rc = build_z_args(g, K, nsub, thr, nthr, cls, ncls, labels, d, tp, nkeys);
+  if (rc != PSL_OK) return rc;
+  if (nkeys > PSL_NOALLOC_MAX_KEYS) return PSL_ENOTSUP;
+  int32_t* base = nullptr;
+  if ((rc = noalloc_scratch(&base)) != PSL_OK) return rc;
+  int32_t* present = base;
+  int32_t* rank = base + PSL_NOALLOC_MAX_KEYS;
+  int32_t* bad = base + 2 * PSL_NOALLOC_MAX_KEYS + 1;
+  return build_z_on(g->nx, g->ny, g->nz, nsub, ncls, K, cls, tp, nkeys, present, rank, bad,
+                    labels, d, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -480,7 +511,7 @@ __global__ void k_cc_label(int n, const int32_t* parent, const int32_t* rank, in
   labels[c] = rank[parent[c]];
 }
 
-// argument checks shared by psl_build_Z and psl_build_Z_cc
+// argument checks shared by the label builders
 static int build_z_args(const psl_grid* g, const double* K, const int32_t nsub[3],
                         const double* thr, int32_t nthr, const int32_t* cls, int32_t& ncls,
                         int32_t* labels, int32_t* d, ThrPack& tp, int& nkeys) {

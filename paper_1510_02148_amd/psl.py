@@ -97,6 +97,9 @@ _build_z = _sig("psl_build_Z", ctypes.c_int,
                 [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
 _build_z_cc = _sig("psl_build_Z_cc", ctypes.c_int,
                    [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P, _P])
+_build_z_noalloc = _sig("psl_build_Z_noalloc", ctypes.c_int,
+                        [ctypes.POINTER(psl_grid), _P, _I32P, _DP, _I32, _P, _I32, _P, _I32P,
+                         _P])
 _setup_e = _sig("psl_setup_E", ctypes.c_int,
                 [ctypes.POINTER(_P), ctypes.POINTER(psl_grid), _P, _P, _P, _P, _I32, _I32P, _P])
 _setup_e_ex = _sig("psl_setup_E_ex", ctypes.c_int,
@@ -124,7 +127,7 @@ _default_poly_opts = _sig("psl_default_poly_opts", None, [ctypes.POINTER(psl_pol
 _solve_poly = _sig("psl_solve_poly", ctypes.c_int,
                    [_P, _P, _P, ctypes.POINTER(psl_poly_opts), ctypes.POINTER(psl_solve_stats), _P])
 
-EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_setup_E", "psl_setup_E_ex",
+EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_build_Z_noalloc", "psl_setup_E", "psl_setup_E_ex",
             "psl_default_setup_opts", "psl_solve",
             "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
@@ -192,9 +195,14 @@ def psl_assemble_tpfa(grid, K: torch.Tensor, dirichlet_mask: int,
 
 
 def psl_build_Z(grid, K: Optional[torch.Tensor], nsub, thr=None, cls: Optional[torch.Tensor] = None,
-                ncls: int = 0, labels: Optional[torch.Tensor] = None, components: bool = False):
+                ncls: int = 0, labels: Optional[torch.Tensor] = None, components: bool = False,
+                noalloc: bool = False):
     """Subdomain-levelset labels (int32 device tensor) and d; components=True splits every
-    region into its connected components (psl_build_Z_cc)."""
+    region into its connected components (psl_build_Z_cc); noalloc=True calls
+    psl_build_Z_noalloc (no device allocation inside the library; pass `labels` to keep the
+    call free of allocation on the Python side too)."""
+    if components and noalloc:
+        raise ValueError("psl_build_Z: noalloc has no connected-components form")
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
     dev = (K if K is not None else cls).device
     labels = torch.empty(n, dtype=torch.int32, device=dev) if labels is None else labels
@@ -205,7 +213,9 @@ def psl_build_Z(grid, K: Optional[torch.Tensor], nsub, thr=None, cls: Optional[t
     d = ctypes.c_int32(0)
     kp = _dev(K, torch.float64, n, "K") if K is not None else ctypes.c_void_p(0)
     cp = _dev(cls, torch.int32, n, "cls") if cls is not None else ctypes.c_void_p(0)
-    fn, name = (_build_z_cc, "psl_build_Z_cc") if components else (_build_z, "psl_build_Z")
+    fn, name = ((_build_z_cc, "psl_build_Z_cc") if components else
+                (_build_z_noalloc, "psl_build_Z_noalloc") if noalloc else
+                (_build_z, "psl_build_Z"))
     _check(fn(ctypes.byref(g), kp, ns, th, len(thr), cp, int(ncls),
               _dev(labels, torch.int32, n, "labels"), ctypes.byref(d), _stream()), name)
     return labels, int(d.value)
