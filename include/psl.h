@@ -412,6 +412,28 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
 int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, void* stream);
 
 /*
+ * psl_profile_kernel -- time one kernel of the CG iteration inside the following psl_solve
+ * calls on this context: an event is recorded on the solve's stream before and after each
+ * launch of `kernel` (PSL_KERNEL_STENCIL, PSL_KERNEL_COARSE (the label sum and the coarse
+ * product together) or PSL_KERNEL_UPDATE) in the precision of `mode` (PSL_MIXED: the
+ * float32 launches of a mixed solve), for up to `max_launches` launches (1 .. 2^20) counted
+ * from this call. While armed, the solves launch their iterations directly (no replayed
+ * graphs), so every launch is the solve's own; launches enqueued past convergence return
+ * at once and show as short durations. kernel < 0 disarms. The events are created here
+ * and kept by the context. Errors: PSL_EINVAL, PSL_ENOMEM, PSL_EHIP.
+ */
+int psl_profile_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t max_launches);
+
+/*
+ * psl_profile_read -- synchronise `stream` and return the number of launches timed since
+ * psl_profile_kernel (or the last read) in *count and the first min(count, max) durations
+ * in microseconds (host out, launch order) in durations_us; then restart the count.
+ * Errors: PSL_EINVAL, PSL_EHIP.
+ */
+int psl_profile_read(psl_ctx* ctx, int32_t* count, float* durations_us, int32_t max,
+                     void* stream);
+
+/*
  * psl_bench_copy -- device-to-device streaming copy of `bytes` (multiple of 16, both
  * pointers 16-byte aligned) with a plain load/store kernel, one 16-byte load and store per
  * thread: the reference for achievable bandwidth and for calibrating hardware byte

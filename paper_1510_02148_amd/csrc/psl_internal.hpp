@@ -147,6 +147,13 @@ struct psl_ctx {
   char* arena = nullptr;
   size_t arena_left = 0;
   int last_iters64[8] = {0}, last_iters32[8] = {0};  // inner iterations per refinement step
+  // per-launch timing of one CG kernel inside the solves (psl_profile_kernel): events
+  // recorded on the solve's stream before and after each launch of that kernel in that
+  // precision, up to prof_cap launches
+  int prof_kernel = -1;               // PSL_KERNEL_* id, -1 when off
+  int prof_mode = 0;                  // PSL_FP64 or PSL_MIXED (float32 launches)
+  int prof_cap = 0, prof_count = 0;
+  hipEvent_t* prof_ev = nullptr;      // [2 * prof_cap]
 };
 
 #define PSL_HIP(call)                                                              \

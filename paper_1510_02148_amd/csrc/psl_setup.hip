@@ -1442,6 +1442,10 @@ extern "C" void psl_destroy(psl_ctx* c) {
   if (c->gm_host) (void)hipHostFree(c->gm_host);
   for (hipEvent_t ev : c->gm_ev)
     if (ev) (void)hipEventDestroy(ev);
+  if (c->prof_ev) {
+    for (int i = 0; i < 2 * c->prof_cap; ++i) (void)hipEventDestroy(c->prof_ev[i]);
+    delete[] c->prof_ev;
+  }
   (void)hipSetDevice(cur);
   delete c;
 }

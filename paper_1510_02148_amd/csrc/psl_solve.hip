@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <type_traits>
 
 #include "psl_internal.hpp"
@@ -423,40 +424,78 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other)
-// (v_other = 0 across an outer face; 0 on cells without a cut face). Two coarse vectors
-// at once: corr1 from e1, corr2 from e2 (skipped when e2 is null). A wave with skip set
-// does no work but takes both barriers (it only publishes a stop decision).
-template <typename CT, typename ST>
+// (v_other = 0 across an outer face; 0 on cells without a cut face), for one coarse vector
+// (e1 -> corr1) or two at once (e2 -> corr2; skipped when e2 is null). The tile's faces are
+// listed by cell (bit 31 of az_cell marks the first face of a cell). They are taken in
+// rounds of kFaceRound: each face's term is formed by its own thread, with every load of
+// the round in flight together, and staged in LDS; then the thread holding the first face
+// of a cell (or the round's first entry, the rest of a cell begun in the previous round)
+// adds that cell's terms in list order. The sum order is the list order, whatever the
+// round size. A wave with skip set does no work but takes every barrier (it only
+// publishes a stop decision). Ends with a barrier.
+constexpr int kFaceRound = 2 * kBlock;
+
+// face transmissibility arrays of either precision, for tile_correction
+__device__ inline const float* az32(const float* p) { return p; }
+__device__ inline const float* az32(const double*) { return nullptr; }
+__device__ inline const double* az64(const float*) { return nullptr; }
+__device__ inline const double* az64(const double* p) { return p; }
+
+template <bool TWO>
 __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_ptr,
                                        const int32_t* az_cell, const int32_t* az_lab,
-                                       const int32_t* az_oth, const CT* az_t, const double* e1,
-                                       const double* e2, ST* corr1, ST* corr2,
-                                       bool skip = false) {
-  for (int j = threadIdx.x; j < T.ncell && !skip; j += kBlock) {
-    corr1[j] = ST(0);
-    if (e2) corr2[j] = ST(0);
-  }
-  __syncthreads();
+                                       const int32_t* az_oth, const float* az_t32,
+                                       const double* az_t64, const double* e1, const double* e2,
+                                       double* corr1, double* corr2, bool skip) {
+  __shared__ double term1[kFaceRound];
+  __shared__ double term2[TWO ? kFaceRound : 1];
+  __shared__ int32_t cellw[kFaceRound];
   const int a = az_ptr[t], b = skip ? a : az_ptr[t + 1];
-  for (int k = a + threadIdx.x; k < b; k += kBlock) {
-    const int32_t cw = az_cell[k];
-    if (cw >= 0) continue;  // not the first face of its cell
-    const int ls = az_lab[k];
-    const double vs1 = e1[ls];
-    const double vs2 = e2 ? e2[ls] : 0.0;
-    double a1 = 0.0, a2 = 0.0;
-    int m = k;
-    do {
-      const int lo = az_oth[m];
-      const double tf = double(az_t[m]);
-      a1 += tf * (vs1 - (lo < 0 ? 0.0 : e1[lo]));
-      if (e2) a2 += tf * (vs2 - (lo < 0 ? 0.0 : e2[lo]));
-      ++m;
-    } while (m < b && az_cell[m] >= 0);
-    corr1[cw & 0x7fffffff] = ST(a1);
-    if (e2) corr2[cw & 0x7fffffff] = ST(a2);
+  for (int j = threadIdx.x; j < T.ncell && !skip; j += kBlock) {
+    corr1[j] = 0.0;
+    if (TWO) corr2[j] = 0.0;
   }
-  __syncthreads();
+  for (int base = a; base < b || base == a; base += kFaceRound) {
+    // terms of this round's faces
+#pragma unroll
+    for (int r = 0; r < kFaceRound / kBlock; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      const int k = base + i;
+      if (k < b) {
+        const int32_t cw = az_cell[k];
+        const int ls = az_lab[k];
+        const int lo = az_oth[k];
+        const double tf = az_t32 ? double(az_t32[k]) : az_t64[k];
+        cellw[i] = cw;
+        term1[i] = tf * (e1[ls] - (lo < 0 ? 0.0 : e1[lo]));
+        if (TWO) term2[i] = tf * (e2[ls] - (lo < 0 ? 0.0 : e2[lo]));
+      }
+    }
+    __syncthreads();
+    // per cell, in list order
+    const int cnt = min(kFaceRound, b - base);
+#pragma unroll
+    for (int r = 0; r < kFaceRound / kBlock; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      if (i < cnt) {
+        const int32_t cw = cellw[i];
+        if (cw < 0 || i == 0) {
+          double s1 = term1[i], s2 = TWO ? term2[i] : 0.0;
+          int m = i + 1;
+          while (m < cnt && cellw[m] >= 0) {
+            s1 += term1[m];
+            if (TWO) s2 += term2[m];
+            ++m;
+          }
+          const int j = cw & 0x7fffffff;
+          corr1[j] += s1;
+          if (TWO) corr2[j] += s2;
+        }
+      }
+    }
+    __syncthreads();
+    if (b <= a) break;
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -481,8 +520,8 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
                                       Scalars* sc, int bench) {
   using psl::ld;
   using psl::st;
-  __shared__ R corr[kTileMax];            // A Z e, rounded to the working precision
-  __shared__ R corr2[RP ? kTileMax : 1];  // A Z er
+  __shared__ double corr[kTileMax];            // A Z e
+  __shared__ double corr2[RP ? kTileMax : 1];  // A Z er
   __shared__ double coef[3];              // alpha, beta, go (1) / stop (0)
   const bool stop = sc->done != 0;        // acted on once the cell loads are in flight
   const Tile T = load_tile(g.tiles, t);
@@ -576,8 +615,9 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
       coef[2] = go;
     }
   }
-  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e, RP ? er : nullptr, corr,
-                  corr2, stop);   // ends with a barrier, after which coef[] is visible
+  tile_correction<RP != 0>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
+                          er, corr, corr2, stop);   // ends with a barrier, after which
+                                                           // coef[] is visible
   if (coef[2] == 0.0) return;
   const R alpha = R(coef[0]), beta = R(coef[1]);
 #pragma unroll
@@ -585,11 +625,11 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
     if (cc[k] < 0) continue;
     const uint32_t c = uint32_t(cc[k]);
     const int j = threadIdx.x + k * kBlock;
-    const R w = vv[k] - corr[j];
+    const R w = vv[k] - R(corr[j]);
     const R qn = w + beta * qv[k];
     const R pn = uv[k] + beta * pv[k];
     R rn = rv[k] - alpha * qn;
-    if (RP) rn -= corr2[j];
+    if (RP) rn -= R(corr2[j]);
     st(q, c, qn);
     st(p, c, pn);
     st(x, c, xv[k] + alpha * pn);
@@ -768,8 +808,8 @@ __global__ void __launch_bounds__(kBlock)
                 const double* cpart, int G, double* upart, Scalars* sc, int bench) {
   using psl::ld;
   using psl::st;
-  __shared__ R corr[kTileMax];   // A Z e, rounded to the working precision
-  __shared__ double coef[2];     // alpha, go (1) / stop (0)
+  __shared__ double corr[kTileMax];   // A Z e
+  __shared__ double coef[2];          // alpha, go (1) / stop (0)
   __shared__ double lds[2 * kNW];
   const bool stop = sc->done != 0;   // acted on once the first tile's loads are in flight
   double acc[2] = {0.0, 0.0};
@@ -830,8 +870,8 @@ __global__ void __launch_bounds__(kBlock)
         coef[1] = go;
       }
     }
-    tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
-                    static_cast<const double*>(nullptr), corr, corr, stop);  // ends with a barrier
+    tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
+                           nullptr, corr, corr, stop);  // ends with a barrier
     if (coef[1] == 0.0) return;
     const R alpha = R(coef[0]);
 #pragma unroll
@@ -839,7 +879,7 @@ __global__ void __launch_bounds__(kBlock)
       if (cc[k] < 0) continue;
       const uint32_t c = uint32_t(cc[k]);
       const int j = threadIdx.x + k * kBlock;
-      const R w = qv[k] - corr[j];
+      const R w = qv[k] - R(corr[j]);
       const R rn = rv[k] - alpha * w;
       const R un = rn * dv[k];
       st(x, c, axpy(alpha, pv[k], xv[k]));
@@ -946,8 +986,8 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
-  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
-                  static_cast<const double*>(nullptr), corr, corr);
+  tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, nullptr, az_t, e, nullptr, corr,
+                         corr, false);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   double acc[1] = {0.0};
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
@@ -1332,12 +1372,34 @@ void enqueue_outer_step(psl_ctx* c, const double* b, double* x, hipStream_t st) 
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(kBlock), 0, st, red(c, 1), c->ntiles, &c->sc->rr);
 }
 
+// Launch timing for psl_profile_kernel: an event before and after each launch of the
+// armed kernel in the armed precision (no-ops otherwise).
+template <typename R>
+inline bool prof_on(const psl_ctx* c, int kernel) {
+  const int mode = std::is_same<R, float>::value ? PSL_MIXED : PSL_FP64;
+  return c->prof_kernel == kernel && c->prof_mode == mode && c->prof_count < c->prof_cap;
+}
+template <typename R>
+inline void prof_begin(psl_ctx* c, int kernel, hipStream_t st) {
+  if (prof_on<R>(c, kernel)) (void)hipEventRecord(c->prof_ev[2 * c->prof_count], st);
+}
+template <typename R>
+inline void prof_end(psl_ctx* c, int kernel, hipStream_t st) {
+  if (prof_on<R>(c, kernel)) (void)hipEventRecord(c->prof_ev[2 * c->prof_count++ + 1], st);
+}
+
 // one CG iteration of parity PAR (three launches)
 template <typename R, int RP, int PAR>
 void enqueue_iteration(psl_ctx* c, hipStream_t st) {
+  prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
   with_ns<CgStencilL<R, RP>::template F>(c->nslot_max, c, st);
+  prof_end<R>(c, PSL_KERNEL_STENCIL, st);
+  prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<RP, kCgQ>(c, 1, st);
+  prof_end<R>(c, PSL_KERNEL_COARSE, st);
+  prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<CgUpdateC<R, RP, PAR>::template F>(c->cpt, c, st, 0);
+  prof_end<R>(c, PSL_KERNEL_UPDATE, st);
 }
 
 // `count` iterations (even), alternating parity
@@ -1357,9 +1419,15 @@ void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
 // one two-reduction iteration of parity PAR (three launches)
 template <typename R, int PAR>
 void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
+  prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
   with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, 0);
+  prof_end<R>(c, PSL_KERNEL_STENCIL, st);
+  prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<0, 1>(c, 1, st);
+  prof_end<R>(c, PSL_KERNEL_COARSE, st);
+  prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<SdUpdateC<R, PAR>::template F>(c->cpt, c, st, 0);
+  prof_end<R>(c, PSL_KERNEL_UPDATE, st);
 }
 
 template <typename R>
@@ -1599,7 +1667,7 @@ extern "C" int psl_solve(psl_ctx* c, const double* b, double* x, const psl_solve
   // Replayed graphs pay off only when the iteration kernels are shorter than a launch;
   // above that size direct launches keep the queue ahead of the GPU just as well and save
   // capturing and instantiating a graph for every new context.
-  const int use_graph = c->n < kGraphMaxCells;
+  const int use_graph = c->n < kGraphMaxCells && c->prof_kernel < 0;   // events need launches
   const char* verbose_env = std::getenv("PSL_VERBOSE");
   const bool verbose = verbose_env && verbose_env[0] == '1';
   int mode = o.mode;
@@ -1815,6 +1883,55 @@ extern "C" int psl_bench_copy(const void* src, void* dst, int64_t bytes, void* s
   hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   PSL_HIP(hipGetLastError());
+  return PSL_OK;
+}
+
+extern "C" int psl_profile_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_t max_launches) {
+  if (!c) return PSL_EINVAL;
+  if (kernel < 0) {
+    c->prof_kernel = -1;
+    return PSL_OK;
+  }
+  if ((kernel != PSL_KERNEL_STENCIL && kernel != PSL_KERNEL_COARSE &&
+       kernel != PSL_KERNEL_UPDATE) ||
+      (mode != PSL_FP64 && mode != PSL_MIXED) || max_launches < 1 || max_launches > (1 << 20))
+    return PSL_EINVAL;
+  if (max_launches > c->prof_cap) {
+    hipEvent_t* ev = new (std::nothrow) hipEvent_t[2 * max_launches];
+    if (!ev) return PSL_ENOMEM;
+    int made = 0;
+    for (; made < 2 * max_launches; ++made)
+      if (hipEventCreate(&ev[made]) != hipSuccess) break;
+    if (made < 2 * max_launches) {
+      for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+      delete[] ev;
+      return PSL_EHIP;
+    }
+    if (c->prof_ev) {
+      for (int i = 0; i < 2 * c->prof_cap; ++i) (void)hipEventDestroy(c->prof_ev[i]);
+      delete[] c->prof_ev;
+    }
+    c->prof_ev = ev;
+    c->prof_cap = max_launches;
+  }
+  c->prof_kernel = kernel;
+  c->prof_mode = mode;
+  c->prof_count = 0;
+  return PSL_OK;
+}
+
+extern "C" int psl_profile_read(psl_ctx* c, int32_t* count, float* durations_us, int32_t max,
+                                void* stream) {
+  if (!c || !count || max < 0 || (max > 0 && !durations_us)) return PSL_EINVAL;
+  PSL_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  const int n = c->prof_kernel >= 0 ? c->prof_count : 0;
+  *count = n;
+  for (int i = 0; i < std::min(n, int(max)); ++i) {
+    float ms = 0.0f;
+    PSL_HIP(hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+    durations_us[i] = 1e3f * ms;
+  }
+  c->prof_count = 0;
   return PSL_OK;
 }
 
@@ -2354,20 +2471,20 @@ __global__ void __launch_bounds__(kBlock)
                 const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
                 const PcScalars* s, const R* __restrict__ p, const R* __restrict__ w,
                 R* __restrict__ x, R* __restrict__ r) {
-  __shared__ R corr[kTileMax];
+  __shared__ double corr[kTileMax];
   const double ad = s->alpha;
   if (ad == 0.0) return;
   const R a = R(ad);
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
-  tile_correction(T, t, az_ptr, az_cell, az_lab, az_oth, az_t, e,
-                  static_cast<const double*>(nullptr), corr, corr);
+  tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
+                         nullptr, corr, corr, false);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
     int ix, iy, iz;
     cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
     const int c = ix + g.nx * (iy + g.ny * iz);
-    const R wf = w[c] - corr[j];
+    const R wf = w[c] - R(corr[j]);
     x[c] += a * p[c];
     r[c] -= a * wf;
   }

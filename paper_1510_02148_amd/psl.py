@@ -118,6 +118,9 @@ _destroy = _sig("psl_destroy", None, [_P])
 _get_info = _sig("psl_get_info", ctypes.c_int, [_P, ctypes.POINTER(psl_ctx_info)])
 _bench_kernel = _sig("psl_bench_kernel", ctypes.c_int, [_P, _I32, _I32, _I32, _P])
 _bench_copy = _sig("psl_bench_copy", ctypes.c_int, [_P, _P, ctypes.c_int64, _P])
+_profile_kernel = _sig("psl_profile_kernel", ctypes.c_int, [_P, _I32, _I32, _I32])
+_profile_read = _sig("psl_profile_read", ctypes.c_int,
+                     [_P, _I32P, ctypes.POINTER(ctypes.c_float), _I32, _P])
 _status_str = _sig("psl_status_str", ctypes.c_char_p, [ctypes.c_int])
 _default_opts = _sig("psl_default_opts", None, [ctypes.POINTER(psl_solve_opts)])
 _default_gmres_opts = _sig("psl_default_gmres_opts", None, [ctypes.POINTER(psl_gmres_opts)])
@@ -132,6 +135,7 @@ EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_build_Z_n
             "psl_solve_batched", "psl_apply_A",
             "psl_deflate", "psl_get_coarse", "psl_destroy", "psl_status_str",
             "psl_default_opts", "psl_bench_kernel", "psl_bench_copy", "psl_get_info",
+            "psl_profile_kernel", "psl_profile_read",
             "psl_solve_gmres", "psl_default_gmres_opts", "psl_solve_poly",
             "psl_default_poly_opts")
 (KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL,
@@ -462,3 +466,20 @@ def psl_bench_copy(src: torch.Tensor, dst: torch.Tensor):
 
 def psl_destroy(ctx: Context):
     ctx.destroy()
+
+
+def psl_profile_kernel(ctx, kernel: int, mode: int, max_launches: int = 4096):
+    """Arm per-launch event timing of one CG kernel (KERNEL_STENCIL, KERNEL_COARSE,
+    KERNEL_UPDATE) in the precision of `mode` for the following solves; kernel < 0 disarms."""
+    _check(_profile_kernel(ctx.handle, int(kernel), int(mode), int(max_launches)),
+           "psl_profile_kernel")
+
+
+def psl_profile_read(ctx, max_launches: int = 4096):
+    """Durations (microseconds, launch order) of the launches timed since arming or the last
+    read, as a list of floats."""
+    n = ctypes.c_int32(0)
+    buf = (ctypes.c_float * max(1, int(max_launches)))()
+    _check(_profile_read(ctx.handle, ctypes.byref(n), buf, int(max_launches), _stream()),
+           "psl_profile_read")
+    return [float(buf[i]) for i in range(min(n.value, int(max_launches)))]
