@@ -177,22 +177,22 @@ def run_batched(args):
         return [pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), tile_cells=t)
                 for p, K, t in zip(probs, Ks, tl)]
 
-    def step(tl):
+    def step(tl, mode=psl.FP64):
         t0 = time.perf_counter()
         setups = setup_all(tl)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        xs, stats, rc = psl.psl_solve_batched([s.ctx for s in setups], bs)
+        xs, stats, rc = psl.psl_solve_batched([s.ctx for s in setups], bs, mode=mode)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return setups, xs, stats, rc, t1 - t0, t2 - t1
 
-    def leg(tl, label):
+    def leg(tl, label, mode=psl.FP64):
         for _ in range(args.warmup):
-            step(tl)
+            step(tl, mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rec = [step(tl) for _ in range(args.steps)]
+        rec = [step(tl, mode) for _ in range(args.steps)]
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
         setups, xs, stats, rc = rec[-1][:4]
@@ -217,6 +217,15 @@ def run_batched(args):
     seq_s = float(np.median(seq))
     log(f"sequential psl_solve: {seq_s * 1e3:.1f} ms")
     _, wall_def = leg([None] * len(probs), "batched, library-default tiles")
+    # the same batch in mixed precision (float32 refinement steps for all systems together)
+    rec_m, wall_m = leg(tiles, "batched mixed, tuned tiles", mode=psl.MIXED)
+    stats_m, rc_m = rec_m[-1][2], rec_m[-1][3]
+    mixed_leg = {"s_per_step": round(wall_m, 6),
+                 "solve_s": float(np.median([r[5] for r in rec_m])),
+                 "converged": bool(rc_m == 0 and all(st["relres_true"] <= 1e-8 for st in stats_m)),
+                 "iterations_mean": round(float(np.mean([st["iters"] for st in stats_m])), 1),
+                 "fell_back": int(sum(st["fell_back"] for st in stats_m)),
+                 "speedup_vs_fp64_batched": round(wall / wall_m, 3)}
     # effective bandwidth of the whole batched solve (stencil + coarse + update per iteration)
     total_bytes = 0.0
     for p, s, st in zip(probs, setups, stats):
@@ -256,6 +265,7 @@ def run_batched(args):
         "setup_s": setup_s, "solve_s": solve_s, "sequential_solve_s": seq_s,
         "speedup_vs_sequential": round(seq_s / solve_s, 3),
         "default_tiles_s_per_step": round(wall_def, 6),
+        "mixed": mixed_leg,
         "tiles": {str(k): v["tile_cells"] for k, v in sorted(table.items())},
         "roofline": {"bound": "hbm", "kernel": "batched CG (stencil + coarse + update)",
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -398,6 +408,8 @@ def main():
     ap.add_argument("--degree", type=int, default=3, help="Chebyshev steps (--solver poly)")
     ap.add_argument("--ratio", type=float, default=30.0,
                     help="Chebyshev interval [2 / ratio, 2] (--solver poly)")
+    ap.add_argument("--tiles", default=None,
+                    help="tile sizes 'f64,f32' instead of the tuned ones (tuning runs)")
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -438,6 +450,8 @@ def main():
             autotune.save_table(entries)
             t = autotune.tiles_for([prob.grid], entries, precision=prec, kind="single")[0]
         tiles[prec] = t
+    if args.tiles:
+        tiles["f64"], tiles["f32"] = (int(v) for v in args.tiles.split(","))
     log(f"tile sizes: float64 {tiles['f64']}, mixed {tiles['f32']}")
     K = torch.as_tensor(prob.K, dtype=torch.float64, device=dev)
     b = torch.as_tensor(prob.q, dtype=torch.float64, device=dev)

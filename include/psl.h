@@ -284,7 +284,14 @@ typedef struct {
   int32_t tile_cells;   /* cells per work tile, 64..2048 (one workgroup each; tiles never
                            straddle a subdomain); 0 = the library's choice (1024, halved
                            down to 256 while the grid would give fewer than 2048 tiles) */
-  int32_t reserved[7];  /* must be 0 */
+  int32_t finish_kernels; /* 1: every CG iteration takes its step decisions (inner products
+                           summed from the workgroup partials, stop test, step coefficients)
+                           in small one-workgroup kernels, so the pass kernels only read
+                           them and the update pass runs one workgroup per tile; -1: each
+                           pass workgroup sums the partials itself; 0 (default): 1 for
+                           grids of 2^21 cells or more, -1 below (where the extra launches
+                           cost more than the repeated sums) */
+  int32_t reserved[6];  /* must be 0 */
 } psl_setup_opts;
 
 /* Fill `o` with the defaults (all zero). */
@@ -339,19 +346,27 @@ int psl_solve(psl_ctx* ctx, const double* b, double* x, const psl_solve_opts* o,
  * psl_solve_batched -- solve nsys independent systems A_i x_i = b_i, each set up by its
  * own psl_setup_E, together: every float64 CG launch covers the work tiles of all systems
  * through a (system, tile) work list, while each system keeps its own scalars, tolerance
- * test and stop flag (a converged system's workgroups return at once). The per-system
- * arithmetic is that of psl_solve in PSL_FP64, so each x_i is the one psl_solve returns
- * for that system alone. The launch plan (argument table, work lists, captured graph of
- * iteration chunks) is cached on ctxs[0] while the same contexts are passed in the same
- * order.
+ * test and stop flag (a converged system's workgroups return at once). In PSL_FP64 the
+ * per-system arithmetic is that of psl_solve in PSL_FP64, so each x_i is the one psl_solve
+ * returns for that system alone. In PSL_MIXED the systems first take float32 refinement
+ * steps together: each step is a fresh float32 two-reduction DEF1-PCG on the projected
+ * float64 residual (every pass one launch for all systems, the step decisions of each
+ * system in small per-system kernels) until that residual has dropped by tau_inner,
+ * followed by x += ||r|| xhat and the float64 refinement step; a system leaves this phase
+ * when it converges, reaches mixed_floor, or a step fails to halve its float64 residual,
+ * and the float64 batched loop finishes it (st[i].fell_back = 1). This schedule restarts
+ * the float32 direction at every step, unlike psl_solve's PSL_MIXED, so its iterates are
+ * its own (each x_i meets the same tolerance). The launch plan (argument table, work
+ * lists, captured graph of iteration chunks) is cached on ctxs[0] while the same contexts
+ * are passed in the same order.
  *   ctxs  host[nsys]: distinct contexts on the current device.
  *   b, x  host[nsys] arrays of device pointers, each dev[n_i] float64 (as in psl_solve).
  *   o     options as in psl_solve (NULL = defaults); use_x0 applies to every system.
  *   st    host out[nsys] statistics (may be NULL); st[i].status is system i's result.
  * A system that stalls or breaks down is finished by psl_solve from its current x.
  * Returns PSL_OK if every system converged, otherwise the first failing system's code.
- * Errors: PSL_EINVAL (null pointers, nsys < 1, a context twice, another device),
- * PSL_ENOTSUP (PSL_MIXED, or a context whose coarse solve needs the separate label
+ * Errors: PSL_EINVAL (null pointers, nsys < 1, a context twice, another device, options
+ * out of range), PSL_ENOTSUP (a context whose coarse solve needs the separate label
  * reduction: d > 4096 or very many label partials).
  */
 int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const double* const* b,

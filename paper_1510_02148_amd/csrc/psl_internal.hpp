@@ -37,6 +37,7 @@ struct Scalars {
   double bnorm2;
   double delta;      // (p, P1 A p) of the last step (diagnostic)
   double ztr2;       // ||Z^T r||^2 of the final float64 residual (diagnostic)
+  double beta[2];    // direction coefficient of the step (finish kernels)
   int32_t cnt[2];    // iterations done
   int32_t done;      // inner loop finished (converged or failed)
   int32_t iters;     // inner iterations done in this inner solve
@@ -81,6 +82,8 @@ struct psl_ctx {
   int nslot_max = 0;
   int tile_max = 0;                   // cells per tile (<= 2048)
   int cpt = 1;                        // cells per thread = ceil(tile_max / kBlock)
+  int pre = 0;                        // CG step decisions in one-workgroup finish kernels
+                                      // (the pass kernels read the coefficients)
   int nsub[3] = {1, 1, 1};
   // operator data (owned copies)
   double *Tx = nullptr, *Ty = nullptr, *Tz = nullptr;

@@ -1492,6 +1492,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   psl_alloc_stream = static_cast<hipStream_t>(stream);
   if (so) {
     if (so->tile_cells != 0 && (so->tile_cells < 64 || so->tile_cells > 2048)) return PSL_EINVAL;
+    if (so->finish_kernels < -1 || so->finish_kernels > 1) return PSL_EINVAL;
     for (int32_t r : so->reserved)
       if (r != 0) return PSL_EINVAL;
   }
@@ -1585,6 +1586,9 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   int tile_max = 1024;
   while (tile_max > 256 && int64_t(n) / tile_max < 2048) tile_max /= 2;
   if (so && so->tile_cells) tile_max = so->tile_cells;
+  // step decisions in finish kernels on large grids (the pass kernels then skip the
+  // repeated partial sums; below this size the extra launches cost more)
+  c->pre = (so && so->finish_kernels) ? (so->finish_kernels > 0) : (int64_t(n) >= (int64_t(1) << 21));
   for (;;) {
     c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
     c->ntiles = int(c->h_tiles.size());

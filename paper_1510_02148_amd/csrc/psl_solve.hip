@@ -441,31 +441,73 @@ __device__ inline const float* az32(const double*) { return nullptr; }
 __device__ inline const double* az64(const float*) { return nullptr; }
 __device__ inline const double* az64(const double* p) { return p; }
 
+// The first round of a tile's cut faces, loaded into registers before the cell loads of
+// the pass that uses it (tile_correction needs these before its coarse-vector gathers;
+// issued first, they arrive while the cell loads are still in flight).
+constexpr int kFacePer = kFaceRound / kBlock;
+struct FaceRound {
+  int a, b;                  // the tile's face range
+  int32_t cw[kFacePer], ls[kFacePer], lo[kFacePer];
+  double tf[kFacePer];
+};
+
+__device__ inline int ld_uniform(const int32_t* p) {
+  using CI = const __attribute__((address_space(4))) int32_t;
+  return *(const CI*)p;   // read-only during the launch: one scalar load
+}
+
+__device__ inline void face_prefetch(int t, const int32_t* az_ptr, const int32_t* az_cell,
+                                     const int32_t* az_lab, const int32_t* az_oth,
+                                     const float* az_t32, const double* az_t64, bool skip,
+                                     FaceRound& f) {
+  f.a = ld_uniform(az_ptr + t);
+  f.b = skip ? f.a : ld_uniform(az_ptr + t + 1);
+#pragma unroll
+  for (int r = 0; r < kFacePer; ++r) {
+    const int k = f.a + int(threadIdx.x) + r * kBlock;
+    if (k < f.b) {
+      f.cw[r] = az_cell[k];
+      f.ls[r] = az_lab[k];
+      f.lo[r] = az_oth[k];
+      f.tf[r] = az_t32 ? double(az_t32[k]) : az_t64[k];
+    }
+  }
+}
+
 template <bool TWO>
-__device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_ptr,
-                                       const int32_t* az_cell, const int32_t* az_lab,
-                                       const int32_t* az_oth, const float* az_t32,
-                                       const double* az_t64, const double* e1, const double* e2,
-                                       double* corr1, double* corr2, bool skip) {
+__device__ inline void tile_correction(const Tile& T, const FaceRound& f, const int32_t* az_cell,
+                                       const int32_t* az_lab, const int32_t* az_oth,
+                                       const float* az_t32, const double* az_t64,
+                                       const double* e1, const double* e2, double* corr1,
+                                       double* corr2, bool skip) {
   __shared__ double term1[kFaceRound];
   __shared__ double term2[TWO ? kFaceRound : 1];
   __shared__ int32_t cellw[kFaceRound];
-  const int a = az_ptr[t], b = skip ? a : az_ptr[t + 1];
+  const int a = f.a, b = f.b;
   for (int j = threadIdx.x; j < T.ncell && !skip; j += kBlock) {
     corr1[j] = 0.0;
     if (TWO) corr2[j] = 0.0;
   }
   for (int base = a; base < b || base == a; base += kFaceRound) {
-    // terms of this round's faces
+    // terms of this round's faces (the first round's faces are already in registers)
 #pragma unroll
-    for (int r = 0; r < kFaceRound / kBlock; ++r) {
+    for (int r = 0; r < kFacePer; ++r) {
       const int i = threadIdx.x + r * kBlock;
       const int k = base + i;
       if (k < b) {
-        const int32_t cw = az_cell[k];
-        const int ls = az_lab[k];
-        const int lo = az_oth[k];
-        const double tf = az_t32 ? double(az_t32[k]) : az_t64[k];
+        int32_t cw, ls, lo;
+        double tf;
+        if (base == a) {
+          cw = f.cw[r];
+          ls = f.ls[r];
+          lo = f.lo[r];
+          tf = f.tf[r];
+        } else {
+          cw = az_cell[k];
+          ls = az_lab[k];
+          lo = az_oth[k];
+          tf = az_t32 ? double(az_t32[k]) : az_t64[k];
+        }
         cellw[i] = cw;
         term1[i] = tf * (e1[ls] - (lo < 0 ? 0.0 : e1[lo]));
         if (TWO) term2[i] = tf * (e2[ls] - (lo < 0 ? 0.0 : e2[lo]));
@@ -475,7 +517,7 @@ __device__ inline void tile_correction(const Tile& T, int t, const int32_t* az_p
     // per cell, in list order
     const int cnt = min(kFaceRound, b - base);
 #pragma unroll
-    for (int r = 0; r < kFaceRound / kBlock; ++r) {
+    for (int r = 0; r < kFacePer; ++r) {
       const int i = threadIdx.x + r * kBlock;
       if (i < cnt) {
         const int32_t cw = cellw[i];
@@ -517,7 +559,7 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
                                       const int32_t* az_oth, const R* az_t,
                                       const double* __restrict__ e,
                                       const double* __restrict__ er, const double* cpart, int G,
-                                      Scalars* sc, int bench) {
+                                      Scalars* sc, int bench, int pre) {
   using psl::ld;
   using psl::st;
   __shared__ double corr[kTileMax];            // A Z e
@@ -526,7 +568,9 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
   const bool stop = sc->done != 0;        // acted on once the cell loads are in flight
   const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
-  // issue the cell loads first so their latency overlaps the reductions below
+  // the cut faces first, then the cell loads: their latency overlaps the reductions below
+  FaceRound fr;
+  face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), stop, fr);
   int cc[CPT];
   R vv[CPT], rv[CPT], uv[CPT], pv[CPT], qv[CPT], xv[CPT], dv[CPT];
 #pragma unroll
@@ -551,8 +595,15 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
   // which every workgroup reaches from the same partials, but the waves of a workgroup
   // read it at different times: a wave that sees it leaves, except wave 0, which stays to
   // publish the decision the others read (otherwise they would read a stale coef[]).
-  if (stop && threadIdx.x >= psl::kWave) return;
-  if (threadIdx.x < psl::kWave) {
+  if (stop && (pre || threadIdx.x >= psl::kWave)) return;
+  if (pre) {
+    // the step was decided by the finish kernel before this launch
+    if (threadIdx.x == 0) {
+      coef[0] = bench ? 1e-3 : sc->alpha[PAR];
+      coef[1] = bench ? 0.5 : sc->beta[PAR];
+      coef[2] = 1.0;
+    }
+  } else if (threadIdx.x < psl::kWave) {
     // one wave reduces the coarse partials (fixed order) and decides the step
     double alpha_d = 1e-3, beta_d = 0.5, go = stop ? 0.0 : 1.0;
     if (!bench && !stop) {
@@ -615,9 +666,8 @@ __device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __
       coef[2] = go;
     }
   }
-  tile_correction<RP != 0>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
-                          er, corr, corr2, stop);   // ends with a barrier, after which
-                                                           // coef[] is visible
+  tile_correction<RP != 0>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, er, corr,
+                          corr2, stop);   // ends with a barrier, after which coef[] is visible
   if (coef[2] == 0.0) return;
   const R alpha = R(coef[0]), beta = R(coef[1]);
 #pragma unroll
@@ -645,10 +695,61 @@ __global__ void __launch_bounds__(kBlock)
                 const R* __restrict__ invd, const int32_t* az_ptr, const int32_t* az_cell,
                 const int32_t* az_lab, const int32_t* az_oth, const R* az_t,
                 const double* __restrict__ e, const double* __restrict__ er,
-                const double* cpart, int G, Scalars* sc, int bench) {
+                const double* cpart, int G, Scalars* sc, int bench, int pre) {
   cg_update_tile<R, RP, CPT, PAR>(tile_of_block(blockIdx.x, g.ntiles), blockIdx.x == 0, g, v, r,
                                   u, p, q, x, invd, az_ptr, az_cell, az_lab, az_oth, az_t, e, er,
-                                  cpart, G, sc, bench);
+                                  cpart, G, sc, bench, pre);
+}
+
+// Step decision of the single-reduction iteration of parity PAR in one wave (the same sums
+// and tests the update workgroups make themselves without it): gamma, delta and ||r||^2
+// from the coarse partials, stop (converged, budget, non-finite) or breakdown, else
+// alpha and beta into the PAR slots for the update pass.
+template <int PAR>
+__global__ void __launch_bounds__(psl::kWave) k_cg_finish(const double* cpart, int G, Scalars* sc) {
+  if (sc->done) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = threadIdx.x; i < G; i += psl::kWave) {
+    s0 += cpart[i];           // s^T e
+    s1 += cpart[G + i];       // (v, u)
+    s2 += cpart[2 * G + i];   // (r, u)
+    s3 += cpart[3 * G + i];   // (r, r)
+  }
+  s0 = psl::wave_sum(s0);
+  s1 = psl::wave_sum(s1);
+  s2 = psl::wave_sum(s2);
+  s3 = psl::wave_sum(s3);
+  if (threadIdx.x != 0) return;
+  const double gamma = s2, delta = s1 - s0, rr = s3;
+  const double gprev = sc->gamma[PAR ^ 1], aprev = sc->alpha[PAR ^ 1];
+  const int cnt = sc->cnt[PAR ^ 1];
+  if (!(rr < INFINITY) || !(fabs(gamma) < INFINITY) || !(fabs(delta) < INFINITY)) {
+    sc->status = PSL_ENONFINITE;
+    sc->done = 1;
+    sc->iters = cnt;
+  } else if (rr <= sc->goal2 || cnt >= sc->maxit) {
+    sc->rr = rr;
+    sc->done = 1;
+    sc->iters = cnt;
+  } else {
+    const double beta_d = gamma / gprev;                      // gprev = +inf before the first step
+    const double den = delta - beta_d * gamma / aprev;
+    if (!(den > 0.0)) {
+      sc->status = PSL_EBREAKDOWN;
+      sc->done = 1;
+      sc->iters = cnt;
+      sc->rr = rr;
+    } else {
+      const double alpha_d = gamma / den;
+      sc->gamma[PAR] = gamma;
+      sc->alpha[PAR] = alpha_d;
+      sc->beta[PAR] = beta_d;
+      sc->cnt[PAR] = cnt + 1;
+      sc->iters = cnt + 1;
+      sc->rr = rr;
+      sc->delta = den;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -673,19 +774,19 @@ __device__ inline R axpy(R a, R x, R y) {   // a x + y, contracted the same way 
 }
 
 template <typename R, int NS, int CPT, int PAR>
-__global__ void __launch_bounds__(kBlock)
-    k_sd_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
-                 const R* __restrict__ Tz, const R* __restrict__ u,
-                 const R* __restrict__ pprev, R* __restrict__ p, R* __restrict__ q,
-                 const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
-                 double* zq, double* red, const double* upart, int GU, Scalars* sc,
-                 int bench) {
+__device__ inline void sd_stencil_tile(int t, bool lead_block, Geo g, const R* __restrict__ Tx,
+                                       const R* __restrict__ Ty, const R* __restrict__ Tz,
+                                       const R* __restrict__ u, const R* __restrict__ pprev,
+                                       R* __restrict__ p, R* __restrict__ q,
+                                       const uint8_t* __restrict__ slot,
+                                       const int32_t* __restrict__ slot_pos, double* zq,
+                                       double* red, const double* upart, int GU, Scalars* sc,
+                                       int bench, int pre) {
   using psl::ld;
   using psl::st;
   __shared__ double lds[(NS + 1) * kNW];
   __shared__ double lds2[2 * kNW];
   const bool stop = sc->done != 0;   // acted on once the cell loads are in flight
-  const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -732,42 +833,46 @@ __global__ void __launch_bounds__(kBlock)
     }
   }
   if (stop) return;
-  // rho and ||r||^2 of the current residual, summed from the update partials
-  double rs[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < GU; i += kBlock) {
-    rs[0] += upart[i];
-    rs[1] += upart[GU + i];
-  }
-  psl::block_sum<2>(rs, lds2);
   double beta_d = 0.5;
-  if (!bench) {
-    const double rho = rs[0], rr = rs[1];
-    const int cnt = sc->cnt[PAR ^ 1];
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    if (!(rr < INFINITY) || !(fabs(rho) < INFINITY)) {
-      if (lead) {
-        sc->status = PSL_ENONFINITE;
-        sc->iters = cnt;
-        sc->stop_par = PAR;
-        sc->done = 1;
-      }
-      return;
+  if (pre) {
+    if (!bench) beta_d = sc->beta[PAR];   // decided by the finish kernel
+  } else {
+    // rho and ||r||^2 of the current residual, summed from the update partials
+    double rs[2] = {0.0, 0.0};
+    for (int i = threadIdx.x; i < GU; i += kBlock) {
+      rs[0] += upart[i];
+      rs[1] += upart[GU + i];
     }
-    if (rr <= sc->goal2 || cnt >= sc->maxit) {
+    psl::block_sum<2>(rs, lds2);
+    if (!bench) {
+      const double rho = rs[0], rr = rs[1];
+      const int cnt = sc->cnt[PAR ^ 1];
+      const bool lead = lead_block && threadIdx.x == 0;
+      if (!(rr < INFINITY) || !(fabs(rho) < INFINITY)) {
+        if (lead) {
+          sc->status = PSL_ENONFINITE;
+          sc->iters = cnt;
+          sc->stop_par = PAR;
+          sc->done = 1;
+        }
+        return;
+      }
+      if (rr <= sc->goal2 || cnt >= sc->maxit) {
+        if (lead) {
+          sc->rr = rr;
+          sc->iters = cnt;
+          sc->stop_par = PAR;
+          sc->done = 1;
+        }
+        return;
+      }
+      beta_d = rho / sc->gamma[PAR ^ 1];   // +inf before the first step of a fresh start
       if (lead) {
+        sc->gamma[PAR] = rho;
+        sc->cnt[PAR] = cnt + 1;
+        sc->iters = cnt + 1;
         sc->rr = rr;
-        sc->iters = cnt;
-        sc->stop_par = PAR;
-        sc->done = 1;
       }
-      return;
-    }
-    beta_d = rho / sc->gamma[PAR ^ 1];   // +inf before the first step of a fresh start
-    if (lead) {
-      sc->gamma[PAR] = rho;
-      sc->cnt[PAR] = cnt + 1;
-      sc->iters = cnt + 1;
-      sc->rr = rr;
     }
   }
   const R beta = R(beta_d);
@@ -799,13 +904,32 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) red[t] = acc[NS];
 }
 
-template <typename R, int CPT, int PAR>
+template <typename R, int NS, int CPT, int PAR>
 __global__ void __launch_bounds__(kBlock)
-    k_sd_update(Geo g, const R* __restrict__ q, R* __restrict__ r, R* __restrict__ u,
-                const R* __restrict__ p, R* __restrict__ x, const R* __restrict__ invd,
-                const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
-                const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
-                const double* cpart, int G, double* upart, Scalars* sc, int bench) {
+    k_sd_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
+                 const R* __restrict__ Tz, const R* __restrict__ u,
+                 const R* __restrict__ pprev, R* __restrict__ p, R* __restrict__ q,
+                 const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
+                 double* zq, double* red, const double* upart, int GU, Scalars* sc,
+                 int bench, int pre) {
+  sd_stencil_tile<R, NS, CPT, PAR>(tile_of_block(blockIdx.x, g.ntiles), blockIdx.x == 0, g, Tx,
+                                   Ty, Tz, u, pprev, p, q, slot, slot_pos, zq, red, upart, GU,
+                                   sc, bench, pre);
+}
+
+// Update pass over the tiles tb0, tb0 + step, ... (tile_of_block order; step 0: tile tb0
+// itself, once); the workgroup's (r, u), (r, r) partials go to upart[pidx] and
+// upart[pcount + pidx].
+template <typename R, int CPT, int PAR>
+__device__ inline void sd_update_tiles(int tb0, int step, int pidx, int pcount, bool lead_block,
+                                       Geo g, const R* __restrict__ q, R* __restrict__ r,
+                                       R* __restrict__ u, const R* __restrict__ p,
+                                       R* __restrict__ x, const R* __restrict__ invd,
+                                       const int32_t* az_ptr, const int32_t* az_cell,
+                                       const int32_t* az_lab, const int32_t* az_oth,
+                                       const R* az_t, const double* __restrict__ e,
+                                       const double* cpart, int G, double* upart, Scalars* sc,
+                                       int bench, int pre) {
   using psl::ld;
   using psl::st;
   __shared__ double corr[kTileMax];   // A Z e
@@ -814,10 +938,12 @@ __global__ void __launch_bounds__(kBlock)
   const bool stop = sc->done != 0;   // acted on once the first tile's loads are in flight
   double acc[2] = {0.0, 0.0};
   bool first = true;
-  for (int tb = blockIdx.x; tb < g.ntiles; tb += gridDim.x) {
-    const int t = tile_of_block(tb, g.ntiles);
+  for (int tb = tb0; tb < g.ntiles; tb += (step > 0 ? step : g.ntiles)) {
+    const int t = step > 0 ? tile_of_block(tb, g.ntiles) : tb;
     const Tile T = load_tile(g.tiles, t);
     const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
+    FaceRound fr;   // the cut faces first, then the cell loads
+    face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), stop, fr);
     int cc[CPT];
     R qv[CPT], rv[CPT], pv[CPT], xv[CPT], dv[CPT];
 #pragma unroll
@@ -838,8 +964,14 @@ __global__ void __launch_bounds__(kBlock)
     }
     // a wave that sees the stop flag leaves, except wave 0, which publishes the decision
     // (the flag is raised inside this launch only together with a stop decision)
-    if (stop && threadIdx.x >= psl::kWave) return;
-    if (first && threadIdx.x < psl::kWave) {
+    if (stop && (pre || threadIdx.x >= psl::kWave)) return;
+    if (first && pre) {
+      // the step was decided by the finish kernel before this launch
+      if (threadIdx.x == 0) {
+        coef[0] = bench ? 1e-3 : sc->alpha[PAR];
+        coef[1] = 1.0;
+      }
+    } else if (first && threadIdx.x < psl::kWave) {
       // one wave reduces the coarse partials (fixed order) and takes the step decision
       double alpha_d = 1e-3, go = stop ? 0.0 : 1.0;
       if (!bench && !stop) {
@@ -851,7 +983,7 @@ __global__ void __launch_bounds__(kBlock)
         s0 = psl::wave_sum(s0);
         s1 = psl::wave_sum(s1);
         const double den = s1 - s0;   // (p, P1 A p)
-        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        const bool lead = lead_block && threadIdx.x == 0;
         if (!(fabs(den) < INFINITY) || !(den > 0.0)) {
           go = 0.0;
           if (lead) {
@@ -870,8 +1002,8 @@ __global__ void __launch_bounds__(kBlock)
         coef[1] = go;
       }
     }
-    tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
-                           nullptr, corr, corr, stop);  // ends with a barrier
+    tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
+                           corr, corr, stop);  // ends with a barrier
     if (coef[1] == 0.0) return;
     const R alpha = R(coef[0]);
 #pragma unroll
@@ -893,9 +1025,92 @@ __global__ void __launch_bounds__(kBlock)
   }
   psl::block_sum<2>(acc, lds);
   if (threadIdx.x == 0) {
-    upart[blockIdx.x] = acc[0];
-    upart[gridDim.x + blockIdx.x] = acc[1];
+    upart[pidx] = acc[0];
+    upart[pcount + pidx] = acc[1];
   }
+}
+
+template <typename R, int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_sd_update(Geo g, const R* __restrict__ q, R* __restrict__ r, R* __restrict__ u,
+                const R* __restrict__ p, R* __restrict__ x, const R* __restrict__ invd,
+                const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
+                const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
+                const double* cpart, int G, double* upart, Scalars* sc, int bench, int pre) {
+  sd_update_tiles<R, CPT, PAR>(blockIdx.x, gridDim.x, blockIdx.x, gridDim.x, blockIdx.x == 0, g,
+                               q, r, u, p, x, invd, az_ptr, az_cell, az_lab, az_oth, az_t, e,
+                               cpart, G, upart, sc, bench, pre);
+}
+
+// Step decisions of the two-reduction iteration of parity PAR in one workgroup (the same
+// sums and tests the pass workgroups make themselves without them).
+// finish_b, before the stencil pass: rho = (r, M^-1 r) and ||r||^2 from the update
+// partials, stop test, beta = rho / rho_prev into the PAR slot.
+template <int PAR>
+__device__ inline void sd_finish_b(const double* upart, int GU, Scalars* sc) {
+  __shared__ double lds2[2 * kNW];
+  if (sc->done) return;
+  double rs[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < GU; i += kBlock) {
+    rs[0] += upart[i];
+    rs[1] += upart[GU + i];
+  }
+  psl::block_sum<2>(rs, lds2);
+  if (threadIdx.x != 0) return;
+  const double rho = rs[0], rr = rs[1];
+  const int cnt = sc->cnt[PAR ^ 1];
+  if (!(rr < INFINITY) || !(fabs(rho) < INFINITY)) {
+    sc->status = PSL_ENONFINITE;
+    sc->iters = cnt;
+    sc->stop_par = PAR;
+    sc->done = 1;
+  } else if (rr <= sc->goal2 || cnt >= sc->maxit) {
+    sc->rr = rr;
+    sc->iters = cnt;
+    sc->stop_par = PAR;
+    sc->done = 1;
+  } else {
+    sc->beta[PAR] = rho / sc->gamma[PAR ^ 1];   // +inf before the first step of a fresh start
+    sc->gamma[PAR] = rho;
+    sc->cnt[PAR] = cnt + 1;
+    sc->iters = cnt + 1;
+    sc->rr = rr;
+  }
+}
+
+template <int PAR>
+__global__ void __launch_bounds__(kBlock) k_sd_finish_b(const double* upart, int GU, Scalars* sc) {
+  sd_finish_b<PAR>(upart, GU, sc);
+}
+
+// finish_a, before the update pass: (p, P1 A p) = (p, q) - s^T e from the coarse partials,
+// breakdown test, alpha = rho / (p, P1 A p) into the PAR slot.
+template <int PAR>
+__device__ inline void sd_finish_a(const double* cpart, int G, Scalars* sc) {
+  if (sc->done || threadIdx.x >= psl::kWave) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < G; i += psl::kWave) {
+    s0 += cpart[i];       // s^T e
+    s1 += cpart[G + i];   // (p, q)
+  }
+  s0 = psl::wave_sum(s0);
+  s1 = psl::wave_sum(s1);
+  if (threadIdx.x != 0) return;
+  const double den = s1 - s0;   // (p, P1 A p)
+  if (!(fabs(den) < INFINITY) || !(den > 0.0)) {
+    sc->status = (fabs(den) < INFINITY) ? PSL_EBREAKDOWN : PSL_ENONFINITE;
+    sc->iters = sc->cnt[PAR] - 1;
+    sc->stop_par = -1;
+    sc->done = 1;
+  } else {
+    sc->alpha[PAR] = sc->gamma[PAR] / den;
+    sc->delta = den;
+  }
+}
+
+template <int PAR>
+__global__ void __launch_bounds__(psl::kWave) k_sd_finish_a(const double* cpart, int G, Scalars* sc) {
+  sd_finish_a<PAR>(cpart, G, sc);
 }
 
 // Two-reduction start (fresh) or restart after a residual replacement (keep): r = sigma
@@ -986,8 +1201,10 @@ __global__ void __launch_bounds__(kBlock)
   __shared__ double lds[kNW];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
-  tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, nullptr, az_t, e, nullptr, corr,
-                         corr, false);
+  FaceRound fr;
+  face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, nullptr, az_t, false, fr);
+  tile_correction<false>(T, fr, az_cell, az_lab, az_oth, nullptr, az_t, e, nullptr, corr, corr,
+                         false);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   double acc[1] = {0.0};
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
@@ -1279,7 +1496,7 @@ struct CgUpdateC {
       hipLaunchKernelGGL((k_cg_update<R, RP, CPT, PAR>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), v.v, v.rh, v.u, v.p, v.q, v.xh, Prec<R>::invd(c), c->az_ptr,
                          c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e, c->er,
-                         c->cpart, c->coarse_blocks, c->sc, bench);
+                         c->cpart, c->coarse_blocks, c->sc, bench, c->pre);
     }
   };
 };
@@ -1301,7 +1518,7 @@ struct SdStencilC {
       hipLaunchKernelGGL((k_sd_stencil<R, NS, CPT, PAR>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
                          v.u, PAR ? v.p : v.p2, PAR ? v.p2 : v.p, v.q, c->slot, c->slot_pos,
-                         c->zq, c->red, c->upart, c->upd_blocks, c->sc, bench);
+                         c->zq, c->red, c->upart, c->upd_blocks, c->sc, bench, c->pre);
     }
   };
 };
@@ -1325,7 +1542,7 @@ struct SdUpdateC {
       hipLaunchKernelGGL((k_sd_update<R, CPT, PAR>), dim3(c->upd_blocks), dim3(kBlock), 0, st,
                          geo(c), v.q, v.rh, v.u, PAR ? v.p2 : v.p, v.xh, Prec<R>::invd(c),
                          c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
-                         c->cpart, c->coarse_blocks, c->upart, c->sc, bench);
+                         c->cpart, c->coarse_blocks, c->upart, c->sc, bench, c->pre);
     }
   };
 };
@@ -1342,8 +1559,12 @@ int ensure_sd(psl_ctx* c) {
   if (!v.p2 && psl_ctx_alloc(c, reinterpret_cast<void**>(&v.p2), sizeof(R) * size_t(c->n)) != PSL_OK)
     return PSL_ENOMEM;
   if (!c->upart) {
-    c->upd_blocks = std::min(c->ntiles, kUpdMaxBlocks);
-    if (psl_ctx_alloc(c, reinterpret_cast<void**>(&c->upart), sizeof(double) * 2 * c->upd_blocks) != PSL_OK)
+    // with finish kernels the update pass runs one workgroup per tile (its partials are
+    // summed once, by the finish kernel); otherwise a capped grid keeps the number of
+    // partials every stencil workgroup sums small
+    c->upd_blocks = c->pre ? c->ntiles : std::min(c->ntiles, kUpdMaxBlocks);
+    // room for one partial pair per tile (the batched float32 iteration writes those)
+    if (psl_ctx_alloc(c, reinterpret_cast<void**>(&c->upart), sizeof(double) * 2 * c->ntiles) != PSL_OK)
       return PSL_ENOMEM;
   }
   return PSL_OK;
@@ -1397,6 +1618,9 @@ void enqueue_iteration(psl_ctx* c, hipStream_t st) {
   prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<RP, kCgQ>(c, 1, st);
   prof_end<R>(c, PSL_KERNEL_COARSE, st);
+  if (c->pre)
+    hipLaunchKernelGGL(k_cg_finish<PAR>, dim3(1), dim3(psl::kWave), 0, st, c->cpart,
+                       c->coarse_blocks, c->sc);
   prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<CgUpdateC<R, RP, PAR>::template F>(c->cpt, c, st, 0);
   prof_end<R>(c, PSL_KERNEL_UPDATE, st);
@@ -1419,12 +1643,18 @@ void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
 // one two-reduction iteration of parity PAR (three launches)
 template <typename R, int PAR>
 void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
+  if (c->pre)
+    hipLaunchKernelGGL(k_sd_finish_b<PAR>, dim3(1), dim3(kBlock), 0, st, c->upart,
+                       c->upd_blocks, c->sc);
   prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
   with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, 0);
   prof_end<R>(c, PSL_KERNEL_STENCIL, st);
   prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<0, 1>(c, 1, st);
   prof_end<R>(c, PSL_KERNEL_COARSE, st);
+  if (c->pre)
+    hipLaunchKernelGGL(k_sd_finish_a<PAR>, dim3(1), dim3(psl::kWave), 0, st, c->cpart,
+                       c->coarse_blocks, c->sc);
   prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<SdUpdateC<R, PAR>::template F>(c->cpt, c, st, 0);
   prof_end<R>(c, PSL_KERNEL_UPDATE, st);
@@ -2477,8 +2707,10 @@ __global__ void __launch_bounds__(kBlock)
   const R a = R(ad);
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
-  tile_correction<false>(T, t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e,
-                         nullptr, corr, corr, false);
+  FaceRound fr;
+  face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), false, fr);
+  tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
+                         corr, corr, false);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
     int ix, iy, iz;
@@ -3024,6 +3256,10 @@ struct SysArgs {
   const int32_t *slot_pos, *lab_ptr, *az_ptr, *az_cell, *az_lab, *az_oth;
   double *zq, *zr, *red, *cpart, *s, *sr, *e, *er;
   double *xh, *rh, *p, *q, *v, *u;
+  // float32 two-reduction iteration (PSL_MIXED; null when the plan has no float32 part)
+  const float *Tx32, *Ty32, *Tz32, *invd32, *az_t32;
+  float *xh32, *rh32, *p32, *p2_32, *q32, *u32;
+  double* upart;   // [2 * ntiles] per-tile (r, M^-1 r), (r, r) partials
   Scalars* sc;
   int d, G;
 };
@@ -3057,7 +3293,52 @@ __global__ void __launch_bounds__(kBlock)
   const SysArgs& A = sa[w.x];
   cg_update_tile<double, 0, CPT, PAR>(w.y, w.y == 0, A.g, A.v, A.rh, A.u, A.p, A.q, A.xh,
                                       A.invd, A.az_ptr, A.az_cell, A.az_lab, A.az_oth, A.az_t,
-                                      A.e, A.er, A.cpart, A.G, A.sc, 0);
+                                      A.e, A.er, A.cpart, A.G, A.sc, 0, 0);
+}
+
+// float32 two-reduction iteration over the (system, tile) work list, with every step
+// decision in one workgroup per system (finish kernels); a finished system's workgroups
+// return at once
+template <int PAR>
+__global__ void __launch_bounds__(kBlock) k_b_sd_finish_b(const SysArgs* __restrict__ sa) {
+  const SysArgs& A = sa[blockIdx.x];
+  sd_finish_b<PAR>(A.upart, A.g.ntiles, A.sc);
+}
+
+template <int NS, int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_b_sd_stencil(const SysArgs* __restrict__ sa, const int2* __restrict__ work, int nwork) {
+  const int2 w = work[tile_of_block(blockIdx.x, nwork)];
+  const SysArgs& A = sa[w.x];
+  sd_stencil_tile<float, NS, CPT, PAR>(w.y, w.y == 0, A.g, A.Tx32, A.Ty32, A.Tz32, A.u32,
+                                       PAR ? A.p32 : A.p2_32, PAR ? A.p2_32 : A.p32, A.q32,
+                                       A.slot, A.slot_pos, A.zq, A.red, A.upart, A.g.ntiles,
+                                       A.sc, 0, 1);
+}
+
+__global__ void __launch_bounds__(kBlock)
+    k_b_sd_coarse(const SysArgs* __restrict__ sa, const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const SysArgs& A = sa[w.x];
+  coarse_block<0, 1, 1>(w.y, A.G, A.Einv, A.zq, A.zr, A.lab_ptr, A.s, A.sr, A.e, A.er, A.red,
+                        A.g.ntiles, A.cpart, A.d, A.sc, 1);
+}
+
+template <int PAR>
+__global__ void __launch_bounds__(psl::kWave) k_b_sd_finish_a(const SysArgs* __restrict__ sa) {
+  const SysArgs& A = sa[blockIdx.x];
+  sd_finish_a<PAR>(A.cpart, A.G, A.sc);
+}
+
+template <int CPT, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_b_sd_update(const SysArgs* __restrict__ sa, const int2* __restrict__ work, int nwork) {
+  const int2 w = work[tile_of_block(blockIdx.x, nwork)];
+  const SysArgs& A = sa[w.x];
+  sd_update_tiles<float, CPT, PAR>(w.y, 0, w.y, A.g.ntiles, w.y == 0, A.g, A.q32, A.rh32, A.u32,
+                                   PAR ? A.p2_32 : A.p32, A.xh32, A.invd32, A.az_ptr, A.az_cell,
+                                   A.az_lab, A.az_oth, A.az_t32, A.e, A.cpart, A.G, A.upart,
+                                   A.sc, 0, 1);
 }
 
 __global__ void k_b_gather(const SysArgs* __restrict__ sa, int nsys, SysStat* out) {
@@ -3099,6 +3380,7 @@ struct BatchPlan {
   int graph_chunk = 0, graph_nwork = 0;
   const int2* graph_list = nullptr;
   int last_iters = 0;                 // iterations the last batched solve needed
+  bool has32 = false;                 // argument table holds the float32 iteration's arrays
 };
 
 void destroy_batch_plan(BatchPlan* p) {
@@ -3113,20 +3395,38 @@ void destroy_batch_plan(BatchPlan* p) {
 
 namespace {
 
-int build_plan(psl_ctx* const* ctxs, int nsys, hipStream_t st, psl::BatchPlan** out) {
+int build_plan(psl_ctx* const* ctxs, int nsys, bool with32, hipStream_t st,
+               psl::BatchPlan** out) {
   auto* P = new psl::BatchPlan();
   P->nsys = nsys;
+  P->has32 = with32;
   std::vector<SysArgs> args(nsys);
   std::vector<int2> work, cwork;
   for (int i = 0; i < nsys; ++i) {
     psl_ctx* c = ctxs[i];
     P->ids.push_back(c->id);
-    const int rc = ensure_vecs<double>(c);
+    int rc = ensure_vecs<double>(c);
+    if (rc == PSL_OK && with32) rc = ensure_sd<float>(c);
     if (rc != PSL_OK) {
       psl::destroy_batch_plan(P);
       return rc;
     }
     SysArgs& a = args[i];
+    std::memset(&a, 0, sizeof(a));
+    if (with32) {
+      a.Tx32 = c->Tx32;
+      a.Ty32 = c->Ty32;
+      a.Tz32 = c->Tz32;
+      a.invd32 = c->invdiag32;
+      a.az_t32 = c->az_t32;
+      a.xh32 = c->v32.xh;
+      a.rh32 = c->v32.rh;
+      a.p32 = c->v32.p;
+      a.p2_32 = c->v32.p2;
+      a.q32 = c->v32.q;
+      a.u32 = c->v32.u;
+      a.upart = c->upart;
+    }
     a.g = geo(c);
     a.Tx = c->Tx;
     a.Ty = c->Ty;
@@ -3232,6 +3532,46 @@ void enqueue_b_iteration(const psl::BatchPlan* P, hipStream_t st) {
   with_cpt<BUpdateC<PAR>::template F>(P->cpt_max, P, st);
 }
 
+template <int NS>
+struct BSdStencilL {
+  template <int CPT>
+  struct F {
+    template <int PAR>
+    static void go(const psl::BatchPlan* P, hipStream_t st) {
+      hipLaunchKernelGGL((k_b_sd_stencil<NS, CPT, PAR>), dim3(P->nwork), dim3(kBlock), 0, st,
+                         P->args, P->work, P->nwork);
+    }
+    static void run(const psl::BatchPlan* P, int par, hipStream_t st) {
+      if (par) go<1>(P, st); else go<0>(P, st);
+    }
+  };
+  static void run(const psl::BatchPlan* P, int par, hipStream_t st) {
+    with_cpt<F>(P->cpt_max, P, par, st);
+  }
+};
+
+template <int CPT>
+struct BSdUpdateC {
+  static void run(const psl::BatchPlan* P, int par, hipStream_t st) {
+    if (par)
+      hipLaunchKernelGGL((k_b_sd_update<CPT, 1>), dim3(P->nwork), dim3(kBlock), 0, st, P->args,
+                         P->work, P->nwork);
+    else
+      hipLaunchKernelGGL((k_b_sd_update<CPT, 0>), dim3(P->nwork), dim3(kBlock), 0, st, P->args,
+                         P->work, P->nwork);
+  }
+};
+
+// one float32 two-reduction iteration of every system in the work lists (five launches)
+template <int PAR>
+void enqueue_b_sd_iteration(const psl::BatchPlan* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_b_sd_finish_b<PAR>, dim3(P->nsys), dim3(kBlock), 0, st, P->args);
+  with_ns<BSdStencilL>(P->ns_max, P, PAR, st);
+  hipLaunchKernelGGL(k_b_sd_coarse, dim3(P->ncwork), dim3(kBlock), 0, st, P->args, P->cwork);
+  hipLaunchKernelGGL(k_b_sd_finish_a<PAR>, dim3(P->nsys), dim3(psl::kWave), 0, st, P->args);
+  with_cpt<BSdUpdateC>(P->cpt_max, P, PAR, st);
+}
+
 // Launch only the systems still iterating: compacted (system, tile) and coarse lists.
 int compact_work(psl::BatchPlan* P, const std::vector<char>& live, hipStream_t st) {
   std::vector<int2> w, cw;
@@ -3301,8 +3641,11 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
   psl_solve_opts o;
   psl_default_opts(&o);
   if (o_in) o = *o_in;
-  if (!(o.tol > 0.0) || o.maxit < 0 || o.check_every < 1 || o.check_every > 4096) return PSL_EINVAL;
-  if (o.mode != PSL_FP64) return PSL_ENOTSUP;
+  if (!(o.tol > 0.0) || o.maxit < 0 || o.check_every < 1 || o.check_every > 4096 ||
+      o.max_outer < 1 || (o.mode != PSL_FP64 && o.mode != PSL_MIXED) ||
+      !(o.tau_inner > 0.0 && o.tau_inner < 1.0) || !(o.mixed_floor >= 0.0 && o.mixed_floor < 1.0))
+    return PSL_EINVAL;
+  const bool mixed = o.mode == PSL_MIXED;
   int dev = 0;
   (void)hipGetDevice(&dev);
   for (int i = 0; i < nsys; ++i) {
@@ -3315,12 +3658,12 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
   hipStream_t st = static_cast<hipStream_t>(stream);
   // launch plan, cached on the first context while the batch is the same
   psl_ctx* c0 = ctxs[0];
-  bool same = c0->plan && c0->plan->nsys == nsys;
+  bool same = c0->plan && c0->plan->nsys == nsys && (c0->plan->has32 || !mixed);
   for (int i = 0; same && i < nsys; ++i) same = c0->plan->ids[i] == ctxs[i]->id;
   if (!same) {
     psl::destroy_batch_plan(c0->plan);
     c0->plan = nullptr;
-    const int rc = build_plan(ctxs, nsys, st, &c0->plan);
+    const int rc = build_plan(ctxs, nsys, mixed, st, &c0->plan);
     if (rc != PSL_OK) return rc;
   }
   psl::BatchPlan* P = c0->plan;
@@ -3359,8 +3702,112 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
       stats[i].status = PSL_OK;
     } else {
       active[i] = 1;
+    }
+  }
+  // PSL_MIXED: float32 refinement steps for every system together. Each step runs a fresh
+  // float32 two-reduction DEF1-PCG on the projected float64 residual (one launch of each
+  // pass for all systems, step decisions per system in finish kernels) until it has
+  // reduced that residual by tau_inner, then x += ||r|| xhat and the float64 refinement
+  // step. A system leaves the float32 phase once it converges, reaches mixed_floor, or a
+  // step fails to halve its float64 residual; the float64 phase below finishes it.
+  if (mixed) {
+    std::vector<char> f32(nsys, 0);
+    for (int i = 0; i < nsys; ++i) f32[i] = char(active[i]);
+    const int chunk32 = o.check_every + (o.check_every & 1);
+    for (int outer = 0; outer < o.max_outer; ++outer) {
+      int n32 = 0;
+      for (int i = 0; i < nsys; ++i) {
+        psl_ctx* c = ctxs[i];
+        if (!f32[i]) {
+          hipLaunchKernelGGL(k_set_done, dim3(1), dim3(1), 0, st, c->sc);
+          continue;
+        }
+        const double goal = std::max(o.tau_inner * rnorm[i], o.tol * bnorm[i]) / rnorm[i];
+        hipLaunchKernelGGL(k_sd_set, dim3(1), dim3(1), 0, st, c->sc, goal * goal,
+                           std::max(0, o.maxit - stats[i].iters), 1);
+        hipLaunchKernelGGL(k_sd_init<float>, dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
+                           c->r64, c->invdiag32, c->v32.rh, c->v32.u, c->v32.xh, c->v32.p,
+                           c->v32.p2, c->upart, c->sc, 1);
+        ++n32;
+      }
+      if (n32 == 0) break;
+      P->work = P->work_all;
+      P->cwork = P->cwork_all;
+      P->nwork = P->nwork_all;
+      P->ncwork = P->ncwork_all;
+      if (n32 < nsys && (rc = compact_work(P, f32, st)) != PSL_OK) return rc;
+      std::vector<double> best(nsys, INFINITY);
+      std::vector<int> best_it(nsys, 0);
+      for (int any = n32; any > 0;) {
+        for (int k = 0; k < chunk32; k += 2) {
+          enqueue_b_sd_iteration<0>(P, st);
+          enqueue_b_sd_iteration<1>(P, st);
+        }
+        PSL_HIP(hipGetLastError());
+        if ((rc = gather(P, st)) != PSL_OK) return rc;
+        any = 0;
+        for (int i = 0; i < nsys; ++i) {
+          if (!f32[i] || P->h_stat[i].done) continue;
+          const SysStat& v = P->h_stat[i];
+          if (v.rr < 0.25 * best[i]) {
+            best[i] = v.rr;
+            best_it[i] = v.iters;
+          } else if (v.iters - best_it[i] >= kStallWindow) {
+            hipLaunchKernelGGL(k_set_done, dim3(1), dim3(1), 0, st, ctxs[i]->sc);
+            continue;   // stalled: the refinement step below decides
+          }
+          ++any;
+        }
+      }
+      // x += ||r|| xhat, then the float64 refinement step
+      std::vector<int> inner_status(nsys, 0);
+      for (int i = 0; i < nsys; ++i) {
+        if (!f32[i]) continue;
+        psl_ctx* c = ctxs[i];
+        stats[i].iters += P->h_stat[i].iters;
+        inner_status[i] = P->h_stat[i].status;
+        hipLaunchKernelGGL(k_accumulate<float>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                           int(c->n), x[i], c->v32.xh, c->sc);
+        enqueue_outer_step(c, b[i], x[i], st);
+      }
+      if ((rc = gather(P, st)) != PSL_OK) return rc;
+      for (int i = 0; i < nsys; ++i) {
+        if (!f32[i]) continue;
+        const double rn = std::sqrt(P->h_stat[i].rr);
+        stats[i].outer += 1;
+        if (!std::isfinite(rn) || inner_status[i] == PSL_ENONFINITE) {
+          f32[i] = 0;
+          active[i] = 0;
+          stats[i].status = PSL_ENONFINITE;
+        } else if (rn <= o.tol * bnorm[i]) {
+          f32[i] = 0;
+          active[i] = 0;
+          stats[i].status = PSL_OK;
+        } else if (rn > 0.5 * rnorm[i] || rn <= o.mixed_floor * bnorm[i] ||
+                   stats[i].iters >= o.maxit) {
+          f32[i] = 0;                 // on to float64
+          stats[i].fell_back = stats[i].iters < o.maxit;
+        }
+        rnorm[i] = rn;
+      }
+    }
+    P->work = P->work_all;
+    P->cwork = P->cwork_all;
+    P->nwork = P->nwork_all;
+    P->ncwork = P->ncwork_all;
+    for (int i = 0; i < nsys; ++i)
+      if (active[i] && stats[i].iters >= o.maxit) {
+        active[i] = 0;
+        stats[i].status = PSL_EMAXIT;
+      }
+  }
+  // float64 inner starts (single-reduction loop) of the systems still active
+  for (int i = 0; i < nsys; ++i) {
+    psl_ctx* c = ctxs[i];
+    if (active[i]) {
       const double goal = o.tol * bnorm[i] / rnorm[i];
-      hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, o.maxit);
+      hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal,
+                         std::max(0, o.maxit - stats[i].iters));
       hipLaunchKernelGGL(k_cg_init<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
                          int(c->n), c->r64, c->invdiag, c->v64.rh, c->v64.u, c->v64.xh,
                          c->v64.p, c->v64.q, c->sc);
@@ -3405,8 +3852,8 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
   for (int i = 0; i < nsys; ++i) {
     if (!active[i]) continue;
     psl_ctx* c = ctxs[i];
-    stats[i].iters = P->h_stat[i].iters;
-    max_iters = std::max(max_iters, stats[i].iters);
+    stats[i].iters += P->h_stat[i].iters;
+    max_iters = std::max(max_iters, P->h_stat[i].iters);
     hipLaunchKernelGGL(k_accumulate<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
                        int(c->n), x[i], c->v64.xh, c->sc);
     enqueue_outer_step(c, b[i], x[i], st);
@@ -3417,7 +3864,7 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
   if ((rc = gather(P, st)) != PSL_OK) return rc;
   for (int i = 0; i < nsys; ++i) {
     if (!active[i]) continue;
-    stats[i].outer = 1;
+    stats[i].outer += 1;
     const double rn = std::sqrt(P->h_stat[i].rr);
     if (rn <= o.tol * bnorm[i]) {
       stats[i].status = PSL_OK;
@@ -3435,6 +3882,7 @@ extern "C" int psl_solve_batched(psl_ctx* const* ctxs, int32_t nsys, const doubl
     // single-system path from the current x
     psl_solve_opts o1 = o;
     o1.use_x0 = 1;
+    o1.mode = PSL_FP64;
     o1.maxit = o.maxit - stats[i].iters;
     psl_solve_stats s1;
     const int r1 = psl_solve(ctxs[i], b[i], x[i], &o1, &s1, stream);

@@ -39,7 +39,8 @@ class psl_grid(ctypes.Structure):
 
 
 class psl_setup_opts(ctypes.Structure):
-    _fields_ = [("tile_cells", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("tile_cells", ctypes.c_int32), ("finish_kernels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class psl_solve_opts(ctypes.Structure):
@@ -253,9 +254,9 @@ class Context:
 
 
 def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
-                labels: torch.Tensor, d: int, nsub=None, tile_cells: Optional[int] = None
-                ) -> Context:
-    """psl_setup_E, or psl_setup_E_ex when a tile size is given."""
+                labels: torch.Tensor, d: int, nsub=None, tile_cells: Optional[int] = None,
+                finish_kernels: int = 0) -> Context:
+    """psl_setup_E, or psl_setup_E_ex when a tile size or the finish-kernel choice is given."""
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
     fx, fy, fz = face_counts(grid)
     g = _grid(grid)
@@ -265,12 +266,13 @@ def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
             _dev(Ty, torch.float64, fy, "Ty"), _dev(Tz, torch.float64, fz, "Tz"),
             _dev(labels, torch.int32, n, "labels"), int(d),
             ns if ns is not None else ctypes.cast(None, _I32P))
-    if tile_cells is None:
+    if tile_cells is None and not finish_kernels:
         _check(_setup_e(*args, _stream()), "psl_setup_E")
     else:
         so = psl_setup_opts()
         _default_setup_opts(ctypes.byref(so))
-        so.tile_cells = int(tile_cells)
+        so.tile_cells = int(tile_cells or 0)
+        so.finish_kernels = int(finish_kernels)
         _check(_setup_e_ex(*args, ctypes.byref(so), _stream()), "psl_setup_E_ex")
     return Context(out.value, grid, int(d))
 
@@ -382,13 +384,16 @@ def psl_solve_poly(ctx: Context, b: torch.Tensor, x: Optional[torch.Tensor] = No
 
 def psl_solve_batched(ctxs, bs, xs=None, *, tol: Optional[float] = None,
                       maxit: Optional[int] = None, use_x0: bool = False,
-                      check_every: Optional[int] = None, check: bool = False):
-    """Solve independent systems A_i x_i = b_i together (float64 CG, one launch per kernel
-    for all systems). Returns (xs, [stats dict per system], overall status)."""
+                      check_every: Optional[int] = None, check: bool = False,
+                      mode: int = FP64):
+    """Solve independent systems A_i x_i = b_i together (float64 CG, or float32 refinement
+    steps then float64 with mode=MIXED; one launch per kernel for all systems). Returns
+    (xs, [stats dict per system], overall status)."""
     n = len(ctxs)
     if n < 1 or len(bs) != n or (xs is not None and len(xs) != n):
         raise ValueError("need one b (and x) per context")
     o = default_opts()
+    o.mode = int(mode)
     if tol is not None:
         o.tol = tol
     if maxit is not None:

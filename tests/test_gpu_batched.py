@@ -1,6 +1,7 @@
-"""Batched solve (many independent systems per launch) on the GPU: every system's answer
-is the single-system float64 answer bit for bit, meets the oracle's accuracy bar, and
-the per-system failure paths stay per system."""
+"""Batched solve (many independent systems per launch) on the GPU: every system's float64
+answer is the single-system float64 answer bit for bit, the mixed-precision answers meet
+the oracle's accuracy bar and do not depend on the rest of the batch, and the per-system
+failure paths stay per system."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -118,4 +119,55 @@ def test_batched_argument_errors(gpu_lib):
     xs = [b.clone() for b in bs]
     xp = (ctypes.c_void_p * 2)(*[x.data_ptr() for x in xs])
     st = (psl.psl_solve_stats * 2)()
-    assert psl._solve_batched(handles, 2, bp, xp, ctypes.byref(o), st, None) == psl.ENOTSUP
+    o.tau_inner = 1.5                  # out of (0, 1)
+    assert psl._solve_batched(handles, 2, bp, xp, ctypes.byref(o), st, None) == psl.EINVAL
+    o.tau_inner = 0.01
+    o.mode = 7
+    assert psl._solve_batched(handles, 2, bp, xp, ctypes.byref(o), st, None) == psl.EINVAL
+
+
+def test_batched_mixed_matches_oracle(gpu_lib):
+    """PSL_MIXED batched: float32 refinement steps for all systems together, float64 to
+    finish. Every x meets 1e-8 in the oracle's matrix and 1e-6 against a direct solve,
+    and its float64 residual is the library's own figure."""
+    psl = gpu_lib
+    probs = _small_batch(nsys=8, seed=11)
+    setups, bs = _setup_all(probs)
+    xs, stats, rc = psl.psl_solve_batched([s.ctx for s in setups], bs, mode=psl.MIXED)
+    assert rc == 0, [s["status_str"] for s in stats]
+    for p, s, b, xg, st in zip(probs, setups, bs, xs, stats):
+        A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+        xh = xg.cpu().numpy()
+        res = O.relres(A, bh, xh)
+        xr = spla.spsolve(A.tocsc(), bh)
+        err = np.linalg.norm(xh - xr) / np.linalg.norm(xr)
+        x1, st1 = psl.psl_solve(s.ctx, b, mode=psl.MIXED)
+        say(f"  side {p.grid[0]} c={p.meta.get('contrast', 0):.1e} mixed batched: iters "
+            f"{st['iters']} outer {st['outer']} fell_back {st['fell_back']} relres {res:.2e} "
+            f"err {err:.2e} (single mixed: iters {st1['iters']} outer {st1['outer']})")
+        assert st["status"] == 0 and res <= 1e-8 and st["relres_true"] <= 1e-8
+        assert abs(st["relres_true"] - res) <= 2e-2 * res + 1e-12
+        assert err <= 1e-6
+        assert st["outer"] >= 1
+
+
+def test_batched_mixed_independent_of_batch(gpu_lib):
+    """In PSL_MIXED each system's arithmetic is its own (per-system scalars and step
+    decisions, fixed-order sums): its x does not depend on the other systems of the batch,
+    on their order, or on a repeat of the call (bit for bit)."""
+    psl = gpu_lib
+    probs = _small_batch(nsys=5, seed=13)
+    setups, bs = _setup_all(probs)
+    ctxs = [s.ctx for s in setups]
+    xs, st, rc = psl.psl_solve_batched(ctxs, bs, mode=psl.MIXED)
+    assert rc == 0
+    xs = [x.clone() for x in xs]
+    xs2, st2, _ = psl.psl_solve_batched(ctxs, bs, mode=psl.MIXED)
+    xs3, st3, _ = psl.psl_solve_batched(ctxs[::-1], bs[::-1], mode=psl.MIXED)
+    say("mixed batched iterations " + ",".join(str(s["iters"]) for s in st))
+    for i in range(len(probs)):
+        xa, sa = psl.psl_solve_batched([ctxs[i]], [bs[i]], mode=psl.MIXED)[:2]
+        assert np.array_equal(xs[i].cpu().numpy(), xs2[i].cpu().numpy())
+        assert np.array_equal(xs[i].cpu().numpy(), xs3[len(probs) - 1 - i].cpu().numpy())
+        assert np.array_equal(xs[i].cpu().numpy(), xa[0].cpu().numpy())
+        assert st[i]["iters"] == st2[i]["iters"] == sa[0]["iters"]

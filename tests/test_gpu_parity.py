@@ -847,3 +847,46 @@ def test_deep_tolerance_recovers(gpu_lib, seed, tol):
         assert st["status"] == 0
     else:
         assert st["status"] in (0, psl.ESTAGNATION, psl.EMAXIT)
+
+
+FINISH_CASES = [("c2", 4, {}), ("c3", 4, {"contrast": 1e5}), ("ragged", 0, {})]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name,scale,kw", FINISH_CASES,
+                         ids=[f"{c[0]}-{c[1]}" for c in FINISH_CASES])
+def test_finish_kernels(gpu_lib, name, scale, kw, mode):
+    """Step decisions taken in the one-workgroup finish kernels (the large-grid
+    configuration, forced on here for small grids) against the oracle, and against the
+    same solve with every pass workgroup summing the partials itself: float64 (the
+    single-reduction loop sums the same partials in the same order: identical x) and mixed
+    (the update partials are grouped per tile instead of per capped workgroup: the same
+    iteration count within one)."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _problem(name, scale, kw)
+    say(f"finish kernels {name}/{scale} grid={p.grid} mode={mode}")
+    K, b = dev(p.K), dev(p.q)
+    out = {}
+    for fk in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), finish_kernels=fk)
+        x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=mode)
+        out[fk] = (x.clone(), st)
+    A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    Z = O.deflation_matrix(*O.levelset_labels(p.grid, p.K, p.nsub, p.thr))
+    ref = O.dpcg(A, bh, Z, tol=1e-8)
+    xr = _reference_x(A, bh, p.n)
+    if xr is None:
+        xr = O.dpcg(A, bh, Z, tol=1e-12).x
+    (x1, st1), (x0, st0) = out[1], out[-1]
+    res = O.relres(A, bh, host(x1))
+    err = np.linalg.norm(host(x1) - xr) / np.linalg.norm(xr)
+    say(f"  finish kernels: status={st1['status_str']} iters={st1['iters']} outer={st1['outer']} "
+        f"relres={res:.2e} err={err:.2e}; in the passes: iters={st0['iters']} "
+        f"(oracle {ref.iters})")
+    assert st1["status"] == 0 and res <= 1e-8 and err <= 1e-6
+    if mode == 0:
+        assert torch.equal(x1, x0) and st1["iters"] == st0["iters"]
+        assert abs(st1["iters"] - ref.iters) <= max(2, 0.02 * ref.iters)
+    else:
+        assert abs(st1["iters"] - st0["iters"]) <= 1
