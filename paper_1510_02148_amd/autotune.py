@@ -105,16 +105,17 @@ def tune(problems: Sequence, candidates: Iterable[int] = CANDIDATES, sample: int
 
 
 def tune_single(problem, precision: str = "f64", candidates: Iterable[int] = CANDIDATES,
-                reps: int = 3, log=print) -> Dict[str, dict]:
+                reps: int = 3, log=print, components: bool = False) -> Dict[str, dict]:
     """Time the single-system solve (psl_solve in the given precision, from set-up to
-    1e-8) of one problem for each candidate tile size; the table entry for its class."""
+    1e-8) of one problem for each candidate tile size; the table entry for its class.
+    components: deflation vectors by connected components (psl_build_Z_cc)."""
     K = torch.as_tensor(problem.K, dtype=torch.float64, device="cuda")
     b = torch.as_tensor(problem.q, dtype=torch.float64, device="cuda")
     mode = psl.MIXED if precision == "f32" else psl.FP64
     times = {}
     for tile in candidates:
         s = pipeline.setup(problem.grid, K, problem.dirichlet_mask, problem.nsub,
-                           list(problem.thr), tile_cells=int(tile))
+                           list(problem.thr), tile_cells=int(tile), components=components)
         psl.psl_solve(s.ctx, b, tol=problem.tol, mode=mode)       # warm
         best = math.inf
         for _ in range(reps):
@@ -145,3 +146,31 @@ def tiles_for(grids: Sequence[Sequence[int]], table: Optional[Dict[str, dict]] =
         e = table.get(_key(precision, shape_class(int(g[0]) * int(g[1]) * int(g[2])), kind))
         out.append(int(e["tile_cells"]) if e else None)
     return out
+
+
+def main(argv=None):
+    """python -m paper_1510_02148_amd.autotune [--single NAME] [--labels L]: tune the
+    single-system tile sizes (float64 and float32) of a named workload's shape class and
+    store them in the table."""
+    import argparse
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import psl_inputs as pi
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--single", default="c3", help="workload name of psl_inputs.config")
+    ap.add_argument("--labels", default="components", choices=["regions", "components"])
+    ap.add_argument("--precision", default="both", choices=["f64", "f32", "both"])
+    a = ap.parse_args(argv)
+    prob = pi.config(a.single, contrast=1e6) if a.single == "c3" else pi.config(a.single)
+    entries = {}
+    for prec in (("f64", "f32") if a.precision == "both" else (a.precision,)):
+        entries.update(tune_single(prob, prec, components=a.labels == "components"))
+    save_table(entries)
+
+
+if __name__ == "__main__":
+    main()
