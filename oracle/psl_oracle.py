@@ -444,15 +444,17 @@ def dpcg_poly(A, b, Z, degree: int = 3, ratio: float = 30.0, lmax: float = 2.0, 
 def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000,
             coarse: Optional[Coarse] = None, degree: int = 1, ratio: float = 30.0,
             lmax: float = 2.0) -> Result:
-    """Right-preconditioned restarted GMRES(m) on the deflated system with a priori
-    subdomain-levelset vectors (Algorithm 1 with Z, E, P1, P2 and x* formed before the
-    iteration, Section 3.2), M = diag(A):
+    """The paper's deflated GMRES (Algorithm 1) with the subdomain-levelset vectors formed
+    a priori (Section 3.2): restarted GMRES(m) with right preconditioning M = diag(A) on
+    the deflated operator P1 A, then the projection back (eq. "projectback").
 
-      r0 = P1 (b - A x0), beta = ||r0||, v1 = r0 / beta
-      Arnoldi with modified Gram-Schmidt on w = P1 A M^-1 v_j, h_ij, h_{j+1,j} = ||w||
-      u = argmin ||beta e1 - Hbar_j u|| (library least squares), stop when its residual is
-      <= tol ||b|| or h_{j+1,j} = 0, or after m steps (restart from x0 + M^-1 V u)
-      at convergence x = P2 x_m + x* = x_m + Z E^-1 Z^T (b - A x_m).
+    Within a cycle the iterate minimises ||P1 (b - A x)||_2 over x0 + M^-1 K_j(P1 A M^-1,
+    r0). Here the basis is kept orthonormal by classical Gram-Schmidt applied twice, the
+    small least-squares problem is triangularised by one Givens rotation per step as the
+    basis grows, and the residual norm of the minimiser is read from the rotated
+    right-hand side (no solve needed to test convergence). A cycle ends on convergence
+    (residual <= tol ||b||), on an invariant subspace (new basis direction of norm 0), or
+    after m steps; the cycle's correction is M^-1 V y with y from the triangle.
 
     ``iters`` counts products with A inside the cycles; ``history`` holds the least-
     squares residual after every step (starting with ||r0||). degree >= 2 replaces
@@ -480,43 +482,58 @@ def pdgmres(A, b, Z, m: int = 30, x0=None, tol: float = 1e-8, maxit: int = 10000
             return v / dg
         return chebyshev_apply(A, v, degree, lmax / ratio, lmax)
 
+    def op(v):                        # the right-preconditioned deflated operator
+        return P1(A @ Minv(v))
+
     xm = x0.copy()
     it = 0
     hist = []
     status = "ok"
+    goal = tol * bnorm
     while True:
         r0 = P1(b - A @ xm)
         beta = np.linalg.norm(r0)
         if not hist:
             hist.append(beta)
-        if beta <= tol * bnorm:
+        if beta <= goal:
             break
         if it >= maxit:
             status = "maxit"
             break
-        V = np.zeros((n, m + 1))
-        H = np.zeros((m + 1, m))
-        V[:, 0] = r0 / beta
-        u = np.zeros(0)
-        j_end = 0
-        for j in range(m):
-            w = P1(A @ Minv(V[:, j]))
-            for i in range(j + 1):
-                H[i, j] = w @ V[:, i]
-                w = w - H[i, j] * V[:, i]
-            H[j + 1, j] = np.linalg.norm(w)
+        basis = [r0 / beta]
+        R = np.zeros((m, m))          # triangular factor of the rotated Hessenberg matrix
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)           # rotated right-hand side beta e1
+        g[0] = beta
+        k = 0                         # steps taken in this cycle
+        while k < m:
+            w = op(basis[k])
+            Vk = np.array(basis)      # (k + 1) x n
+            h = Vk @ w
+            w = w - Vk.T @ h
+            h2 = Vk @ w               # second pass: reorthogonalisation
+            w = w - Vk.T @ h2
+            h = h + h2
+            hnext = np.linalg.norm(w)
             it += 1
-            rhs = np.zeros(j + 2)
-            rhs[0] = beta
-            u = np.linalg.lstsq(H[:j + 2, :j + 1], rhs, rcond=None)[0]
-            res = np.linalg.norm(rhs - H[:j + 2, :j + 1] @ u)
+            # earlier rotations act on the new column; a new one zeroes its last entry
+            for i in range(k):
+                h[i], h[i + 1] = cs[i] * h[i] + sn[i] * h[i + 1], -sn[i] * h[i] + cs[i] * h[i + 1]
+            rad = np.hypot(h[k], hnext)
+            cs[k], sn[k] = (h[k] / rad, hnext / rad) if rad > 0.0 else (1.0, 0.0)
+            R[:k + 1, k] = h[:k + 1]
+            R[k, k] = rad
+            g[k + 1] = -sn[k] * g[k]
+            g[k] = cs[k] * g[k]
+            res = abs(g[k + 1])
             hist.append(res)
-            j_end = j + 1
-            if H[j + 1, j] == 0.0 or res <= tol * bnorm or it >= maxit:
+            k += 1
+            if hnext == 0.0 or res <= goal or it >= maxit:
                 break
-            V[:, j + 1] = w / H[j + 1, j]
-        xm = xm + Minv(V[:, :j_end] @ u)
-        if hist[-1] <= tol * bnorm:
+            basis.append(w / hnext)
+        y = sla.solve_triangular(R[:k, :k], g[:k], lower=False)
+        xm = xm + Minv(np.array(basis[:k]).T @ y)
+        if hist[-1] <= goal:
             break
     x = xm + coarse.correction(b - A @ xm)
     relres = np.linalg.norm(b - A @ x) / bnorm

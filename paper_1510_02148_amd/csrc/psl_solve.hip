@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(kBlock)
 // (zr).
 // ---------------------------------------------------------------------------------------
 template <typename R, int NS, int RP, int CPT>
-__device__ inline void cg_stencil_tile(int t, Geo g, const R* __restrict__ Tx,
+__device__ __forceinline__ void cg_stencil_tile(int t, Geo g, const R* __restrict__ Tx,
                                        const R* __restrict__ Ty, const R* __restrict__ Tz,
                                        const R* __restrict__ r, const R* __restrict__ u,
                                        R* __restrict__ v, const uint8_t* __restrict__ slot,
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kBlock)
 // for q < NQ, cpart[(1 + q) G + g] = its slice of the tile partials red[q * ntiles + .].
 // ---------------------------------------------------------------------------------------
 template <int RP, int FUSED, int NQ>
-__device__ inline void coarse_block(int blk, int G, const double* __restrict__ Einv,
+__device__ __forceinline__ void coarse_block(int blk, int G, const double* __restrict__ Einv,
                                     const double* zq, const double* zr, const int32_t* lab_ptr,
                                     double* s, double* sr, double* e, double* er,
                                     const double* red, int ntiles, double* cpart, int d,
@@ -366,21 +366,29 @@ __device__ inline void coarse_block(int blk, int G, const double* __restrict__ E
       if (RP) ss2[c - c0] = v2;
     }
     __syncthreads();
+    // the wave's rows are read together (a row past d reads row d - 1 and is discarded),
+    // so twice as many loads are in flight per wave: the product streams E^-1 from HBM
+    const double* erow[kRowsPerWave];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) erow[r] = Einv + int64_t(min(row0 + r, d - 1)) * d;
+    double a[kRowsPerWave], a2[kRowsPerWave];
+#pragma unroll
+    for (int r = 0; r < kRowsPerWave; ++r) a[r] = a2[r] = 0.0;
+#pragma unroll 8
+    for (int c = c0 + lane; c < c1; c += psl::kWave) {
+      const double sv = ss[c - c0];
+      const double sv2 = RP ? ss2[c - c0] : 0.0;
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; ++r) {
+        const double m = erow[r][c];
+        a[r] += m * sv;
+        if (RP) a2[r] += m * sv2;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < kRowsPerWave; ++r) {
-      const int row = row0 + r;
-      if (row < d) {
-        const double* erow = Einv + int64_t(row) * d;
-        double a = 0.0, a2 = 0.0;
-#pragma unroll 8
-        for (int c = c0 + lane; c < c1; c += psl::kWave) {
-          const double m = erow[c];
-          a += m * ss[c - c0];
-          if (RP) a2 += m * ss2[c - c0];
-        }
-        racc[r] += a;
-        racc2[r] += a2;
-      }
+      racc[r] += a[r];
+      racc2[r] += a2[r];
     }
   }
   double part[1 + NQ];
@@ -456,7 +464,7 @@ __device__ inline int ld_uniform(const int32_t* p) {
   return *(const CI*)p;   // read-only during the launch: one scalar load
 }
 
-__device__ inline void face_prefetch(int t, const int32_t* az_ptr, const int32_t* az_cell,
+__device__ __forceinline__ void face_prefetch(int t, const int32_t* az_ptr, const int32_t* az_cell,
                                      const int32_t* az_lab, const int32_t* az_oth,
                                      const float* az_t32, const double* az_t64, bool skip,
                                      FaceRound& f) {
@@ -475,7 +483,7 @@ __device__ inline void face_prefetch(int t, const int32_t* az_ptr, const int32_t
 }
 
 template <bool TWO>
-__device__ inline void tile_correction(const Tile& T, const FaceRound& f, const int32_t* az_cell,
+__device__ __forceinline__ void tile_correction(const Tile& T, const FaceRound& f, const int32_t* az_cell,
                                        const int32_t* az_lab, const int32_t* az_oth,
                                        const float* az_t32, const double* az_t64,
                                        const double* e1, const double* e2, double* corr1,
@@ -551,7 +559,7 @@ __device__ inline void tile_correction(const Tile& T, const FaceRound& f, const 
 // coefficients (kernel timing only).
 // ---------------------------------------------------------------------------------------
 template <typename R, int RP, int CPT, int PAR>
-__device__ inline void cg_update_tile(int t, bool lead_block, Geo g, const R* __restrict__ v,
+__device__ __forceinline__ void cg_update_tile(int t, bool lead_block, Geo g, const R* __restrict__ v,
                                       R* __restrict__ r, R* __restrict__ u, R* __restrict__ p,
                                       R* __restrict__ q, R* __restrict__ x,
                                       const R* __restrict__ invd, const int32_t* az_ptr,
@@ -774,7 +782,7 @@ __device__ inline R axpy(R a, R x, R y) {   // a x + y, contracted the same way 
 }
 
 template <typename R, int NS, int CPT, int PAR>
-__device__ inline void sd_stencil_tile(int t, bool lead_block, Geo g, const R* __restrict__ Tx,
+__device__ __forceinline__ void sd_stencil_tile(int t, bool lead_block, Geo g, const R* __restrict__ Tx,
                                        const R* __restrict__ Ty, const R* __restrict__ Tz,
                                        const R* __restrict__ u, const R* __restrict__ pprev,
                                        R* __restrict__ p, R* __restrict__ q,
@@ -921,7 +929,7 @@ __global__ void __launch_bounds__(kBlock)
 // itself, once); the workgroup's (r, u), (r, r) partials go to upart[pidx] and
 // upart[pcount + pidx].
 template <typename R, int CPT, int PAR>
-__device__ inline void sd_update_tiles(int tb0, int step, int pidx, int pcount, bool lead_block,
+__device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int pcount, bool lead_block,
                                        Geo g, const R* __restrict__ q, R* __restrict__ r,
                                        R* __restrict__ u, const R* __restrict__ p,
                                        R* __restrict__ x, const R* __restrict__ invd,
@@ -1046,17 +1054,42 @@ __global__ void __launch_bounds__(kBlock)
 // sums and tests the pass workgroups make themselves without them).
 // finish_b, before the stencil pass: rho = (r, M^-1 r) and ||r||^2 from the update
 // partials, stop test, beta = rho / rho_prev into the PAR slot.
-template <int PAR>
-__device__ inline void sd_finish_b(const double* upart, int GU, Scalars* sc) {
-  __shared__ double lds2[2 * kNW];
+template <int PAR, int NT>
+__device__ __forceinline__ void sd_finish_b(const double* upart, int GU, Scalars* sc) {
+  constexpr int NWT = NT / psl::kWave;
+  __shared__ double lds2[2 * NWT];
   if (sc->done) return;
-  double rs[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < GU; i += kBlock) {
-    rs[0] += upart[i];
-    rs[1] += upart[GU + i];
+  // eight independent partial sums per thread keep eight load pairs in flight; waves
+  // combine in a fixed order (the result does not depend on timing)
+  double a0[8], a1[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a0[u] = a1[u] = 0.0;
+  for (int i0 = threadIdx.x; i0 < GU; i0 += 8 * NT) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT;
+      if (i < GU) {
+        a0[u] += upart[i];
+        a1[u] += upart[GU + i];
+      }
+    }
   }
-  psl::block_sum<2>(rs, lds2);
+  double r0 = ((a0[0] + a0[1]) + (a0[2] + a0[3])) + ((a0[4] + a0[5]) + (a0[6] + a0[7]));
+  double r1 = ((a1[0] + a1[1]) + (a1[2] + a1[3])) + ((a1[4] + a1[5]) + (a1[6] + a1[7]));
+  r0 = psl::wave_sum(r0);
+  r1 = psl::wave_sum(r1);
+  const int w = threadIdx.x / psl::kWave;
+  if ((threadIdx.x & (psl::kWave - 1)) == 0) {
+    lds2[w] = r0;
+    lds2[NWT + w] = r1;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double rs[2] = {0.0, 0.0};
+  for (int k = 0; k < NWT; ++k) {
+    rs[0] += lds2[k];
+    rs[1] += lds2[NWT + k];
+  }
   const double rho = rs[0], rr = rs[1];
   const int cnt = sc->cnt[PAR ^ 1];
   if (!(rr < INFINITY) || !(fabs(rho) < INFINITY)) {
@@ -1079,14 +1112,14 @@ __device__ inline void sd_finish_b(const double* upart, int GU, Scalars* sc) {
 }
 
 template <int PAR>
-__global__ void __launch_bounds__(kBlock) k_sd_finish_b(const double* upart, int GU, Scalars* sc) {
-  sd_finish_b<PAR>(upart, GU, sc);
+__global__ void __launch_bounds__(1024) k_sd_finish_b(const double* upart, int GU, Scalars* sc) {
+  sd_finish_b<PAR, 1024>(upart, GU, sc);
 }
 
 // finish_a, before the update pass: (p, P1 A p) = (p, q) - s^T e from the coarse partials,
 // breakdown test, alpha = rho / (p, P1 A p) into the PAR slot.
 template <int PAR>
-__device__ inline void sd_finish_a(const double* cpart, int G, Scalars* sc) {
+__device__ __forceinline__ void sd_finish_a(const double* cpart, int G, Scalars* sc) {
   if (sc->done || threadIdx.x >= psl::kWave) return;
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < G; i += psl::kWave) {
@@ -1644,7 +1677,7 @@ void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
 template <typename R, int PAR>
 void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
   if (c->pre)
-    hipLaunchKernelGGL(k_sd_finish_b<PAR>, dim3(1), dim3(kBlock), 0, st, c->upart,
+    hipLaunchKernelGGL(k_sd_finish_b<PAR>, dim3(1), dim3(1024), 0, st, c->upart,
                        c->upd_blocks, c->sc);
   prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
   with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, 0);
@@ -3302,7 +3335,7 @@ __global__ void __launch_bounds__(kBlock)
 template <int PAR>
 __global__ void __launch_bounds__(kBlock) k_b_sd_finish_b(const SysArgs* __restrict__ sa) {
   const SysArgs& A = sa[blockIdx.x];
-  sd_finish_b<PAR>(A.upart, A.g.ntiles, A.sc);
+  sd_finish_b<PAR, kBlock>(A.upart, A.g.ntiles, A.sc);
 }
 
 template <int NS, int CPT, int PAR>

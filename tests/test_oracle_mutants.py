@@ -41,8 +41,12 @@ MUTANTS = {
     "components_ignore_class": ("key = (sub * ncls + c).reshape(nz, ny, nx)",
                                 "key = (sub * ncls + 0 * c).reshape(nz, ny, nx)"),
     "components_no_z_faces": ("for axis in (2, 1, 0):", "for axis in (2, 1):"),
-    "gmres_left_preconditioned": ("w = P1(A @ Minv(V[:, j]))", "w = Minv(P1(A @ V[:, j]))"),
-    "gmres_update_without_Minv": ("xm = xm + Minv(V[:, :j_end] @ u)", "xm = xm + V[:, :j_end] @ u"),
+    "gmres_left_preconditioned": ("        return P1(A @ Minv(v))", "        return Minv(P1(A @ v))"),
+    "gmres_update_without_Minv": ("xm = xm + Minv(np.array(basis[:k]).T @ y)",
+                                  "xm = xm + np.array(basis[:k]).T @ y"),
+    "gmres_rotation_sign": ("            g[k + 1] = -sn[k] * g[k]", "            g[k + 1] = sn[k] * g[k] * 0.5"),
+    "gmres_earlier_rotations_skipped": ("            for i in range(k):\n                h[i], h[i + 1]",
+                                        "            for i in range(0):\n                h[i], h[i + 1]"),
     "gmres_no_projection_back": ("x = xm + coarse.correction(b - A @ xm)", "x = xm.copy()"),
     "cheb_rho_sign": ("rho_next = 1.0 / (2.0 * sigma - rho)", "rho_next = 1.0 / (2.0 * sigma + rho)"),
     "cheb_step_without_jacobi": ("(2.0 * rho_next / delta) * (res / dg)", "(2.0 * rho_next / delta) * res"),
