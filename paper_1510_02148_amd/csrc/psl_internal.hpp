@@ -44,6 +44,7 @@ struct Scalars {
   int32_t status;    // PSL_OK or failure code raised on device
   int32_t maxit;     // iteration budget for this inner solve
   int32_t stop_par;  // parity of the launch that ended the last two-reduction inner solve
+  int32_t stalled;   // the one-workgroup inner solve stopped without halving ||r|| in a window
 };
 
 template <typename R>
@@ -82,6 +83,9 @@ struct psl_ctx {
   int nslot_max = 0;
   int tile_max = 0;                   // cells per tile (<= 2048)
   int cpt = 1;                        // cells per thread = ceil(tile_max / kBlock)
+  int small = 0;                      // float64 inner solves in one workgroup (small grids)
+  int16_t* small_lptr = nullptr;      // its label-major cell lists: [d + 1] offsets
+  uint16_t* small_lcell = nullptr;    // [n] cells
   int pre = 0;                        // CG step decisions in one-workgroup finish kernels
                                       // (the pass kernels read the coefficients)
   int nsub[3] = {1, 1, 1};

@@ -1671,6 +1671,9 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   // coarse workgroups stage all of s (d <= 4096 doubles of LDS) and each re-sums the
   // label partials; beyond ~4M partial reads a separate reduction kernel is cheaper
   c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
+  // grids up to 4096 cells with up to 32 vectors: float64 inner solves in one workgroup
+  // (the iteration's vectors in LDS, no launch per iteration)
+  c->small = (n <= 4096) && (d <= 32);
   const int64_t dd = int64_t(d) * d;
   double* Lw = nullptr;
   if (dalloc(c, &c->E, dd) || dalloc(c, &c->Einv, dd) || dalloc(c, &Lw, dd) ||

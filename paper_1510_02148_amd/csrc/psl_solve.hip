@@ -1380,6 +1380,274 @@ __global__ void k_zero(double* x, int n) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Small grids (n <= 4096 cells, d <= 32 vectors): the whole float64 inner solve in one
+// workgroup of 1024 threads, the same single-reduction DEF1-PCG as the three-launch loop,
+// with no launch or host check per iteration. Each thread owns four cells: their r and p
+// stay in its registers; M^-1 r and A M^-1 r (read by neighbours and by other waves),
+// P1 A p and xhat live in LDS (CDNA4 gives a workgroup up to 160 KiB), with E^-1, the
+// labels and each label's cell list (built once per context by k_small_lists); the face
+// values and the inverse diagonal are re-read from cache each iteration (holding them in
+// registers would spill). Z^T v and E^-1 s take 32 lanes per label or row; A Z e is
+// evaluated per cell from the neighbours' labels; the four dot products go through two
+// paired workgroup sums. Every sum has a fixed order.
+// ---------------------------------------------------------------------------------------
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallCells = 4096;
+constexpr int kSmallD = 32;
+constexpr int kSmallW = kSmallThreads / psl::kWave;
+
+// two workgroup sums at once (fixed order: wave trees, then the waves in order); red
+// holds 2 * kSmallW doubles; every thread gets both results
+__device__ inline void small_block_sum2(double& a, double& b, double* red) {
+  a = psl::wave_sum(a);
+  b = psl::wave_sum(b);
+  const int w = threadIdx.x / psl::kWave;
+  __syncthreads();
+  if ((threadIdx.x & (psl::kWave - 1)) == 0) {
+    red[w] = a;
+    red[kSmallW + w] = b;
+  }
+  __syncthreads();
+  a = b = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSmallW; ++k) {
+    a += red[k];
+    b += red[kSmallW + k];
+  }
+}
+
+// sum over the 32 lanes of a half wave (fixed tree), result in all of them
+__device__ inline double half_wave_sum(double v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, psl::kWave);
+  return v;
+}
+
+// label-major cell lists of a small grid, each label's cells in cell order: a wave ballot
+// per label gives each cell its rank among the equal-labelled cells of its wave, and the
+// per-wave counts (in cell order of the waves) give the offsets
+__global__ void __launch_bounds__(kSmallThreads)
+    k_small_lists(int n, int d, const int32_t* __restrict__ labels, int16_t* __restrict__ lptr,
+                  uint16_t* __restrict__ lcell) {
+  constexpr int CPT = kSmallCells / kSmallThreads, NW = CPT * kSmallW;
+  __shared__ int cnt[NW][kSmallD];   // [wave chunk][label], chunk = k * kSmallW + wave
+  __shared__ int base[kSmallD + 1];
+  const int tid = threadIdx.x, lane = tid & (psl::kWave - 1), wv = tid / psl::kWave;
+  int lk[CPT], rk[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * kSmallThreads;
+    lk[k] = c < n ? labels[c] : -1;
+    rk[k] = 0;
+    for (int l = 0; l < d; ++l) {
+      const unsigned long long m = __ballot(lk[k] == l);
+      if (lk[k] == l) rk[k] = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) cnt[k * kSmallW + wv][l] = __popcll(m);
+    }
+  }
+  __syncthreads();
+  if (tid < d) {   // exclusive prefix over the chunks, per label
+    int a = 0;
+    for (int w = 0; w < NW; ++w) {
+      const int t = cnt[w][tid];
+      cnt[w][tid] = a;
+      a += t;
+    }
+    base[tid + 1] = a;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    base[0] = 0;
+    for (int l = 0; l < d; ++l) base[l + 1] += base[l];
+  }
+  __syncthreads();
+  if (tid <= d) lptr[tid] = int16_t(base[tid]);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+    if (lk[k] >= 0)
+      lcell[base[lk[k]] + cnt[k * kSmallW + wv][lk[k]] + rk[k]] = uint16_t(tid + k * kSmallThreads);
+}
+
+__global__ void __launch_bounds__(kSmallThreads)
+    k_small_cg(int nx, int ny, int nz, const double* __restrict__ Tx, const double* __restrict__ Ty,
+               const double* __restrict__ Tz, const int32_t* __restrict__ labels,
+               const int16_t* __restrict__ lptr_g, const uint16_t* __restrict__ lcell_g,
+               const double* __restrict__ invd, const double* __restrict__ Einv, int d,
+               const double* __restrict__ r64, double* __restrict__ rh, double* __restrict__ xh,
+               Scalars* sc) {
+  constexpr int CPT = kSmallCells / kSmallThreads;
+  __shared__ double ul[kSmallCells];               // M^-1 r
+  __shared__ double vl[kSmallCells];               // A M^-1 r
+  __shared__ double xl[kSmallCells];               // xhat
+  __shared__ double ql[kSmallCells];               // P1 A p
+  __shared__ uint16_t lcell[kSmallCells];          // cells grouped by label, each in cell order
+  __shared__ int16_t lptr[kSmallD + 1];
+  __shared__ uint8_t lab[kSmallCells];
+  __shared__ double El[kSmallD * kSmallD];
+  __shared__ double sv[kSmallD], ev[kSmallD];
+  __shared__ double red[4 * kSmallW];
+  const int n = nx * ny * nz, sxy = nx * ny, tid = threadIdx.x;
+  // ---- set-up: labels, cell lists and E^-1 into LDS
+  for (int c = tid; c < n; c += kSmallThreads) {
+    lab[c] = uint8_t(labels[c]);
+    lcell[c] = lcell_g[c];
+  }
+  for (int i = tid; i < d * d; i += kSmallThreads) El[i] = Einv[i];
+  if (tid <= d) lptr[tid] = lptr_g[tid];
+  // a thread's cells are tid + k * kSmallThreads; r and p stay in registers (only the
+  // cell's own thread reads them), M^-1 r and A M^-1 r (read by neighbours and other
+  // waves), xhat and P1 A p in LDS
+  int fxk[CPT], fyk[CPT], nb[CPT];   // face indices; neighbour flags (bit 0..5: -x +x -y +y -z +z)
+  double rk[CPT], pk[CPT];
+  const int off[6] = {-1, 1, -nx, nx, -sxy, sxy};
+  const double sigma = sc->sigma;
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * kSmallThreads;
+    nb[k] = 0;
+    fxk[k] = fyk[k] = 0;
+    rk[k] = pk[k] = 0.0;
+    if (c < n) {
+      const int ix = c % nx, iy = (c / nx) % ny, iz = c / sxy;
+      fxk[k] = c + (iy + ny * iz);
+      fyk[k] = c + nx * iz;
+      nb[k] = (ix > 0) | ((ix < nx - 1) << 1) | ((iy > 0) << 2) | ((iy < ny - 1) << 3) |
+              ((iz > 0) << 4) | ((iz < nz - 1) << 5);
+      // start: r = sigma r64, u = M^-1 r, x = p = q = 0; (r, u), (r, r)
+      rk[k] = sigma * r64[c];
+      const double uv = rk[k] * invd[c];
+      ul[c] = uv;
+      xl[c] = 0.0;
+      ql[c] = 0.0;
+      d1 += rk[k] * uv;
+      d2 += rk[k] * rk[k];
+    }
+  }
+  small_block_sum2(d1, d2, red);
+  double ru = d1, rr = d2;
+  double gprev = INFINITY, aprev = 1.0, best = INFINITY;
+  int it = 0, best_it = 0, status = PSL_OK, stalled = 0;
+  const double goal2 = sc->goal2;
+  const int maxit = sc->maxit;
+  for (;;) {
+    // v = A u (flux form, zero across outer faces)
+    double d0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int c = tid + k * kSmallThreads;
+      if (c >= n) continue;
+      int fx = fxk[k], fy = fyk[k], fz = c;
+      asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz));   // reload faces (cached), not hoisted
+      const double tf[6] = {Tx[fx], Tx[fx + 1], Ty[fy], Ty[fy + nx], Tz[fz], Tz[fz + sxy]};
+      const double u0 = ul[c];
+      double a = 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) a += tf[f] * (u0 - ((nb[k] >> f) & 1 ? ul[c + off[f]] : 0.0));
+      vl[c] = a;
+      d0 += a * u0;
+    }
+    __syncthreads();   // publishes vl
+    // s = Z^T v: 32 lanes per label (over its cells, then a fixed-order half-wave sum)
+    const int g = tid >> 5, gl = tid & 31;   // half-wave group and its lane
+    if (g < d) {
+      double a = 0.0;
+      for (int i = lptr[g] + gl; i < lptr[g + 1]; i += 32) a += vl[lcell[i]];
+      a = half_wave_sum(a);
+      if (gl == 0) sv[g] = a;
+    }
+    __syncthreads();
+    // e = E^-1 s: 32 lanes per row (one column each), and s^T e with (v, u) in one sum
+    double se = 0.0;
+    if (g < d) {
+      double a = gl < d ? El[g * d + gl] * sv[gl] : 0.0;
+      a = half_wave_sum(a);
+      if (gl == 0) {
+        ev[g] = a;
+        se = a * sv[g];
+      }
+    }
+    small_block_sum2(d0, se, red);   // also publishes ev
+    const double vu = d0, ste = se;
+    // step decision (every thread takes the same one from the same sums)
+    const double gamma = ru, delta = vu - ste;
+    double alpha = 0.0, beta = 0.0;
+    bool go = true;
+    if (!(rr < INFINITY) || !(fabs(gamma) < INFINITY) || !(fabs(delta) < INFINITY)) {
+      go = false;
+      status = PSL_ENONFINITE;
+    } else if (rr <= goal2 || it >= maxit) {
+      go = false;
+    } else {
+      if (rr < 0.25 * best) {
+        best = rr;
+        best_it = it;
+      } else if (it - best_it >= 512) {
+        stalled = 1;
+        go = false;
+      }
+      if (go) {
+        beta = gamma / gprev;
+        const double den = delta - beta * gamma / aprev;
+        if (!(den > 0.0)) {
+          go = false;
+          status = PSL_EBREAKDOWN;
+        } else {
+          alpha = gamma / den;
+          gprev = gamma;
+          aprev = alpha;
+        }
+      }
+    }
+    if (!go) break;
+    // w = v - A Z e; p, q, x, r, u; (r, u), (r, r) of the new residual
+    d1 = d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int c = tid + k * kSmallThreads;
+      if (c >= n) continue;
+      int fx = fxk[k], fy = fyk[k], fz = c;
+      asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz));   // reload faces (cached), not hoisted
+      const double tf[6] = {Tx[fx], Tx[fx + 1], Ty[fy], Ty[fy + nx], Tz[fz], Tz[fz + sxy]};
+      const double dk = invd[fz];
+      const double ec = ev[lab[c]];
+      double az = 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+        az += tf[f] * (ec - ((nb[k] >> f) & 1 ? ev[lab[c + off[f]]] : 0.0));
+      const double qn = (vl[c] - az) + beta * ql[c];
+      ql[c] = qn;
+      pk[k] = ul[c] + beta * pk[k];
+      xl[c] += alpha * pk[k];
+      rk[k] -= alpha * qn;
+      const double un = rk[k] * dk;
+      ul[c] = un;
+      d1 += rk[k] * un;
+      d2 += rk[k] * rk[k];
+    }
+    ++it;
+    small_block_sum2(d1, d2, red + 2 * kSmallW);   // its barriers also publish ul
+    ru = d1;
+    rr = d2;
+  }
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * kSmallThreads;
+    if (c < n) {
+      rh[c] = rk[k];
+      xh[c] = xl[c];
+    }
+  }
+  if (tid == 0) {
+    sc->iters = it;
+    sc->rr = rr;
+    sc->status = status;
+    sc->stalled = stalled;
+    sc->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
 inline Geo geo(const psl_ctx* c) { return Geo{c->nx, c->ny, c->nz, c->ntiles, c->tiles}; }
@@ -1791,6 +2059,28 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
   if (rc != PSL_OK) return rc;
   psl::VecSet<R>& v = Prec<R>::vecs(c);
   const int chunk = check_every + (check_every & 1);  // parity pattern needs an even count
+  if (std::is_same<R, double>::value && form == kFormSingle && !rp && c->small &&
+      c->prof_kernel < 0) {
+    // small grid: the whole inner solve in one workgroup, one host read at its end
+    hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit);
+    if (!c->small_lcell) {
+      if (psl_ctx_alloc(c, reinterpret_cast<void**>(&c->small_lcell), 2 * size_t(c->n)) ||
+          psl_ctx_alloc(c, reinterpret_cast<void**>(&c->small_lptr), 2 * size_t(c->d + 1)))
+        return PSL_ENOMEM;
+      hipLaunchKernelGGL(k_small_lists, dim3(1), dim3(kSmallThreads), 0, st, int(c->n), c->d, c->labels,
+                         c->small_lptr, c->small_lcell);
+    }
+    hipLaunchKernelGGL(k_small_cg, dim3(1), dim3(kSmallThreads), 0, st, c->nx, c->ny, c->nz,
+                       c->Tx, c->Ty, c->Tz, c->labels, c->small_lptr, c->small_lcell,
+                       c->invdiag, c->Einv, c->d, c->r64, c->v64.rh, c->v64.xh, c->sc);
+    if ((rc = read_scalars(c, st)) != PSL_OK) return rc;
+    *iters = c->h_sc->iters;
+    *status = c->h_sc->status;
+    *stalled = c->h_sc->stalled;
+    hipLaunchKernelGGL(k_accumulate<double>, dim3(elem_grid(c->n)), dim3(kBlock), 0, st,
+                       int(c->n), x, c->v64.xh, c->sc);
+    return PSL_OK;
+  }
   if (form == kFormTwo) {
     hipLaunchKernelGGL(k_sd_set, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit, fresh);
     hipLaunchKernelGGL(k_sd_init<R>, dim3(c->upd_blocks), dim3(kBlock), 0, st, geo(c), c->r64,
