@@ -110,11 +110,17 @@ def counter_traffic(kernel: str, workload: str, mode: str):
                 (kernel, workload, mode):
             continue
         src = open(src_path).read()
-        i = src.find(fields.get("source_marker", "\0"))
-        if i < 0:
-            return None
-        body = src[i - 4:src.index("\n}\n", i)]
-        if hashlib.sha256(body.encode()).hexdigest() != fields.get("kernel_source_sha256"):
+        # the kernel and every device function it inlines, each from its marker to the
+        # end of its body
+        markers = fields.get("source_markers", fields.get("source_marker", "\0")).split(" | ")
+        bodies = []
+        for m in markers:
+            i = src.find(m)
+            if i < 0:
+                return None
+            bodies.append(src[i - 4:src.index("\n}\n", i)])
+        if hashlib.sha256("\n".join(bodies).encode()).hexdigest() != \
+                fields.get("kernel_source_sha256"):
             return None
         kib = 1024.0
         return (float(fields["fetch_kib_per_dispatch"]) * float(fields["fetch_factor"]) +
