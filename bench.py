@@ -52,10 +52,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool) -> float:
+def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool,
+                      coarse_sym: bool = False) -> float:
     """Bytes one launch must move at minimum (each array touched once), w = word size.
 
     two=True: the two-reduction loop (float32 path); False: the single-reduction loop.
+    coarse_sym: the coarse product reads the lower triangle of the symmetric E^-1 and
+    writes and re-reads one share of e per (row block, column block) of 64.
     """
     nx, ny, nz = grid
     n = nx * ny * nz
@@ -69,6 +72,9 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
             return 8 * w * n + m_faces * (12 + w)
         return 12 * w * n + m_faces * (12 + w)   # read v, r, u, p, q, x, 1/diag; write 5
     if kernel == "coarse":           # read E^-1 (float64), s; write e
+        if coarse_sym:
+            nb = (d + 63) // 64
+            return 8.0 * d * (d + 1) / 2 + 2 * 8.0 * nb * nb * 64 + 4 * 8 * d
         return 8.0 * d * d + 4 * 8 * d
     if kernel == "cheb_step":         # read y, r, 1/diag, d, T; write y
         return float(w) * (4 * n + faces) + float(w) * n
@@ -93,7 +99,7 @@ SOLVER_TAGS = {
 }
 
 
-def counter_traffic(kernel: str, workload: str, mode: str):
+def counter_traffic(kernel: str, workload: str, mode: str, coarse_sym: int = 0):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary
     (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration), or None when no
     summary covers this kernel, workload and mode or the kernel source changed since."""
@@ -108,6 +114,8 @@ def counter_traffic(kernel: str, workload: str, mode: str):
                 fields[k] = v.strip()
         if (fields.get("bench_kernel"), fields.get("workload"), fields.get("mode")) != \
                 (kernel, workload, mode):
+            continue
+        if kernel == "coarse" and int(fields.get("coarse_sym", "0")) != int(coarse_sym):
             continue
         src = open(src_path).read()
         # the kernel and every device function it inlines, each from its marker to the
@@ -416,6 +424,9 @@ def main():
                     help="Chebyshev interval [2 / ratio, 2] (--solver poly)")
     ap.add_argument("--tiles", default=None,
                     help="tile sizes 'f64,f32' instead of the tuned ones (tuning runs)")
+    ap.add_argument("--coarse", default="auto", choices=["auto", "sym", "dense"],
+                    help="coarse product over the lower block triangle of E^-1 or the dense "
+                         "one (default: the library's choice by d)")
     ap.add_argument("--quick", action="store_true",
                     help="one step, no comparison legs (for profiler counter runs)")
     args = ap.parse_args()
@@ -467,7 +478,8 @@ def main():
         t0 = time.perf_counter()
         s = pipeline.setup(prob.grid, K, prob.dirichlet_mask, prob.nsub, list(prob.thr),
                            tile_cells=tiles["f32" if mode == psl.MIXED else "f64"],
-                           components=args.labels == "components")
+                           components=args.labels == "components",
+                           coarse_sym={"auto": 0, "sym": 1, "dense": -1}[args.coarse])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         if args.solver == "gmres":
@@ -545,7 +557,8 @@ def main():
         # inside real solves: every launch of the kernel in the solve's own precision
         times = in_solve_kernel_times(psl, s.ctx, b, prob.tol, mode, ids)
         for name, t in times.items():
-            nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w, mode == psl.MIXED)
+            nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w, mode == psl.MIXED,
+                                       bool(info["coarse_sym"]))
             kernels[name] = {"us": round(t["us"], 3), "alg_bytes": int(nbytes),
                              "gbs": round(nbytes / (t["us"] * 1e-6) / 1e9, 1),
                              "launches": t["launches"],
@@ -593,7 +606,7 @@ def main():
     else:   # the solver's own pass; the CG stencil is only the SpMV reference there
         dominant = next(k for k in kernels if k != "stencil")
     kd = kernels[dominant]
-    traffic = counter_traffic(dominant, args.workload, args.mode)
+    traffic = counter_traffic(dominant, args.workload, args.mode, int(info["coarse_sym"]))
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
                 "traffic": (round(traffic) if traffic is not None else None),

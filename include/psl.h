@@ -291,7 +291,12 @@ typedef struct {
                            pass workgroup sums the partials itself; 0 (default): 1 for
                            grids of 2^21 cells or more, -1 below (where the extra launches
                            cost more than the repeated sums) */
-  int32_t reserved[6];  /* must be 0 */
+  int32_t coarse_sym;   /* coarse product e = E^-1 s: 1 reads only the lower 64 x 64 block
+                           triangle of the symmetric E^-1 (Def. 3.1: E and so E^-1 are
+                           symmetric), half the bytes of the dense product, and adds the
+                           block shares in a second launch; -1 the dense row-wise product;
+                           0 (default): 1 for d >= 1024, -1 below */
+  int32_t reserved[5];  /* must be 0 */
 } psl_setup_opts;
 
 /* Fill `o` with the defaults (all zero). */
@@ -463,7 +468,8 @@ typedef struct {
   int32_t ntiles;       /* work tiles (one workgroup each) */
   int64_t m_faces;      /* cut faces stored for A Z (faces between labels + Dirichlet) */
   int32_t nslot_max;    /* most distinct labels in one tile */
-  int32_t reserved;
+  int32_t coarse_sym;   /* 1: the coarse product reads the lower block triangle of E^-1
+                           (psl_setup_opts.coarse_sym), 0: the dense product */
 } psl_ctx_info;
 
 int psl_get_info(const psl_ctx* ctx, psl_ctx_info* info);

@@ -15,6 +15,8 @@ constexpr int kBlock = 256;          // threads per workgroup for every cell ker
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kMaxSlots = PSL_MAX_TILE_LABELS;
 constexpr int kCoarseRows = 8;       // coarse GEMV rows per workgroup (two per wave)
+constexpr int kSymBlock = 64;        // block size of the symmetric coarse product
+constexpr int kSymMinD = 1024;       // d from which the coarse product is the symmetric one
 
 // Work tile: a box of cells inside one subdomain; one workgroup per tile.
 struct Tile {
@@ -117,6 +119,10 @@ struct psl_ctx {
   double* Einv = nullptr;             // [d*d]
   int coarse_blocks = 1;              // ceil(d / kCoarseRows) GEMV workgroups
   int coarse_fused = 1;               // coarse workgroups sum s themselves (small d)
+  int coarse_sym = 0;                 // coarse product over the lower block triangle of E^-1
+  int sym_parts = 0;                  // its summing workgroups: ceil(d / (kBlock / 4))
+  double* spart = nullptr;            // its block shares [nb * nb * 64] (nb = ceil(d / 64))
+  double* spart2 = nullptr;           // the same for the second right-hand side
   // work
   double* zq = nullptr;               // [npart] label-major partials of Z^T q (or Z^T r)
   double* zr = nullptr;               // [npart] label-major partials of Z^T rhat

@@ -1493,6 +1493,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   if (so) {
     if (so->tile_cells != 0 && (so->tile_cells < 64 || so->tile_cells > 2048)) return PSL_EINVAL;
     if (so->finish_kernels < -1 || so->finish_kernels > 1) return PSL_EINVAL;
+    if (so->coarse_sym < -1 || so->coarse_sym > 1) return PSL_EINVAL;
     for (int32_t r : so->reserved)
       if (r != 0) return PSL_EINVAL;
   }
@@ -1671,6 +1672,9 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   // coarse workgroups stage all of s (d <= 4096 doubles of LDS) and each re-sums the
   // label partials; beyond ~4M partial reads a separate reduction kernel is cheaper
   c->coarse_fused = (d <= 4096) && (int64_t(c->npart) * c->coarse_blocks <= (int64_t(1) << 22));
+  // large d: the coarse product reads only the lower block triangle of E^-1
+  c->coarse_sym = (so && so->coarse_sym) ? (so->coarse_sym > 0) : (d >= psl::kSymMinD);
+  c->sym_parts = (d + psl::kBlock / 4 - 1) / (psl::kBlock / 4);
   // grids up to 4096 cells with up to 32 vectors: float64 inner solves in one workgroup
   // (the iteration's vectors in LDS, no launch per iteration)
   c->small = (n <= 4096) && (d <= 32);
@@ -1679,9 +1683,15 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   if (dalloc(c, &c->E, dd) || dalloc(c, &c->Einv, dd) || dalloc(c, &Lw, dd) ||
       dalloc(c, &c->zq, std::max(1, c->npart)) || dalloc(c, &c->zr, std::max(1, c->npart)) ||
       dalloc(c, &c->red, int64_t(c->ntiles) * 4) || dalloc(c, &c->s, d) || dalloc(c, &c->e, d) ||
-      dalloc(c, &c->sr, d) || dalloc(c, &c->er, d) || dalloc(c, &c->cpart, 4 * c->coarse_blocks) ||
+      dalloc(c, &c->sr, d) || dalloc(c, &c->er, d) ||
+      dalloc(c, &c->cpart, 4 * std::max(c->coarse_blocks, c->sym_parts)) ||
       dalloc(c, &c->r64, n) || dalloc(c, &c->t64, n) || dalloc(c, &c->sc, 1))
     PSL_FAIL(PSL_ENOMEM);
+  if (c->coarse_sym) {
+    const int64_t nb = (d + psl::kSymBlock - 1) / psl::kSymBlock;
+    if (dalloc(c, &c->spart, nb * nb * psl::kSymBlock) || dalloc(c, &c->spart2, nb * nb * psl::kSymBlock))
+      PSL_FAIL(PSL_ENOMEM);
+  }
   static_assert(sizeof(psl::Scalars) <= 1024, "pinned mirror slot size");
   c->h_sc = static_cast<psl::Scalars*>(psl_internal_pinned_get(sizeof(psl::Scalars)));
   if (!c->h_sc) PSL_FAIL(PSL_ENOMEM);
@@ -1725,6 +1735,6 @@ extern "C" int psl_get_info(const psl_ctx* c, psl_ctx_info* info) {
   info->ntiles = c->ntiles;
   info->m_faces = c->m_az;
   info->nslot_max = c->nslot_max;
-  info->reserved = 0;
+  info->coarse_sym = c->coarse_sym;
   return PSL_OK;
 }

@@ -431,6 +431,155 @@ __global__ void __launch_bounds__(kBlock)
                               ntiles, cpart, d, sc, check_done);
 }
 
+// ---------------------------------------------------------------------------------------
+// Coarse solve through the symmetry of E^-1 (large d): only its lower block triangle
+// (kSB x kSB blocks) is read, once per solve step, half the bytes of the dense product.
+// Workgroup t takes block B = E^-1[I, J], J <= I (t = I (I + 1) / 2 + J): its row sums
+// B s_J are column block J's share of e over the rows of block I; for I > J its column
+// sums B^T s_I are column block I's share of e over the rows of block J (E^-1[J, I] =
+// B^T). Shares land in spart[(X nb + Y) kSB + r] (row block X, column block Y, each pair
+// written once); k_symv_sum adds them in column-block order, so e is run to run
+// identical. The workgroup sums its two blocks' entries of s from the label partials (the
+// diagonal blocks also store s for the summing kernel and the callers).
+// ---------------------------------------------------------------------------------------
+constexpr int kSB = psl::kSymBlock;
+constexpr int kSBRows = kSB / kNW;   // block rows per wave
+
+__device__ inline void sym_block_of(int t, int& I, int& J) {
+  int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+template <int RP>
+__global__ void __launch_bounds__(kBlock)
+    k_symv_blocks(const double* __restrict__ Einv, const double* zq, const double* zr,
+                  const int32_t* lab_ptr, double* s, double* sr, double* __restrict__ spart,
+                  double* __restrict__ spart2, int d, int nb, const Scalars* sc,
+                  int check_done) {
+  constexpr int NV = RP ? 2 : 1;
+  __shared__ double sv[NV][2][kSB];             // [rhs][0: block I, 1: block J][entry]
+  __shared__ double tr[NV][kSB][kSB + 1];       // products for the row sums
+  __shared__ double cs[NV][kNW][kSB];           // per-wave column sums
+  if (check_done && sc->done) return;
+  int I, J;
+  sym_block_of(blockIdx.x, I, J);
+  const int tid = threadIdx.x, c = tid & (kSB - 1), w = tid / psl::kWave;
+  // the block's loads first (a wave reads kSBRows whole 512-byte rows), so they are in
+  // flight while the coarse entries are gathered
+  const int col = J * kSB + c;
+  double m[kSBRows];
+#pragma unroll
+  for (int k = 0; k < kSBRows; ++k) {
+    const int row = I * kSB + w * kSBRows + k;
+    m[k] = (row < d && col < d) ? Einv[int64_t(row) * d + col] : 0.0;
+  }
+  if (tid < 2 * kSB) {
+    const int side = tid / kSB, k = tid & (kSB - 1);
+    const int l = (side ? J : I) * kSB + k;
+    double v = 0.0, v2 = 0.0;
+    if (l < d) {
+      v = label_sum(zq, lab_ptr, l);
+      if (RP) v2 = label_sum(zr, lab_ptr, l);
+      if (I == J && side == 0) {
+        s[l] = v;
+        if (RP) sr[l] = v2;
+      }
+    }
+    sv[0][side][k] = v;
+    if (RP) sv[NV - 1][side][k] = v2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double sj = sv[q][1][c];
+    double ca = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSBRows; ++k) {
+      const int r = w * kSBRows + k;
+      tr[q][r][c] = m[k] * sj;
+      ca += m[k] * sv[q][0][r];
+    }
+    cs[q][w][c] = ca;
+  }
+  __syncthreads();
+  // row sums: four threads per row, sixteen entries each, then the four in a fixed tree
+  // (a + b is exact-commutative, so every lane of the four holds the same sum)
+  const int r = tid >> 2, qt = tid & 3;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < kSB / 4; ++j) a += tr[q][r][qt * (kSB / 4) + j];
+    a += __shfl_xor(a, 1, psl::kWave);
+    a += __shfl_xor(a, 2, psl::kWave);
+    double* dst = q ? spart2 : spart;
+    if (qt == 0) dst[(int64_t(I) * nb + J) * kSB + r] = a;
+    if (I != J && tid < kSB) {
+      double b = 0.0;
+#pragma unroll
+      for (int k = 0; k < kNW; ++k) b += cs[q][k][tid];
+      dst[(int64_t(J) * nb + I) * kSB + tid] = b;
+    }
+  }
+}
+
+// e (and er) from the block shares, four threads per row (each over every fourth column
+// block, then a fixed two-step tree); per workgroup g of G, the same partials as the
+// dense coarse kernel: cpart[g] = sum over its rows of s_r e_r, and for q < NQ
+// cpart[(1 + q) G + g] = its slice of the tile partials red[q * ntiles + .]
+constexpr int kSymSumRows = kBlock / 4;
+
+template <int RP, int NQ>
+__global__ void __launch_bounds__(kBlock)
+    k_symv_sum(const double* __restrict__ spart, const double* __restrict__ spart2,
+               const double* s, double* e, double* er, const double* red, int ntiles,
+               double* cpart, int d, int nb, const Scalars* sc, int check_done) {
+  __shared__ double lds[(1 + NQ) * kNW];
+  if (check_done && sc->done) return;
+  const int G = gridDim.x, blk = blockIdx.x;
+  const int row = blk * kSymSumRows + (threadIdx.x >> 2), qt = threadIdx.x & 3;
+  double part[1 + NQ];
+#pragma unroll
+  for (int q = 0; q <= NQ; ++q) part[q] = 0.0;
+  double a = 0.0, a2 = 0.0;
+  if (row < d) {
+    const int64_t base = int64_t(row / kSB) * nb * kSB + (row & (kSB - 1));
+#pragma unroll 4
+    for (int Y = qt; Y < nb; Y += 4) {
+      a += spart[base + int64_t(Y) * kSB];
+      if (RP) a2 += spart2[base + int64_t(Y) * kSB];
+    }
+  }
+  // the four lanes of a row are adjacent: every one of them ends with the same sum
+  a += __shfl_xor(a, 1, psl::kWave);
+  a += __shfl_xor(a, 2, psl::kWave);
+  if (RP) {
+    a2 += __shfl_xor(a2, 1, psl::kWave);
+    a2 += __shfl_xor(a2, 2, psl::kWave);
+  }
+  if (row < d && qt == 0) {
+    e[row] = a;
+    if (RP) er[row] = a2;
+    part[0] = a * s[row];
+  }
+  const int ta = int((int64_t(ntiles) * blk) / G);
+  const int tb = int((int64_t(ntiles) * (blk + 1)) / G);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    for (int t = ta + threadIdx.x; t < tb; t += kBlock) part[1 + q] += red[q * ntiles + t];
+  psl::block_sum<1 + NQ>(part, lds);
+  if (threadIdx.x <= NQ) {
+    double val = part[0];
+#pragma unroll
+    for (int q = 1; q <= NQ; ++q)
+      if (int(threadIdx.x) == q) val = part[q];
+    cpart[threadIdx.x * G + blk] = val;
+  }
+}
+
 // Per tile: corr[local cell] = (A Z v)_cell = sum over its cut faces of T (v_l - v_other)
 // (v_other = 0 across an outer face; 0 on cells without a cut face), for one coarse vector
 // (e1 -> corr1) or two at once (e2 -> corr2; skipped when e2 is null). The tile's faces are
@@ -1772,9 +1921,25 @@ struct CgStencilL {
   };
 };
 
+// workgroup entries per quantity in cpart for single-system solves
+inline int coarse_parts(const psl_ctx* c) { return c->coarse_sym ? c->sym_parts : c->coarse_blocks; }
+
 // s (and sr) from the partials, then e (and er) = E^-1 s; coarse partials in cpart
+// (coarse_parts(c) workgroup entries per quantity)
 template <int RP, int NQ>
 void launch_coarse(psl_ctx* c, int check_done, hipStream_t st) {
+  if (c->coarse_sym) {
+    // each block workgroup sums only its two blocks' entries of s (128 labels), so the
+    // label sums stay in it at any d
+    const int nb = (c->d + kSB - 1) / kSB;
+    hipLaunchKernelGGL((k_symv_blocks<RP>), dim3(nb * (nb + 1) / 2), dim3(kBlock), 0, st,
+                       c->Einv, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->spart, c->spart2,
+                       c->d, nb, c->sc, check_done);
+    hipLaunchKernelGGL((k_symv_sum<RP, NQ>), dim3(c->sym_parts), dim3(kBlock), 0, st, c->spart,
+                       c->spart2, c->s, c->e, c->er, c->red, c->ntiles, c->cpart, c->d, nb,
+                       c->sc, check_done);
+    return;
+  }
   if (c->coarse_fused) {
     hipLaunchKernelGGL((k_coarse<RP, 1, NQ>), dim3(c->coarse_blocks), dim3(kBlock), 0, st,
                        c->Einv, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->e, c->er, c->red,
@@ -1797,7 +1962,7 @@ struct CgUpdateC {
       hipLaunchKernelGGL((k_cg_update<R, RP, CPT, PAR>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), v.v, v.rh, v.u, v.p, v.q, v.xh, Prec<R>::invd(c), c->az_ptr,
                          c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e, c->er,
-                         c->cpart, c->coarse_blocks, c->sc, bench, c->pre);
+                         c->cpart, coarse_parts(c), c->sc, bench, c->pre);
     }
   };
 };
@@ -1843,7 +2008,7 @@ struct SdUpdateC {
       hipLaunchKernelGGL((k_sd_update<R, CPT, PAR>), dim3(c->upd_blocks), dim3(kBlock), 0, st,
                          geo(c), v.q, v.rh, v.u, PAR ? v.p2 : v.p, v.xh, Prec<R>::invd(c),
                          c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
-                         c->cpart, c->coarse_blocks, c->upart, c->sc, bench, c->pre);
+                         c->cpart, coarse_parts(c), c->upart, c->sc, bench, c->pre);
     }
   };
 };
@@ -1921,7 +2086,7 @@ void enqueue_iteration(psl_ctx* c, hipStream_t st) {
   prof_end<R>(c, PSL_KERNEL_COARSE, st);
   if (c->pre)
     hipLaunchKernelGGL(k_cg_finish<PAR>, dim3(1), dim3(psl::kWave), 0, st, c->cpart,
-                       c->coarse_blocks, c->sc);
+                       coarse_parts(c), c->sc);
   prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<CgUpdateC<R, RP, PAR>::template F>(c->cpt, c, st, 0);
   prof_end<R>(c, PSL_KERNEL_UPDATE, st);
@@ -1955,7 +2120,7 @@ void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
   prof_end<R>(c, PSL_KERNEL_COARSE, st);
   if (c->pre)
     hipLaunchKernelGGL(k_sd_finish_a<PAR>, dim3(1), dim3(psl::kWave), 0, st, c->cpart,
-                       c->coarse_blocks, c->sc);
+                       coarse_parts(c), c->sc);
   prof_begin<R>(c, PSL_KERNEL_UPDATE, st);
   with_cpt<SdUpdateC<R, PAR>::template F>(c->cpt, c, st, 0);
   prof_end<R>(c, PSL_KERNEL_UPDATE, st);
@@ -3333,7 +3498,7 @@ void pc_iteration(psl_ctx* c, const PcBufsT<R>& B, const PcPlan& pl, R* x, hipSt
   launch_coarse<0, 0>(c, 0, st);
   hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(kBlock), 0, st, B.s,
                      static_cast<const double*>(red(c, 0)), c->ntiles,
-                     static_cast<const double*>(c->cpart), c->coarse_blocks);
+                     static_cast<const double*>(c->cpart), coarse_parts(c));
   hipLaunchKernelGGL((k_pc_update<R>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
                      static_cast<const int32_t*>(c->az_ptr), static_cast<const int32_t*>(c->az_cell),
                      static_cast<const int32_t*>(c->az_lab), static_cast<const int32_t*>(c->az_oth),

@@ -5,6 +5,7 @@ within a few ulps of |A||p|; solves reach ||b - A x|| / ||b|| <= 1e-8 (residual 
 by the oracle's own matrix from the GPU x) and ||x - x_ref|| / ||x_ref|| <= 1e-6 with
 x_ref a direct solve (small) or the oracle at tol 1e-12.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -890,3 +891,80 @@ def test_finish_kernels(gpu_lib, name, scale, kw, mode):
         assert abs(st1["iters"] - ref.iters) <= max(2, 0.02 * ref.iters)
     else:
         assert abs(st1["iters"] - st0["iters"]) <= 1
+
+
+SYM_CASES = [("c2", 4, {}, None), ("ragged", 0, {}, None),
+             ("c3", 4, {"contrast": 1e5}, (16, 16, 12))]
+
+
+@pytest.mark.parametrize("name,scale,kw,nsub", SYM_CASES,
+                         ids=["c2-4", "ragged-0", "c3-4-d5115"])
+def test_coarse_symmetric(gpu_lib, name, scale, kw, nsub):
+    """The coarse product over the lower block triangle of the symmetric E^-1 (Def. 3.1;
+    the large-d configuration, forced on here) against the dense row-wise product on the
+    same context set-up, and both against the oracle: float64 (with and without the
+    per-iteration re-projection, which takes the second right-hand side), mixed, the
+    polynomial CG and deflated GMRES (Chebyshev-preconditioned). Cases: a single block
+    (d < 64), d = 512 (8 x 8 blocks) and d = 5115 (80 x 80 blocks, a ragged last block of
+    59; the dense product there sums s in a kernel of its own).
+    Both products sum in fixed orders that differ, and the explicit inverse's rounding
+    (about cond(E) times the unit roundoff) moves the float64 iteration count by a few per
+    cent at d = 5115 (symmetric 268, dense 275, oracle 267): float64 counts within 4 % of
+    the oracle's for both products, the other solvers' counts within 5 % of each other.
+    Errors within 1e-6 of the solution, except GMRES (see below)."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _problem(name, scale, kw)
+    if nsub is not None:
+        p = dataclasses.replace(p, nsub=nsub)
+    K, b = dev(p.K), dev(p.q)
+    A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    lab, d = O.levelset_labels(p.grid, p.K, p.nsub, p.thr)
+    say(f"coarse symmetric {name}/{scale} grid={p.grid} nsub={p.nsub} d={d}")
+    ref = O.dpcg(A, bh, O.deflation_matrix(lab, d), tol=1e-8)
+    xr = _reference_x(A, bh, p.n)
+    if xr is None:
+        xr = O.dpcg(A, bh, O.deflation_matrix(lab, d), tol=1e-12).x
+    runs = [("fp64", dict(mode=0)), ("fp64-reproject", dict(mode=0, reproject=1)),
+            ("mixed", dict(mode=1)), ("poly", None), ("gmres", None)]
+    out = {}
+    for cs in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), coarse_sym=cs)
+        assert s.d == d
+        assert psl.psl_get_info(s.ctx)["coarse_sym"] == (cs > 0)
+        for tag, kw_solve in runs:
+            if tag == "poly":
+                x, st = psl.psl_solve_poly(s.ctx, b, tol=1e-8)
+            elif tag == "gmres":
+                # GMRES(30) with diag(A) stagnates on the region vectors of the d = 5115
+                # case (as the oracle's does); with the Chebyshev preconditioner it converges
+                x, st = psl.psl_solve_gmres(s.ctx, b, tol=1e-8, degree=3)
+            else:
+                x, st = psl.psl_solve(s.ctx, b, tol=1e-8, **kw_solve)
+            out[(cs, tag)] = (host(x), st)
+        s.ctx.destroy()
+    failures = []
+    for tag, _ in runs:
+        (xs, sts), (xd, std) = out[(1, tag)], out[(-1, tag)]
+        res, resd = O.relres(A, bh, xs), O.relres(A, bh, xd)
+        err = np.linalg.norm(xs - xr) / np.linalg.norm(xr)
+        errd = np.linalg.norm(xd - xr) / np.linalg.norm(xr)
+        say(f"  {tag}: symmetric iters={sts['iters']} relres={res:.2e} err={err:.2e}; "
+            f"dense iters={std['iters']} relres={resd:.2e} err={errd:.2e} "
+            f"(oracle DPCG {ref.iters})")
+        ok = sts["status"] == 0 and std["status"] == 0 and res <= 1e-8 and resd <= 1e-8
+        if tag == "gmres":
+            # GMRES minimises the preconditioned deflated residual, not an energy norm: at
+            # a 1e-8 residual its error on the d = 5115 case is 3.7e-6 with either product
+            # (its accuracy against the oracle's GMRES is tested elsewhere)
+            ok = ok and err <= max(1e-6, 2 * errd)
+        else:
+            ok = ok and err <= 1e-6 and errd <= 1e-6
+        if tag.startswith("fp64"):
+            ok = ok and all(abs(k - ref.iters) <= max(2, 0.04 * ref.iters)
+                            for k in (sts["iters"], std["iters"]))
+        else:
+            ok = ok and abs(sts["iters"] - std["iters"]) <= max(3, 0.05 * std["iters"])
+        if not ok:
+            failures.append(tag)
+    assert not failures, failures
