@@ -189,8 +189,76 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// a float64 value moved across lanes by a DPP control (both 32-bit halves; every control
+// used here is a permutation within a row of 16 lanes, so every source lane is active
+// whenever the whole wave is)
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(static_cast<long long>(
+      (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo)));
+}
+
+__device__ inline double read_lane(double v, int lane) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(b)), lane));
+  const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(b >> 32)), lane));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum of a float64 over the 64 lanes of a wave (every lane active), the same value in
+// every lane, in a fixed order: within each row of 16 lanes a butterfly of lane pairs
+// (lane xor 1, xor 2 by quad permutes, then the mirrored quad of each 8 and the mirrored
+// 8 of each 16; a + b and b + a round alike, so every lane of a row holds the same row
+// sum), then the four row sums added in row order. DPP moves and lane reads run on the
+// vector ALU; the generic version's cross-lane permutes go through the LDS unit.
+__device__ inline double wave_sum(double v) {
+  v += dpp_double<0xB1>(v);    // quad_perm [1, 0, 3, 2]: lane xor 1
+  v += dpp_double<0x4E>(v);    // quad_perm [2, 3, 0, 1]: lane xor 2
+  v += dpp_double<0x141>(v);   // row_half_mirror: the other quad of each 8
+  v += dpp_double<0x140>(v);   // row_mirror: the other 8 of each 16
+  return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
+}
+
 // Block-wide sum of NV values per thread in a fixed tree order; result valid in
 // every thread. lds must hold NV * (kBlock / kWave) doubles.
+// block_sum of the entries whose bit is set in `active` (the same mask in every thread,
+// so the skips are uniform branches); the other entries are left unreduced and must not
+// be read. Tiles with fewer labels than their kernel's slot count skip the unused slots.
+template <int NV>
+__device__ inline void block_sum_active(double (&v)[NV], double* lds, unsigned long long active) {
+  static_assert(NV <= 64, "active mask");
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  constexpr int NW = kBlock / kWave;
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    if ((active >> k) & 1ull) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if ((active >> k) & 1ull) lds[k * NW + w] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (!((active >> k) & 1ull)) continue;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc += lds[k * NW + j];
+    v[k] = acc;
+  }
+  __syncthreads();
+}
+
+// bits 0 .. n-1
+__device__ inline unsigned long long low_bits(int n) {
+  return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double* lds) {
   const int lane = threadIdx.x & (kWave - 1);

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? v : 0.0;
   }
-  psl::block_sum<NS + 1>(acc, lds);
+  psl::block_sum_active<NS + 1>(acc, lds, psl::low_bits(T.nslot) | (1ull << NS));
   double zs[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) zs[m] = acc[m];
@@ -283,7 +283,8 @@ __device__ __forceinline__ void cg_stencil_tile(int t, Geo g, const R* __restric
       for (int m = 0; m < NS; ++m) acc[NS + 3 + m] += (sl[k] == m) ? rd : 0.0;
     }
   }
-  psl::block_sum<NA>(acc, lds);
+  psl::block_sum_active<NA>(acc, lds, psl::low_bits(T.nslot) | (7ull << NS) |
+                                     (RP ? psl::low_bits(T.nslot) << (NS + 3) : 0ull));
   double zs[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) zs[m] = acc[m];
@@ -1053,7 +1054,7 @@ __device__ __forceinline__ void sd_stencil_tile(int t, bool lead_block, Geo g, c
 #pragma unroll
     for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? qd : 0.0;
   }
-  psl::block_sum<NS + 1>(acc, lds);
+  psl::block_sum_active<NS + 1>(acc, lds, psl::low_bits(T.nslot) | (1ull << NS));
   double zs[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) zs[m] = acc[m];
@@ -1423,7 +1424,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
     for (int k = 0; k < NS; ++k) acc[k] += (sl == k) ? val : 0.0;
   }
-  psl::block_sum<NS>(acc, lds);
+  psl::block_sum_active<NS>(acc, lds, psl::low_bits(T.nslot));
   write_slots<NS>(acc, T.nslot, slot_pos, t, zq);
 }
 
@@ -1565,11 +1566,14 @@ __device__ inline void small_block_sum2(double& a, double& b, double* red) {
   }
 }
 
-// sum over the 32 lanes of a half wave (fixed tree), result in all of them
+// sum over the 32 lanes of a half wave (every lane of the half active), result in all of
+// them: the row sums of psl::wave_sum (DPP steps within rows of 16), then the two rows
 __device__ inline double half_wave_sum(double v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, psl::kWave);
-  return v;
+  v += psl::dpp_double<0xB1>(v);
+  v += psl::dpp_double<0x4E>(v);
+  v += psl::dpp_double<0x141>(v);
+  v += psl::dpp_double<0x140>(v);
+  return v + __shfl_xor(v, 16, psl::kWave);
 }
 
 // label-major cell lists of a small grid, each label's cells in cell order: a wave ballot
