@@ -296,7 +296,13 @@ typedef struct {
                            symmetric), half the bytes of the dense product, and adds the
                            block shares in a second launch; -1 the dense row-wise product;
                            0 (default): 1 for d >= 1024, -1 below */
-  int32_t reserved[5];  /* must be 0 */
+  int32_t stencil_split; /* float32 (two-reduction) CG with finish kernels: 0 (default) or
+                           1 forms the new direction p = u + beta p_prev in a pass of its
+                           own and then q = A p in the plain stencil pass (bit-identical
+                           results, each neighbour loaded once); -1 keeps the fused pass
+                           that recomputes the neighbours' p. No effect without finish
+                           kernels */
+  int32_t reserved[4];  /* must be 0 */
 } psl_setup_opts;
 
 /* Fill `o` with the defaults (all zero). */

@@ -120,6 +120,7 @@ struct psl_ctx {
   int coarse_blocks = 1;              // ceil(d / kCoarseRows) GEMV workgroups
   int coarse_fused = 1;               // coarse workgroups sum s themselves (small d)
   int coarse_sym = 0;                 // coarse product over the lower block triangle of E^-1
+  int sd_split = 1;                   // two-reduction stencil split in two (with finish kernels)
   int sym_parts = 0;                  // its summing workgroups: ceil(d / (kBlock / 4))
   double* spart = nullptr;            // its block shares [nb * nb * 64] (nb = ceil(d / 64))
   double* spart2 = nullptr;           // the same for the second right-hand side

@@ -1494,6 +1494,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
     if (so->tile_cells != 0 && (so->tile_cells < 64 || so->tile_cells > 2048)) return PSL_EINVAL;
     if (so->finish_kernels < -1 || so->finish_kernels > 1) return PSL_EINVAL;
     if (so->coarse_sym < -1 || so->coarse_sym > 1) return PSL_EINVAL;
+    if (so->stencil_split < -1 || so->stencil_split > 1) return PSL_EINVAL;
     for (int32_t r : so->reserved)
       if (r != 0) return PSL_EINVAL;
   }
@@ -1675,6 +1676,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   // large d: the coarse product reads only the lower block triangle of E^-1
   c->coarse_sym = (so && so->coarse_sym) ? (so->coarse_sym > 0) : (d >= psl::kSymMinD);
   c->sym_parts = (d + psl::kBlock / 4 - 1) / (psl::kBlock / 4);
+  c->sd_split = !(so && so->stencil_split < 0);
   // grids up to 4096 cells with up to 32 vectors: float64 inner solves in one workgroup
   // (the iteration's vectors in LDS, no launch per iteration)
   c->small = (n <= 4096) && (d <= 32);

@@ -120,14 +120,16 @@ __device__ inline void write_slots(const double (&acc)[NS], int nslot, const int
 // ---------------------------------------------------------------------------------------
 // plain stencil pass. MODE 0: out = A in; MODE 1: out = b - A in (float64 refinement
 // residual). Partials per tile: Z^T out (zq) and (in, out) resp. ||out||^2 (red[t]).
+// With `stop` set, the pass returns at once once a solve's stop flag is raised.
 // ---------------------------------------------------------------------------------------
 template <typename R, int MODE, int NS, int CPT>
 __global__ void __launch_bounds__(kBlock)
     k_stencil(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty, const R* __restrict__ Tz,
               const R* __restrict__ in, const double* __restrict__ b, R* __restrict__ out,
               const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
-              double* zq, double* red) {
+              double* zq, double* red, const Scalars* stop) {
   __shared__ double lds[(NS + 1) * kNW];
+  if (stop && stop->done) return;   // an iteration enqueued past the stop
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
@@ -1075,6 +1077,32 @@ __global__ void __launch_bounds__(kBlock)
                                    sc, bench, pre);
 }
 
+// The stencil pass split in two (large grids, where the finish kernel has taken beta
+// before the pass): p = u + beta p_prev over all cells here, 16 bytes of each array per
+// thread, then the plain stencil q = A p with its Z^T q and (p, q) partials. The same
+// fused multiply-add and the same sums in the same order as the fused pass, so p, q and
+// the partials are bit-identical to it; each neighbour value is loaded once instead of
+// two and recombined.
+template <typename R, int PAR>
+__global__ void __launch_bounds__(kBlock)
+    k_sd_dir(int64_t n, const R* __restrict__ u, const R* __restrict__ pprev,
+             R* __restrict__ p, const Scalars* sc, int bench) {
+  if (sc->done) return;
+  constexpr int V = 16 / int(sizeof(R));
+  const R beta = R(bench ? 0.5 : sc->beta[PAR]);
+  const int64_t i0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * V;
+  if (i0 + V <= n) {
+    R a[V], b[V], o[V];
+    __builtin_memcpy(a, __builtin_assume_aligned(u + i0, 16), 16);
+    __builtin_memcpy(b, __builtin_assume_aligned(pprev + i0, 16), 16);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = axpy(beta, b[k], a[k]);
+    __builtin_memcpy(__builtin_assume_aligned(p + i0, 16), o, 16);
+  } else {
+    for (int64_t i = i0; i < n; ++i) p[i] = axpy(beta, pprev[i], u[i]);
+  }
+}
+
 // Update pass over the tiles tb0, tb0 + step, ... (tile_of_block order; step 0: tile tb0
 // itself, once); the workgroup's (r, u), (r, r) partials go to upart[pidx] and
 // upart[pcount + pidx].
@@ -1878,10 +1906,11 @@ template <typename R, int MODE, int NS>
 struct StencilC {
   template <int CPT>
   struct F {
-    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
+    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st,
+                    const Scalars* stop) {
       hipLaunchKernelGGL((k_stencil<R, MODE, NS, CPT>), dim3(c->ntiles), dim3(kBlock), 0, st,
                          geo(c), Prec<R>::face(c, 0), Prec<R>::face(c, 1), Prec<R>::face(c, 2),
-                         in, b, out, c->slot, c->slot_pos, c->zq, red(c, 0));
+                         in, b, out, c->slot, c->slot_pos, c->zq, red(c, 0), stop);
     }
   };
 };
@@ -1890,16 +1919,18 @@ template <typename R, int MODE>
 struct StencilL {
   template <int NS>
   struct F {
-    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
-      with_cpt<StencilC<R, MODE, NS>::template F>(c->cpt, c, in, b, out, st);
+    static void run(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st,
+                    const Scalars* stop) {
+      with_cpt<StencilC<R, MODE, NS>::template F>(c->cpt, c, in, b, out, st, stop);
     }
   };
 };
 
 // plain stencil pass: out = A in (MODE 0) or b - A in (MODE 1); partials in zq / red[0]
 template <typename R, int MODE>
-void launch_stencil(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st) {
-  with_ns<StencilL<R, MODE>::template F>(c->nslot_max, c, in, b, out, st);
+void launch_stencil(psl_ctx* c, const R* in, const double* b, R* out, hipStream_t st,
+                    const Scalars* stop = nullptr) {
+  with_ns<StencilL<R, MODE>::template F>(c->nslot_max, c, in, b, out, st, stop);
 }
 
 template <typename R, int RP, int NS>
@@ -2110,14 +2141,31 @@ void enqueue_iterations(psl_ctx* c, int count, int rp, hipStream_t st) {
   }
 }
 
-// one two-reduction iteration of parity PAR (three launches)
+// the two-reduction stencil pass of parity PAR: fused, or (finish kernels on) split into
+// the direction update and the plain stencil
+template <typename R, int PAR>
+void launch_sd_stencil(psl_ctx* c, hipStream_t st, int bench) {
+  if (c->pre && c->sd_split) {
+    psl::VecSet<R>& v = Prec<R>::vecs(c);
+    const R* pprev = PAR ? v.p : v.p2;
+    R* pout = PAR ? v.p2 : v.p;
+    constexpr int64_t per_block = int64_t(kBlock) * (16 / sizeof(R));
+    hipLaunchKernelGGL((k_sd_dir<R, PAR>), dim3(unsigned((c->n + per_block - 1) / per_block)),
+                       dim3(kBlock), 0, st, int64_t(c->n), v.u, pprev, pout, c->sc, bench);
+    launch_stencil<R, 0>(c, pout, nullptr, v.q, st, c->sc);
+  } else {
+    with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, bench);
+  }
+}
+
+// one two-reduction iteration of parity PAR (three passes)
 template <typename R, int PAR>
 void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
   if (c->pre)
     hipLaunchKernelGGL(k_sd_finish_b<PAR>, dim3(1), dim3(1024), 0, st, c->upart,
                        c->upd_blocks, c->sc);
   prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
-  with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, 0);
+  launch_sd_stencil<R, PAR>(c, st, 0);
   prof_end<R>(c, PSL_KERNEL_STENCIL, st);
   prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<0, 1>(c, 1, st);
@@ -2568,7 +2616,7 @@ extern "C" int psl_bench_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int32_
     switch (kernel) {
       case PSL_KERNEL_STENCIL:
         if (mode == PSL_MIXED)
-          with_ns<SdStencilL<float, 0>::template F>(c->nslot_max, c, st, 1);
+          launch_sd_stencil<float, 0>(c, st, 1);
         else
           with_ns<CgStencilL<double, 0>::template F>(c->nslot_max, c, st);
         break;

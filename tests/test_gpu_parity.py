@@ -968,3 +968,35 @@ def test_coarse_symmetric(gpu_lib, name, scale, kw, nsub):
         if not ok:
             failures.append(tag)
     assert not failures, failures
+
+
+@pytest.mark.parametrize("name,scale,kw", FINISH_CASES,
+                         ids=[f"{c[0]}-{c[1]}" for c in FINISH_CASES])
+def test_stencil_split(gpu_lib, name, scale, kw):
+    """The float32 stencil pass split in two (the direction update p = u + beta p_prev in
+    a pass of its own, then the plain stencil q = A p with its partials) against the
+    fused pass that recomputes the neighbours' p, both with finish kernels (forced on for
+    these small grids), in mixed precision: the same fused multiply-add and the same sums
+    in the same order, so x is bit-identical with equal iteration and refinement counts;
+    and the oracle's residual of x."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _problem(name, scale, kw)
+    say(f"stencil split {name}/{scale} grid={p.grid}")
+    K, b = dev(p.K), dev(p.q)
+    out = {}
+    for split in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), finish_kernels=1,
+                           stencil_split=split)
+        x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=psl.MIXED)
+        out[split] = (x.clone(), st)
+        s.ctx.destroy()
+    (x1, st1), (x0, st0) = out[1], out[-1]
+    A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    res = O.relres(A, bh, host(x1))
+    say(f"  split: iters={st1['iters']} outer={st1['outer']} fell_back={st1['fell_back']} "
+        f"relres={res:.2e}; fused: iters={st0['iters']} outer={st0['outer']}")
+    assert st1["status"] == 0 and res <= 1e-8
+    assert (st1["iters"], st1["outer"], st1["fell_back"]) == \
+        (st0["iters"], st0["outer"], st0["fell_back"])
+    assert torch.equal(x1, x0)
