@@ -122,6 +122,7 @@ struct psl_ctx {
   int coarse_sym = 0;                 // coarse product over the lower block triangle of E^-1
   int sd_split = 1;                   // two-reduction stencil split in two (with finish kernels)
   int sym_parts = 0;                  // its summing workgroups: ceil(d / (kBlock / 4))
+  double* Esym = nullptr;             // its lower blocks of E^-1, packed [nb (nb + 1) / 2 * 64 * 64]
   double* spart = nullptr;            // its block shares [nb * nb * 64] (nb = ceil(d / 64))
   double* spart2 = nullptr;           // the same for the second right-hand side
   // work
@@ -253,6 +254,15 @@ __device__ inline void block_sum_active(double (&v)[NV], double* lds, unsigned l
     v[k] = acc;
   }
   __syncthreads();
+}
+
+// lower-triangle block t = I (I + 1) / 2 + J (J <= I) of the symmetric coarse product
+__device__ inline void sym_block_of(int t, int& I, int& J) {
+  int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  I = i;
+  J = t - i * (i + 1) / 2;
 }
 
 // bits 0 .. n-1

@@ -1485,6 +1485,20 @@ extern "C" void psl_default_setup_opts(psl_setup_opts* o) {
   std::memset(o, 0, sizeof(*o));
 }
 
+// the lower 64 x 64 blocks of E^-1, packed block after block (row-major inside a block,
+// zero past d) for the symmetric coarse product: workgroup t copies block t
+__global__ void __launch_bounds__(kBlock) k_pack_sym(const double* __restrict__ Einv,
+                                                     double* __restrict__ Esym, int d) {
+  constexpr int B = psl::kSymBlock;
+  int I, J;
+  psl::sym_block_of(blockIdx.x, I, J);
+  double* dst = Esym + int64_t(blockIdx.x) * B * B;
+  for (int i = threadIdx.x; i < B * B; i += kBlock) {
+    const int row = I * B + i / B, col = J * B + i % B;
+    dst[i] = (row < d && col < d) ? Einv[int64_t(row) * d + col] : 0.0;
+  }
+}
+
 extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx,
                               const double* Ty, const double* Tz, const int32_t* labels,
                               int32_t d, const int32_t nsub[3], const psl_setup_opts* so,
@@ -1691,7 +1705,9 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
     PSL_FAIL(PSL_ENOMEM);
   if (c->coarse_sym) {
     const int64_t nb = (d + psl::kSymBlock - 1) / psl::kSymBlock;
-    if (dalloc(c, &c->spart, nb * nb * psl::kSymBlock) || dalloc(c, &c->spart2, nb * nb * psl::kSymBlock))
+    if (dalloc(c, &c->spart, nb * nb * psl::kSymBlock) ||
+        dalloc(c, &c->spart2, nb * nb * psl::kSymBlock) ||
+        dalloc(c, &c->Esym, nb * (nb + 1) / 2 * psl::kSymBlock * psl::kSymBlock))
       PSL_FAIL(PSL_ENOMEM);
   }
   static_assert(sizeof(psl::Scalars) <= 1024, "pinned mirror slot size");
@@ -1710,6 +1726,11 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   const int64_t ntri = trtri_scratch(d);
   if (ntri > 0 && dalloc(c, &tri_scratch, ntri)) PSL_FAIL(PSL_ENOMEM);
   int rc = cholesky_inverse(Lw, c->Einv, d, flags + 4, tri_scratch, st);
+  if (rc == PSL_OK && c->coarse_sym) {
+    const int nb = (d + psl::kSymBlock - 1) / psl::kSymBlock;
+    hipLaunchKernelGGL(k_pack_sym, dim3(nb * (nb + 1) / 2), dim3(kBlock), 0, st, c->Einv,
+                       c->Esym, d);
+  }
   if (rc == PSL_OK) rc = read_flags();
   if (rc != PSL_OK) PSL_FAIL(rc);
   if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range

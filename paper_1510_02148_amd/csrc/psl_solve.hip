@@ -437,7 +437,9 @@ __global__ void __launch_bounds__(kBlock)
 // ---------------------------------------------------------------------------------------
 // Coarse solve through the symmetry of E^-1 (large d): only its lower block triangle
 // (kSB x kSB blocks) is read, once per solve step, half the bytes of the dense product.
-// Workgroup t takes block B = E^-1[I, J], J <= I (t = I (I + 1) / 2 + J): its row sums
+// The set-up stores those blocks packed (Esym: block t = I (I + 1) / 2 + J contiguous,
+// row-major, zero past d), so each block is one contiguous 32 KiB read.
+// Workgroup t takes block B = E^-1[I, J], J <= I: its row sums
 // B s_J are column block J's share of e over the rows of block I; for I > J its column
 // sums B^T s_I are column block I's share of e over the rows of block J (E^-1[J, I] =
 // B^T). Shares land in spart[(X nb + Y) kSB + r] (row block X, column block Y, each pair
@@ -448,37 +450,27 @@ __global__ void __launch_bounds__(kBlock)
 constexpr int kSB = psl::kSymBlock;
 constexpr int kSBRows = kSB / kNW;   // block rows per wave
 
-__device__ inline void sym_block_of(int t, int& I, int& J) {
-  int i = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  I = i;
-  J = t - i * (i + 1) / 2;
-}
-
 template <int RP>
 __global__ void __launch_bounds__(kBlock)
-    k_symv_blocks(const double* __restrict__ Einv, const double* zq, const double* zr,
+    k_symv_blocks(const double* __restrict__ Esym, const double* zq, const double* zr,
                   const int32_t* lab_ptr, double* s, double* sr, double* __restrict__ spart,
                   double* __restrict__ spart2, int d, int nb, const Scalars* sc,
                   int check_done) {
   constexpr int NV = RP ? 2 : 1;
+  constexpr int HR = kSB / 2;                   // rows per round of the row sums
   __shared__ double sv[NV][2][kSB];             // [rhs][0: block I, 1: block J][entry]
-  __shared__ double tr[NV][kSB][kSB + 1];       // products for the row sums
+  __shared__ double tr[NV][HR][kSB + 1];        // products of half the rows
   __shared__ double cs[NV][kNW][kSB];           // per-wave column sums
   if (check_done && sc->done) return;
   int I, J;
-  sym_block_of(blockIdx.x, I, J);
+  psl::sym_block_of(blockIdx.x, I, J);
   const int tid = threadIdx.x, c = tid & (kSB - 1), w = tid / psl::kWave;
   // the block's loads first (a wave reads kSBRows whole 512-byte rows), so they are in
   // flight while the coarse entries are gathered
-  const int col = J * kSB + c;
+  const double* blk = Esym + int64_t(blockIdx.x) * kSB * kSB;
   double m[kSBRows];
 #pragma unroll
-  for (int k = 0; k < kSBRows; ++k) {
-    const int row = I * kSB + w * kSBRows + k;
-    m[k] = (row < d && col < d) ? Einv[int64_t(row) * d + col] : 0.0;
-  }
+  for (int k = 0; k < kSBRows; ++k) m[k] = blk[(w * kSBRows + k) * kSB + c];
   if (tid < 2 * kSB) {
     const int side = tid / kSB, k = tid & (kSB - 1);
     const int l = (side ? J : I) * kSB + k;
@@ -497,34 +489,46 @@ __global__ void __launch_bounds__(kBlock)
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    const double sj = sv[q][1][c];
     double ca = 0.0;
 #pragma unroll
-    for (int k = 0; k < kSBRows; ++k) {
-      const int r = w * kSBRows + k;
-      tr[q][r][c] = m[k] * sj;
-      ca += m[k] * sv[q][0][r];
-    }
+    for (int k = 0; k < kSBRows; ++k) ca += m[k] * sv[q][0][w * kSBRows + k];
     cs[q][w][c] = ca;
   }
-  __syncthreads();
-  // row sums: four threads per row, sixteen entries each, then the four in a fixed tree
-  // (a + b is exact-commutative, so every lane of the four holds the same sum)
-  const int r = tid >> 2, qt = tid & 3;
+  // row sums B s_J in two rounds of HR rows (the waves holding them stage their products;
+  // eight threads per row add eight entries each, then a fixed three-step tree in the
+  // lanes of an 8-lane group: every lane of the group ends with the same sum)
+  const int r8 = tid >> 3, e8 = tid & 7;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double a = 0.0;
+  for (int h = 0; h < 2; ++h) {
+    if (w / 2 == h) {
 #pragma unroll
-    for (int j = 0; j < kSB / 4; ++j) a += tr[q][r][qt * (kSB / 4) + j];
-    a += __shfl_xor(a, 1, psl::kWave);
-    a += __shfl_xor(a, 2, psl::kWave);
-    double* dst = q ? spart2 : spart;
-    if (qt == 0) dst[(int64_t(I) * nb + J) * kSB + r] = a;
-    if (I != J && tid < kSB) {
+      for (int q = 0; q < NV; ++q) {
+        const double sj = sv[q][1][c];
+#pragma unroll
+        for (int k = 0; k < kSBRows; ++k) tr[q][(w & 1) * kSBRows + k][c] = m[k] * sj;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double a = 0.0;
+#pragma unroll
+      for (int j2 = 0; j2 < 8; ++j2) a += tr[q][r8][e8 * 8 + j2];
+      a += psl::dpp_double<0xB1>(a);    // lane xor 1
+      a += psl::dpp_double<0x4E>(a);    // lane xor 2
+      a += psl::dpp_double<0x141>(a);   // the other quad of the 8
+      if (e8 == 0) (q ? spart2 : spart)[(int64_t(I) * nb + J) * kSB + h * HR + r8] = a;
+    }
+    __syncthreads();
+  }
+  // column sums (I > J): column block I's share of e over the rows of block J
+  if (I != J && tid < kSB) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
       double b = 0.0;
 #pragma unroll
       for (int k = 0; k < kNW; ++k) b += cs[q][k][tid];
-      dst[(int64_t(J) * nb + I) * kSB + tid] = b;
+      (q ? spart2 : spart)[(int64_t(J) * nb + I) * kSB + tid] = b;
     }
   }
 }
@@ -1968,7 +1972,7 @@ void launch_coarse(psl_ctx* c, int check_done, hipStream_t st) {
     // label sums stay in it at any d
     const int nb = (c->d + kSB - 1) / kSB;
     hipLaunchKernelGGL((k_symv_blocks<RP>), dim3(nb * (nb + 1) / 2), dim3(kBlock), 0, st,
-                       c->Einv, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->spart, c->spart2,
+                       c->Esym, c->zq, c->zr, c->lab_ptr, c->s, c->sr, c->spart, c->spart2,
                        c->d, nb, c->sc, check_done);
     hipLaunchKernelGGL((k_symv_sum<RP, NQ>), dim3(c->sym_parts), dim3(kBlock), 0, st, c->spart,
                        c->spart2, c->s, c->e, c->er, c->red, c->ntiles, c->cpart, c->d, nb,
