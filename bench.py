@@ -553,7 +553,16 @@ def main():
     stream = torch.cuda.current_stream()
     ids = {"stencil": psl.KERNEL_STENCIL, "coarse": psl.KERNEL_COARSE,
            "update": psl.KERNEL_UPDATE}
-    if args.solver == "dpcg":
+    small = args.solver == "dpcg" and mode == psl.FP64 and bool(info["small_solve"])
+    if small:
+        # small grids: the whole float64 inner solve is one launch of one workgroup
+        t = in_solve_kernel_times(psl, s.ctx, b, prob.tol, mode,
+                                  {"small_solve": psl.KERNEL_SMALL_SOLVE})["small_solve"]
+        iters = max(1, int(st["iters"]))
+        kernels["small_solve"] = {"us": round(t["us"], 3), "launches": t["launches"],
+                                  "us_per_iteration": round(t["us"] / iters, 3),
+                                  "total_ms": round(t["total_ms"], 3), "timing": "in-solve"}
+    elif args.solver == "dpcg":
         # inside real solves: every launch of the kernel in the solve's own precision
         times = in_solve_kernel_times(psl, s.ctx, b, prob.tol, mode, ids)
         for name, t in times.items():
@@ -601,19 +610,29 @@ def main():
     copy_us = e0.elapsed_time(e1) * 1e3 / 10
     copy_gbs = 2 * src.numel() * 4 / (copy_us * 1e-6) / 1e9
     del src, dst
-    if args.solver == "dpcg":
-        dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    else:   # the solver's own pass; the CG stencil is only the SpMV reference there
-        dominant = next(k for k in kernels if k != "stencil")
-    kd = kernels[dominant]
-    traffic = counter_traffic(dominant, args.workload, args.mode, int(info["coarse_sym"]))
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": (round(traffic) if traffic is not None else None),
-                "traffic_over_algorithmic": (round(traffic / kd["alg_bytes"], 3)
-                                             if traffic is not None else None),
-                "copy_kernel_gbs": round(copy_gbs, 1)}
-    spmv_gbs = kernels["stencil"]["gbs"]
+    if small:
+        # one workgroup on one compute unit: bound by its barriers and dependent sums,
+        # not by HBM (the whole working set is a few hundred KiB)
+        kd = kernels["small_solve"]
+        roofline = {"bound": "latency", "kernel": "small_solve",
+                    "achieved": kd["us_per_iteration"], "unit": "us/iteration", "peak": None,
+                    "frac": None, "traffic": None, "copy_kernel_gbs": round(copy_gbs, 1)}
+        spmv_gbs = None
+    else:
+        if args.solver == "dpcg":
+            dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        else:   # the solver's own pass; the CG stencil is only the SpMV reference there
+            dominant = next(k for k in kernels if k != "stencil")
+        kd = kernels[dominant]
+        traffic = counter_traffic(dominant, args.workload, args.mode, int(info["coarse_sym"]))
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"],
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
+                    "traffic": (round(traffic) if traffic is not None else None),
+                    "traffic_over_algorithmic": (round(traffic / kd["alg_bytes"], 3)
+                                                 if traffic is not None else None),
+                    "copy_kernel_gbs": round(copy_gbs, 1)}
+        spmv_gbs = kernels["stencil"]["gbs"]
 
     # ---- CPU baseline: the oracle on the same workload -------------------------------
     cpu = None

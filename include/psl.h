@@ -418,6 +418,9 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
                                         d, y updates and the (r, y), (r, r) partials; needs a
                                         prior psl_solve_poly; PSL_MIXED times the float32
                                         step after a mixed solve) */
+#define PSL_KERNEL_SMALL_SOLVE    7  /* the one-workgroup float64 inner solve of small grids
+                                        (psl_ctx_info.small_solve; one launch per inner
+                                        solve); psl_profile_kernel only, PSL_FP64 */
 
 /*
  * psl_bench_kernel -- enqueue `reps` back-to-back launches of one kernel of the CG
@@ -440,13 +443,15 @@ int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, v
 /*
  * psl_profile_kernel -- time one kernel of the CG iteration inside the following psl_solve
  * calls on this context: an event is recorded on the solve's stream before and after each
- * launch of `kernel` (PSL_KERNEL_STENCIL, PSL_KERNEL_COARSE (the label sum and the coarse
- * product together) or PSL_KERNEL_UPDATE) in the precision of `mode` (PSL_MIXED: the
- * float32 launches of a mixed solve), for up to `max_launches` launches (1 .. 2^20) counted
- * from this call. While armed, the solves launch their iterations directly (no replayed
- * graphs), so every launch is the solve's own; launches enqueued past convergence return
- * at once and show as short durations. kernel < 0 disarms. The events are created here
- * and kept by the context. Errors: PSL_EINVAL, PSL_ENOMEM, PSL_EHIP.
+ * launch of `kernel` (PSL_KERNEL_STENCIL (with finish kernels: the direction pass and the
+ * stencil pass together), PSL_KERNEL_COARSE (the label sum and the coarse product
+ * together), PSL_KERNEL_UPDATE, or PSL_KERNEL_SMALL_SOLVE with PSL_FP64) in the precision
+ * of `mode` (PSL_MIXED: the float32 launches of a mixed solve), for up to `max_launches`
+ * launches (1 .. 2^20) counted from this call. While the first three are armed, the solves
+ * launch their iterations directly with three or more launches per iteration (no replayed
+ * graphs, no one-workgroup solve), so every launch is the solve's own; launches enqueued
+ * past convergence return at once and show as short durations. kernel < 0 disarms. The
+ * events are created here and kept by the context. Errors: PSL_EINVAL, PSL_ENOMEM, PSL_EHIP.
  */
 int psl_profile_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t max_launches);
 
@@ -476,6 +481,9 @@ typedef struct {
   int32_t nslot_max;    /* most distinct labels in one tile */
   int32_t coarse_sym;   /* 1: the coarse product reads the lower block triangle of E^-1
                            (psl_setup_opts.coarse_sym), 0: the dense product */
+  int32_t small_solve;  /* 1: float64 inner solves run in one workgroup (n <= 4096 cells,
+                           d <= 32) */
+  int32_t reserved;
 } psl_ctx_info;
 
 int psl_get_info(const psl_ctx* ctx, psl_ctx_info* info);

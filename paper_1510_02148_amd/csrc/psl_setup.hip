@@ -1759,5 +1759,7 @@ extern "C" int psl_get_info(const psl_ctx* c, psl_ctx_info* info) {
   info->m_faces = c->m_az;
   info->nslot_max = c->nslot_max;
   info->coarse_sym = c->coarse_sym;
+  info->small_solve = c->small;
+  info->reserved = 0;
   return PSL_OK;
 }

@@ -2281,7 +2281,7 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
   psl::VecSet<R>& v = Prec<R>::vecs(c);
   const int chunk = check_every + (check_every & 1);  // parity pattern needs an even count
   if (std::is_same<R, double>::value && form == kFormSingle && !rp && c->small &&
-      c->prof_kernel < 0) {
+      (c->prof_kernel < 0 || c->prof_kernel == PSL_KERNEL_SMALL_SOLVE)) {
     // small grid: the whole inner solve in one workgroup, one host read at its end
     hipLaunchKernelGGL(k_set_inner, dim3(1), dim3(1), 0, st, c->sc, goal * goal, maxit);
     if (!c->small_lcell) {
@@ -2291,9 +2291,11 @@ int inner_solve(psl_ctx* c, double* x, int form, int fresh, double goal, int max
       hipLaunchKernelGGL(k_small_lists, dim3(1), dim3(kSmallThreads), 0, st, int(c->n), c->d, c->labels,
                          c->small_lptr, c->small_lcell);
     }
+    prof_begin<double>(c, PSL_KERNEL_SMALL_SOLVE, st);
     hipLaunchKernelGGL(k_small_cg, dim3(1), dim3(kSmallThreads), 0, st, c->nx, c->ny, c->nz,
                        c->Tx, c->Ty, c->Tz, c->labels, c->small_lptr, c->small_lcell,
                        c->invdiag, c->Einv, c->d, c->r64, c->v64.rh, c->v64.xh, c->sc);
+    prof_end<double>(c, PSL_KERNEL_SMALL_SOLVE, st);
     if ((rc = read_scalars(c, st)) != PSL_OK) return rc;
     *iters = c->h_sc->iters;
     *status = c->h_sc->status;
@@ -2667,8 +2669,9 @@ extern "C" int psl_profile_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int3
     return PSL_OK;
   }
   if ((kernel != PSL_KERNEL_STENCIL && kernel != PSL_KERNEL_COARSE &&
-       kernel != PSL_KERNEL_UPDATE) ||
-      (mode != PSL_FP64 && mode != PSL_MIXED) || max_launches < 1 || max_launches > (1 << 20))
+       kernel != PSL_KERNEL_UPDATE && kernel != PSL_KERNEL_SMALL_SOLVE) ||
+      (mode != PSL_FP64 && mode != PSL_MIXED) || max_launches < 1 || max_launches > (1 << 20) ||
+      (kernel == PSL_KERNEL_SMALL_SOLVE && mode != PSL_FP64))
     return PSL_EINVAL;
   if (max_launches > c->prof_cap) {
     hipEvent_t* ev = new (std::nothrow) hipEvent_t[2 * max_launches];

@@ -54,7 +54,8 @@ class psl_solve_opts(ctypes.Structure):
 class psl_ctx_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("m_faces", ctypes.c_int64), ("nslot_max", ctypes.c_int32),
-                ("coarse_sym", ctypes.c_int32)]
+                ("coarse_sym", ctypes.c_int32), ("small_solve", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class psl_solve_stats(ctypes.Structure):
@@ -141,7 +142,7 @@ EXPORTED = ("psl_assemble_tpfa", "psl_build_Z", "psl_build_Z_cc", "psl_build_Z_n
             "psl_solve_gmres", "psl_default_gmres_opts", "psl_solve_poly",
             "psl_default_poly_opts")
 (KERNEL_STENCIL, KERNEL_COARSE, KERNEL_UPDATE, KERNEL_DIRECTION, KERNEL_OUTER_RESIDUAL,
- KERNEL_GMRES_PASS, KERNEL_POLY_STEP) = range(7)
+ KERNEL_GMRES_PASS, KERNEL_POLY_STEP, KERNEL_SMALL_SOLVE) = range(8)
 
 
 class PslError(RuntimeError):
@@ -480,7 +481,8 @@ def psl_destroy(ctx: Context):
 
 def psl_profile_kernel(ctx, kernel: int, mode: int, max_launches: int = 4096):
     """Arm per-launch event timing of one CG kernel (KERNEL_STENCIL, KERNEL_COARSE,
-    KERNEL_UPDATE) in the precision of `mode` for the following solves; kernel < 0 disarms."""
+    KERNEL_UPDATE, or KERNEL_SMALL_SOLVE in FP64) in the precision of `mode` for the
+    following solves; kernel < 0 disarms."""
     _check(_profile_kernel(ctx.handle, int(kernel), int(mode), int(max_launches)),
            "psl_profile_kernel")
 

@@ -60,6 +60,8 @@ def test_binding_struct_layout_matches_c(tmp_path):
         " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every),"
         " offsetof(psl_poly_opts, mixed), offsetof(psl_gmres_opts, degree));"
         "printf(\"%zu\\n\", offsetof(psl_solve_stats, zt_r_drift));"
+        "printf(\"%zu %zu %zu\\n\", sizeof(psl_ctx_info), offsetof(psl_ctx_info, coarse_sym),"
+        " offsetof(psl_ctx_info, small_solve));"
         "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -73,7 +75,9 @@ def test_binding_struct_layout_matches_c(tmp_path):
             ctypes.sizeof(psl.psl_gmres_opts), psl.psl_gmres_opts.use_x0.offset,
             ctypes.sizeof(psl.psl_poly_opts), psl.psl_poly_opts.degree.offset,
             psl.psl_poly_opts.check_every.offset, psl.psl_poly_opts.mixed.offset,
-            psl.psl_gmres_opts.degree.offset, psl.psl_solve_stats.zt_r_drift.offset]
+            psl.psl_gmres_opts.degree.offset, psl.psl_solve_stats.zt_r_drift.offset,
+            ctypes.sizeof(psl.psl_ctx_info), psl.psl_ctx_info.coarse_sym.offset,
+            psl.psl_ctx_info.small_solve.offset]
     assert got == want
 
 

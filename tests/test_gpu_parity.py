@@ -1000,3 +1000,48 @@ def test_stencil_split(gpu_lib, name, scale, kw):
     assert (st1["iters"], st1["outer"], st1["fell_back"]) == \
         (st0["iters"], st0["outer"], st0["fell_back"])
     assert torch.equal(x1, x0)
+
+
+def test_profile_kernel(gpu_lib):
+    """psl_profile_kernel / psl_profile_read: events around one kernel's launches inside
+    real solves. On a grid of 2^14 cells, float64: every stencil launch of the solve is
+    timed (at least one per iteration), and x equals the unprofiled solve bit for bit (the
+    same kernels in the same order, launched directly instead of replayed); mixed: the
+    float32 stencil steps are timed, x again bit-identical. On
+    the 64x64 case (float64, one-workgroup inner solve): one timed launch per inner solve,
+    x bit-identical to the unprofiled solve; arming a pass kernel there runs the
+    three-launch loop instead, which still meets the oracle. The one-workgroup id is
+    float64 only."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    for name, scale, mode in (("c2", 4, psl.FP64), ("c2", 4, psl.MIXED), ("c1", 1, psl.FP64)):
+        p = _problem(name, scale, {})
+        s = pipeline.setup(p.grid, dev(p.K), p.dirichlet_mask, p.nsub, list(p.thr))
+        b = dev(p.q)
+        small = bool(psl.psl_get_info(s.ctx)["small_solve"])
+        assert small == (name == "c1")
+        x0, st0 = psl.psl_solve(s.ctx, b, tol=1e-8, mode=mode)
+        kid = psl.KERNEL_SMALL_SOLVE if small else psl.KERNEL_STENCIL
+        psl.psl_profile_kernel(s.ctx, kid, mode)
+        x1, st1 = psl.psl_solve(s.ctx, b, tol=1e-8, mode=mode)
+        dur = psl.psl_profile_read(s.ctx)
+        psl.psl_profile_kernel(s.ctx, -1, mode)
+        say(f"profile {name}: {len(dur)} launches timed, median {np.median(dur):.1f} us, "
+            f"iters {st1['iters']} outer {st1['outer']}")
+        assert torch.equal(x0, x1) and st0["iters"] == st1["iters"]
+        assert all(v > 0 for v in dur)
+        if small:
+            assert len(dur) == st1["outer"]
+            psl.psl_profile_kernel(s.ctx, psl.KERNEL_STENCIL, mode)
+            x2, st2 = psl.psl_solve(s.ctx, b, tol=1e-8, mode=mode)
+            n2 = len(psl.psl_profile_read(s.ctx))
+            psl.psl_profile_kernel(s.ctx, -1, mode)
+            A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+            assert n2 >= st2["iters"] and O.relres(A, bh, host(x2)) <= 1e-8
+            with pytest.raises(psl.PslError):
+                psl.psl_profile_kernel(s.ctx, psl.KERNEL_SMALL_SOLVE, psl.MIXED)
+        elif mode == psl.FP64:
+            assert len(dur) >= st1["iters"]
+        else:
+            assert len(dur) >= 1
+        s.ctx.destroy()
