@@ -1216,7 +1216,7 @@ __global__ void __launch_bounds__(kBlock) k_trtri_off(const double* L, double* X
 // launch adds the chunks in order and applies -X_ii. A workgroup's chain of dependent
 // block products stays at most kTrtriChunk long (on d = 4141 the unsplit form spent up
 // to 65 products in one workgroup).
-constexpr int kTrtriChunk = 8;
+constexpr int kTrtriChunk = 4;
 
 __global__ void __launch_bounds__(kBlock) k_trtri_part(const double* L, const double* X, int d,
                                                        int s, int nchunk, double* P) {
