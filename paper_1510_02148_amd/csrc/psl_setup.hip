@@ -1030,12 +1030,49 @@ __global__ void __launch_bounds__(kBlock) k_trsm_panel(double* A, int d, int kb)
 // AM = 0: A(i,k) = A[i*lda + k]; AM = 1: A(i,k) = A[k*lda + i].
 // BM = 0: B(k,j) = B[k*ldb + j]; BM = 1: B(k,j) = B[j*ldb + k].
 // LOWER: only entries with j <= i are updated (tiles wholly above the diagonal exit).
+// C += A B for 64 x 64 blocks staged in LDS as sa[k][row] = A(row, k) and sb[k][col] =
+// B(k, col), on the float64 matrix cores (v_mfma_f64_16x16x4f64): wave w forms rows
+// 16w .. 16w + 15 as four 16 x 16 tiles, four k per instruction. Lane l feeds A(16w +
+// l % 16, k + l / 16) and B(k + l / 16, 16u + l % 16), and holds C(mac_row(r),
+// mac_col(u)) in acc[u][r] (the result layout of the instruction, checked on gfx950 with
+// a one-wave probe: register r of lane l is row l / 16 + 4 r, column l % 16 of the tile). An instruction reads two operands per lane from LDS where
+// the vector form read 32 bytes per multiply-add pair: the products stop being bound by
+// LDS bandwidth. The summation order inside an instruction is the hardware's, fixed.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline int mac_row(int r) {
+  const int l = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
+  return 16 * w + (l / 16) + 4 * r;
+}
+__device__ inline int mac_col(int u) { return 16 * u + (threadIdx.x & 15); }
+
+__device__ inline void block_mac(const double (*sa)[kNB + 2], const double (*sb)[kNB + 2],
+                                 double (&acc)[4][4]) {
+  const int l = threadIdx.x & (psl::kWave - 1), w = threadIdx.x / psl::kWave;
+  const int lr = l & 15, lk = l >> 4;
+  v4d c[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) c[u] = v4d{acc[u][0], acc[u][1], acc[u][2], acc[u][3]};
+#pragma unroll 4
+  for (int k = 0; k < kNB; k += 4) {
+    const double a = sa[k + lk][16 * w + lr];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      c[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sb[k + lk][16 * u + lr], c[u], 0, 0, 0);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[u][r] = c[u][r];
+}
+
 template <int AM, int BM, int LOWER>
 __global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const double* A,
                                                      int lda, const double* B, int ldb, int M,
                                                      int N, int K) {
-  __shared__ double sa[kNB][64 + 1];  // sa[k][i]
-  __shared__ double sb[kNB][64 + 1];  // sb[k][j]
+  // K = kNB here (a trailing update follows only a full 64-column panel)
+  __shared__ __align__(16) double sa[kNB][kNB + 2];  // sa[k][i]
+  __shared__ __align__(16) double sb[kNB][kNB + 2];  // sb[k][j]
   const int ti = blockIdx.y * 64, tj = blockIdx.x * 64;
   if (LOWER && tj > ti + 63) return;
   // K * 64 <= 4096 entries per operand: 16 per thread, all loads issued before the stores;
@@ -1063,25 +1100,13 @@ __global__ void __launch_bounds__(kBlock) k_gemm_sub(double* C, int ldc, const d
     }
   }
   __syncthreads();
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4] = {};
-  for (int k = 0; k < K; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = sa[k][ty + 16 * u];
-      b[u] = sb[k][tx + 16 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-  }
+  block_mac(sa, sb, acc);
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = ti + ty + 16 * u, j = tj + tx + 16 * v;
+      const int i = ti + mac_row(v), j = tj + mac_col(u);
       if (i < M && j < N && (!LOWER || j <= i)) C[int64_t(i) * ldc + j] -= acc[u][v];
     }
 }
@@ -1128,21 +1153,6 @@ __device__ inline void stage_rect(double (*dst)[kNB + 2], const double* src, int
 // 4x4 outputs per thread, tx = thread % 16, ty = thread / 16). A thread's four rows and
 // four columns are contiguous, so each k step is two 16-byte reads per operand (the rows
 // are shared by the 16 threads of a row group, i.e. broadcast).
-__device__ inline void block_mac(const double (*sa)[kNB + 2], const double (*sb)[kNB + 2],
-                                 double (&acc)[4][4]) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  for (int m = 0; m < kNB; ++m) {
-    const double2* pa = reinterpret_cast<const double2*>(&sa[m][4 * ty]);
-    const double2* pb = reinterpret_cast<const double2*>(&sb[m][4 * tx]);
-    const double2 a01 = pa[0], a23 = pa[1], b01 = pb[0], b23 = pb[1];
-    const double a[4] = {a01.x, a01.y, a23.x, a23.y};
-    const double b[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-  }
-}
 
 // Inverse of each diagonal block of the lower factor, all blocks at once (one wave per
 // block): lane j forms column j of L_kk^-1 by forward substitution,
@@ -1193,22 +1203,19 @@ __global__ void __launch_bounds__(kBlock) k_trtri_off(const double* L, double* X
     block_mac(sa, sb, acc);
     __syncthreads();
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sb[4 * ty + u][4 * tx + v] = acc[u][v];   // T(m, c)
+    for (int v = 0; v < 4; ++v) sb[mac_row(v)][mac_col(u)] = acc[u][v];   // T(m, c)
   stage_rect<1>(sa, X + int64_t(ri) * d + ri, d, mi, mi);                  // sa[m][r] = X_ii(r, m)
   __syncthreads();
   double y[4][4] = {};
   block_mac(sa, sb, y);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = 4 * ty + u;
-    if (r < mi)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[int64_t(ri + r) * d + cj + 4 * tx + v] = -y[u][v];
-  }
+    for (int v = 0; v < 4; ++v)
+      if (mac_row(v) < mi) X[int64_t(ri + mac_row(v)) * d + cj + mac_col(u)] = -y[u][v];
 }
 
 // Long block diagonals (s > kTrtriChunk products per block) are split: workgroup (ii, ch)
@@ -1241,12 +1248,11 @@ __global__ void __launch_bounds__(kBlock) k_trtri_part(const double* L, const do
     block_mac(sa, sb, acc);
     __syncthreads();
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double* out = P + int64_t(blockIdx.x) * kNB * kNB;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(4 * ty + u) * kNB + 4 * tx + v] = acc[u][v];
+    for (int v = 0; v < 4; ++v) out[mac_row(v) * kNB + mac_col(u)] = acc[u][v];
 }
 
 __global__ void __launch_bounds__(kBlock) k_trtri_fin(double* X, int d, int s, int nchunk,
@@ -1255,30 +1261,27 @@ __global__ void __launch_bounds__(kBlock) k_trtri_fin(double* X, int d, int s, i
   __shared__ __align__(16) double sb[kNB][kNB + 2];
   const int ii = blockIdx.x, i = ii + s, j = i - s;
   const int ri = i * kNB, cj = j * kNB, mi = min(kNB, d - ri);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double t[4][4] = {};
   for (int ch = 0; ch < nchunk; ++ch) {   // fixed order
     const double* part = P + int64_t(ii * nchunk + ch) * kNB * kNB;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) t[u][v] += part[(4 * ty + u) * kNB + 4 * tx + v];
+      for (int v = 0; v < 4; ++v) t[u][v] += part[mac_row(v) * kNB + mac_col(u)];
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sb[4 * ty + u][4 * tx + v] = t[u][v];   // T(m, c)
+    for (int v = 0; v < 4; ++v) sb[mac_row(v)][mac_col(u)] = t[u][v];   // T(m, c)
   stage_rect<1>(sa, X + int64_t(ri) * d + ri, d, mi, mi);                // sa[m][r] = X_ii(r, m)
   __syncthreads();
   double y[4][4] = {};
   block_mac(sa, sb, y);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = 4 * ty + u;
-    if (r < mi)
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[int64_t(ri + r) * d + cj + 4 * tx + v] = -y[u][v];
-  }
+    for (int v = 0; v < 4; ++v)
+      if (mac_row(v) < mi) X[int64_t(ri + mac_row(v)) * d + cj + mac_col(u)] = -y[u][v];
 }
 
 // doubles of scratch the split diagonals of cholesky_inverse need (0 when none is split)
@@ -1319,12 +1322,11 @@ __global__ void __launch_bounds__(kBlock) k_lower_gram(const double* Li, double*
     block_mac(sa, sb, acc);
     __syncthreads();
   }
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = 4 * ty + u, c = 4 * tx + v;
+      const int r = mac_row(v), c = mac_col(u);
       if (r < mI && c < mJ) {
         out[int64_t(I * kNB + r) * d + J * kNB + c] = acc[u][v];
         if (I != J) out[int64_t(J * kNB + c) * d + I * kNB + r] = acc[u][v];
@@ -1343,6 +1345,7 @@ static int cholesky_inverse(double* L, double* X, int d, int32_t* bad, double* s
     if (rest > 0) {
       hipLaunchKernelGGL(k_trsm_panel, dim3(nblocks(rest, kBlock / psl::kWave)), dim3(kBlock), 0,
                          st, L, d, kb);
+      // rest > 0 implies nb = kNB: the trailing update's block product always has K = kNB
       const double* P = L + int64_t(kb + nb) * d + kb;   // rest x nb panel
       double* C = L + int64_t(kb + nb) * d + kb + nb;    // trailing block
       dim3 grid(nblocks(rest, 64), nblocks(rest, 64));
