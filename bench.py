@@ -53,12 +53,15 @@ def log(msg):
 
 
 def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool,
-                      coarse_sym: bool = False) -> float:
+                      coarse_sym: bool = False, face_tables: bool = False) -> float:
     """Bytes one launch must move at minimum (each array touched once), w = word size.
 
     two=True: the two-reduction loop (float32 path); False: the single-reduction loop.
     coarse_sym: the coarse product reads the lower triangle of the symmetric E^-1 and
     writes and re-reads one share of e per (row block, column block) of 64.
+    face_tables: the float32 update reads each cut face as one packed word and its T
+    (4 + w bytes instead of 12 + w); the per-tile tables of coarse values (a few labels
+    per tile, cache-resident) are not counted.
     """
     nx, ny, nz = grid
     n = nx * ny * nz
@@ -69,7 +72,7 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
         return 2 * w * n + w * faces + 1 * n + w * n   # read r, u, T, slot; write v = A u
     if kernel == "update":
         if two:   # read q, r, p, x, 1/diag; write r, x, u; + the cut faces of A Z
-            return 8 * w * n + m_faces * (12 + w)
+            return 8 * w * n + m_faces * ((4 if face_tables else 12) + w)
         return 12 * w * n + m_faces * (12 + w)   # read v, r, u, p, q, x, 1/diag; write 5
     if kernel == "coarse":           # read E^-1 (float64), s; write e
         if coarse_sym:
@@ -567,7 +570,7 @@ def main():
         times = in_solve_kernel_times(psl, s.ctx, b, prob.tol, mode, ids)
         for name, t in times.items():
             nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w, mode == psl.MIXED,
-                                       bool(info["coarse_sym"]))
+                                       bool(info["coarse_sym"]), bool(info["face_tables"]))
             kernels[name] = {"us": round(t["us"], 3), "alg_bytes": int(nbytes),
                              "gbs": round(nbytes / (t["us"] * 1e-6) / 1e9, 1),
                              "launches": t["launches"],

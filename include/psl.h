@@ -302,7 +302,13 @@ typedef struct {
                            results, each neighbour loaded once); -1 keeps the fused pass
                            that recomputes the neighbours' p. No effect without finish
                            kernels */
-  int32_t reserved[4];  /* must be 0 */
+  int32_t face_tables;  /* float32 update: 0 (default) or 1 gives every tile a table of the
+                           coarse labels its cut faces reference (at most 126) and packs each
+                           face into one word of local indices, so a workgroup gathers the
+                           tile's few coarse values once, early, instead of one per face
+                           (bit-identical results); -1 keeps the unpacked faces. A tile
+                           with more labels than the table holds keeps them too */
+  int32_t reserved[3];  /* must be 0 */
 } psl_setup_opts;
 
 /* Fill `o` with the defaults (all zero). */
@@ -483,7 +489,8 @@ typedef struct {
                            (psl_setup_opts.coarse_sym), 0: the dense product */
   int32_t small_solve;  /* 1: float64 inner solves run in one workgroup (n <= 4096 cells,
                            d <= 32) */
-  int32_t reserved;
+  int32_t face_tables;  /* 1: the float32 update reads packed faces and per-tile coarse
+                           tables (psl_setup_opts.face_tables) */
 } psl_ctx_info;
 
 int psl_get_info(const psl_ctx* ctx, psl_ctx_info* info);

@@ -17,6 +17,8 @@ constexpr int kMaxSlots = PSL_MAX_TILE_LABELS;
 constexpr int kCoarseRows = 8;       // coarse GEMV rows per workgroup (two per wave)
 constexpr int kSymBlock = 64;        // block size of the symmetric coarse product
 constexpr int kSymMinD = 1024;       // d from which the coarse product is the symmetric one
+constexpr int kTileLabels = 128;     // per-tile coarse table of the float32 update: local
+                                     // indices 0..126, 127 marks an outer face
 
 // Work tile: a box of cells inside one subdomain; one workgroup per tile.
 struct Tile {
@@ -113,6 +115,13 @@ struct psl_ctx {
   int32_t* az_oth = nullptr;          // [m] label across the face, -1 for an outer face
   double* az_t = nullptr;             // [m] face transmissibility
   float* az_t32 = nullptr;            // [m]
+  // per-tile coarse tables (float32 update): the labels a tile's cut faces reference, in
+  // ascending order, and each face packed as local cell | first-face bit 31 | local index
+  // of its own label << 11 | of the other label << 18 (127: outer face)
+  int face_tab = 0;
+  int32_t* az_pk = nullptr;           // [m]
+  int32_t* tlab = nullptr;            // [ntiles * kTileLabels]
+  int32_t* tlab_n = nullptr;          // [ntiles]
   int64_t m_az = 0;
   // coarse operator
   double* E = nullptr;                // [d*d] row-major

@@ -1502,6 +1502,72 @@ __global__ void __launch_bounds__(kBlock) k_pack_sym(const double* __restrict__ 
   }
 }
 
+// Per-tile coarse tables of the float32 update (one workgroup per tile): the labels the
+// tile's cut faces reference are marked in an LDS bitmap over [0, d) (d <= 8192: 256
+// words, one per thread); a label's local index is its rank among the marked ones, so the
+// table is in ascending label order. Each face is packed into one word: local cell (bits
+// 0..10, tiles hold at most 2048 cells), the first-face bit 31, the local index of its own
+// label << 11 and of the other label << 18 (127 for an outer face). A tile with more than
+// 126 labels raises *overflow (the context then keeps the unpacked faces).
+__global__ void __launch_bounds__(kBlock) k_az_pack(const int32_t* az_ptr, const int32_t* az_cell,
+                                                    const int32_t* az_lab, const int32_t* az_oth,
+                                                    int d, int32_t* az_pk, int32_t* tlab,
+                                                    int32_t* tlab_n, int32_t* overflow) {
+  constexpr int NW = PSL_MAX_DENSE_D / 32;
+  static_assert(NW <= kBlock, "one bitmap word per thread");
+  __shared__ uint32_t bits[NW];
+  __shared__ int32_t wrank[NW];
+  __shared__ int32_t wtot[kBlock / psl::kWave];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & (psl::kWave - 1), w = tid / psl::kWave;
+  const int a = az_ptr[t], b = az_ptr[t + 1], nw = (d + 31) / 32;
+  if (tid < NW) bits[tid] = 0u;
+  __syncthreads();
+  for (int k = a + tid; k < b; k += kBlock) {
+    const int ls = az_lab[k], lo = az_oth[k];
+    atomicOr(&bits[ls >> 5], 1u << (ls & 31));
+    if (lo >= 0) atomicOr(&bits[lo >> 5], 1u << (lo & 31));
+  }
+  __syncthreads();
+  // exclusive prefix of the words' popcounts
+  const int cnt = tid < nw ? __popc(bits[tid]) : 0;
+  int incl = cnt;
+  for (int off = 1; off < psl::kWave; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == psl::kWave - 1) wtot[w] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int k = 0; k < kBlock / psl::kWave; ++k) {
+    if (k < w) before += wtot[k];
+    total += wtot[k];
+  }
+  if (tid < NW) wrank[tid] = before + incl - cnt;
+  if (total > psl::kTileLabels - 1) {   // uniform
+    if (tid == 0) overflow[0] = 1;
+    return;
+  }
+  __syncthreads();
+  if (tid == 0) tlab_n[t] = total;
+  if (tid < nw) {
+    uint32_t m = bits[tid];
+    int r = wrank[tid];
+    while (m) {
+      tlab[int64_t(t) * psl::kTileLabels + r++] = tid * 32 + (__ffs(m) - 1);
+      m &= m - 1u;
+    }
+  }
+  for (int k = a + tid; k < b; k += kBlock) {
+    const int ls = az_lab[k], lo = az_oth[k], cw = az_cell[k];
+    const int il = wrank[ls >> 5] + __popc(bits[ls >> 5] & ((1u << (ls & 31)) - 1u));
+    const int io = lo < 0 ? psl::kTileLabels - 1
+                          : wrank[lo >> 5] + __popc(bits[lo >> 5] & ((1u << (lo & 31)) - 1u));
+    az_pk[k] = int32_t((uint32_t(cw) & 0x80000000u) | (uint32_t(cw) & 0x7FFu) |
+                       (uint32_t(il) << 11) | (uint32_t(io) << 18));
+  }
+}
+
 extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx,
                               const double* Ty, const double* Tz, const int32_t* labels,
                               int32_t d, const int32_t nsub[3], const psl_setup_opts* so,
@@ -1512,6 +1578,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
     if (so->finish_kernels < -1 || so->finish_kernels > 1) return PSL_EINVAL;
     if (so->coarse_sym < -1 || so->coarse_sym > 1) return PSL_EINVAL;
     if (so->stencil_split < -1 || so->stencil_split > 1) return PSL_EINVAL;
+    if (so->face_tables < -1 || so->face_tables > 1) return PSL_EINVAL;
     for (int32_t r : so->reserved)
       if (r != 0) return PSL_EINVAL;
   }
@@ -1569,7 +1636,8 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   PSL_TRY(dalloc(c, &c->invdiag32, n));
   PSL_TRY(dalloc(c, &c->labels, n));
   PSL_TRY(dalloc(c, &c->slot, n));
-  int32_t* flags = nullptr;  // 0 diag, 1 tile overflow, 2 empty column, 3 label range, 4 E pivot
+  int32_t* flags = nullptr;  // 0 diag, 1 tile overflow, 2 empty column, 3 label range, 4 E pivot,
+                             // 5 tile label table overflow
   PSL_TRY(dalloc(c, &flags, 8));
   auto free_flags = [&]() { flags = nullptr; };   // arena memory, freed with the context
   int32_t hflags[8] = {0};
@@ -1684,6 +1752,15 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   hipLaunchKernelGGL(k_az_fill, dim3(c->ntiles), dim3(kBlock), 0, st, gd, c->tiles, c->Tx,
                      c->Ty, c->Tz, c->labels, c->az_ptr, c->az_cell, c->az_lab, c->az_oth,
                      c->az_t, c->az_t32);
+  c->face_tab = !(so && so->face_tables < 0);
+  if (c->face_tab) {
+    if (dalloc(c, &c->az_pk, std::max(m, 1)) ||
+        dalloc(c, &c->tlab, int64_t(c->ntiles) * psl::kTileLabels) ||
+        dalloc(c, &c->tlab_n, c->ntiles))
+      PSL_FAIL(PSL_ENOMEM);
+    hipLaunchKernelGGL(k_az_pack, dim3(c->ntiles), dim3(kBlock), 0, st, c->az_ptr, c->az_cell,
+                       c->az_lab, c->az_oth, d, c->az_pk, c->tlab, c->tlab_n, flags + 5);
+  }
 
   // coarse GEMV layout and solve work space
   c->coarse_blocks = (d + psl::kCoarseRows - 1) / psl::kCoarseRows;
@@ -1738,6 +1815,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   if (rc != PSL_OK) PSL_FAIL(rc);
   if (hflags[2] || hflags[3]) PSL_FAIL(PSL_EINVAL);  // empty column / label out of range
   if (hflags[4]) PSL_FAIL(PSL_ENOTSPD);
+  if (hflags[5]) c->face_tab = 0;   // a tile references more labels than a table holds
   free_flags();
 #undef PSL_FAIL
   *out = c;
@@ -1763,6 +1841,6 @@ extern "C" int psl_get_info(const psl_ctx* c, psl_ctx_info* info) {
   info->nslot_max = c->nslot_max;
   info->coarse_sym = c->coarse_sym;
   info->small_solve = c->small;
-  info->reserved = 0;
+  info->face_tables = c->face_tab;
   return PSL_OK;
 }

@@ -704,6 +704,89 @@ __device__ __forceinline__ void tile_correction(const Tile& T, const FaceRound& 
   }
 }
 
+// The same correction from the tile's coarse table (float32 faces; psl_ctx.face_tab):
+// each face is one packed word of local indices and the tile's few coarse values are
+// gathered once, into registers at prefetch time and LDS here, instead of two gathers
+// per face that wait on the face records. The terms and their sums are the unpacked
+// path's, in the same order: identical results.
+struct FaceRoundPk {
+  int a, b, nt;                // the tile's face range, its table size
+  int32_t pk[kFacePer];
+  float tf[kFacePer];
+  double ev;                   // the coarse value of this thread's table entry
+};
+
+__device__ __forceinline__ void face_prefetch_pk(int t, const int32_t* az_ptr, const int32_t* az_pk,
+                                                 const float* az_t32, const int32_t* tlab,
+                                                 const int32_t* tlab_n, const double* e,
+                                                 bool skip, FaceRoundPk& f) {
+  f.a = ld_uniform(az_ptr + t);
+  f.b = skip ? f.a : ld_uniform(az_ptr + t + 1);
+  f.nt = skip ? 0 : ld_uniform(tlab_n + t);
+  f.ev = 0.0;
+  if (int(threadIdx.x) < f.nt) f.ev = e[tlab[int64_t(t) * psl::kTileLabels + threadIdx.x]];
+#pragma unroll
+  for (int r = 0; r < kFacePer; ++r) {
+    const int k = f.a + int(threadIdx.x) + r * kBlock;
+    if (k < f.b) {
+      f.pk[r] = az_pk[k];
+      f.tf[r] = az_t32[k];
+    }
+  }
+}
+
+__device__ __forceinline__ void tile_correction_pk(const Tile& T, const FaceRoundPk& f,
+                                                   const int32_t* az_pk, const float* az_t32,
+                                                   double* corr, bool skip) {
+  constexpr int kOuter = psl::kTileLabels - 1;
+  __shared__ double etab[psl::kTileLabels];
+  __shared__ double term1[kFaceRound];
+  __shared__ int32_t cellw[kFaceRound];
+  const int a = f.a, b = f.b;
+  if (int(threadIdx.x) < f.nt) etab[threadIdx.x] = f.ev;
+  for (int j = threadIdx.x; j < T.ncell && !skip; j += kBlock) corr[j] = 0.0;
+  __syncthreads();
+  for (int base = a; base < b || base == a; base += kFaceRound) {
+#pragma unroll
+    for (int r = 0; r < kFacePer; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      const int k = base + i;
+      if (k < b) {
+        int32_t pk;
+        double tf;
+        if (base == a) {
+          pk = f.pk[r];
+          tf = f.tf[r];
+        } else {
+          pk = az_pk[k];
+          tf = az_t32[k];
+        }
+        const int il = (pk >> 11) & kOuter, io = (pk >> 18) & kOuter;
+        cellw[i] = pk;
+        term1[i] = tf * (etab[il] - (io == kOuter ? 0.0 : etab[io]));
+      }
+    }
+    __syncthreads();
+    // per cell, in list order
+    const int cnt = min(kFaceRound, b - base);
+#pragma unroll
+    for (int r = 0; r < kFacePer; ++r) {
+      const int i = threadIdx.x + r * kBlock;
+      if (i < cnt) {
+        const int32_t cw = cellw[i];
+        if (cw < 0 || i == 0) {
+          double s1 = term1[i];
+          int m = i + 1;
+          while (m < cnt && cellw[m] >= 0) s1 += term1[m++];
+          corr[cw & 0x7FF] += s1;
+        }
+      }
+    }
+    __syncthreads();
+    if (b <= a) break;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // CG update (iteration of parity PAR). Every workgroup reduces the coarse partials in
 // the same order to gamma = (r, u), delta = (v, u) - s^T e and ||r||^2, so all take the
@@ -1110,7 +1193,7 @@ __global__ void __launch_bounds__(kBlock)
 // Update pass over the tiles tb0, tb0 + step, ... (tile_of_block order; step 0: tile tb0
 // itself, once); the workgroup's (r, u), (r, r) partials go to upart[pidx] and
 // upart[pcount + pidx].
-template <typename R, int CPT, int PAR>
+template <typename R, int CPT, int PAR, bool PK = false>
 __device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int pcount, bool lead_block,
                                        Geo g, const R* __restrict__ q, R* __restrict__ r,
                                        R* __restrict__ u, const R* __restrict__ p,
@@ -1119,11 +1202,14 @@ __device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int
                                        const int32_t* az_lab, const int32_t* az_oth,
                                        const R* az_t, const double* __restrict__ e,
                                        const double* cpart, int G, double* upart, Scalars* sc,
-                                       int bench, int pre) {
+                                       int bench, int pre, const int32_t* az_pk = nullptr,
+                                       const int32_t* tlab = nullptr,
+                                       const int32_t* tlab_n = nullptr) {
+  static_assert(!PK || std::is_same<R, float>::value, "packed faces carry float32 T");
   using psl::ld;
   using psl::st;
-  __shared__ double corr[kTileMax];   // A Z e
-  __shared__ double coef[2];          // alpha, go (1) / stop (0)
+  __shared__ double corr[CPT * kBlock];   // A Z e per local cell (a tile holds at most CPT * kBlock)
+  __shared__ double coef[2];              // alpha, go (1) / stop (0)
   __shared__ double lds[2 * kNW];
   const bool stop = sc->done != 0;   // acted on once the first tile's loads are in flight
   double acc[2] = {0.0, 0.0};
@@ -1132,8 +1218,12 @@ __device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int
     const int t = step > 0 ? tile_of_block(tb, g.ntiles) : tb;
     const Tile T = load_tile(g.tiles, t);
     const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
-    FaceRound fr;   // the cut faces first, then the cell loads
-    face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), stop, fr);
+    // the cut faces (and with packed faces the tile's coarse values) first, then the cells
+    typename std::conditional<PK, FaceRoundPk, FaceRound>::type fr;
+    if constexpr (PK)
+      face_prefetch_pk(t, az_ptr, az_pk, az32(az_t), tlab, tlab_n, e, stop, fr);
+    else
+      face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), stop, fr);
     int cc[CPT];
     R qv[CPT], rv[CPT], pv[CPT], xv[CPT], dv[CPT];
 #pragma unroll
@@ -1192,8 +1282,11 @@ __device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int
         coef[1] = go;
       }
     }
-    tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
-                           corr, corr, stop);  // ends with a barrier
+    if constexpr (PK)
+      tile_correction_pk(T, fr, az_pk, az32(az_t), corr, stop);   // ends with a barrier
+    else
+      tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
+                             corr, corr, stop);  // ends with a barrier
     if (coef[1] == 0.0) return;
     const R alpha = R(coef[0]);
 #pragma unroll
@@ -1220,16 +1313,18 @@ __device__ __forceinline__ void sd_update_tiles(int tb0, int step, int pidx, int
   }
 }
 
-template <typename R, int CPT, int PAR>
+template <typename R, int CPT, int PAR, bool PK>
 __global__ void __launch_bounds__(kBlock)
     k_sd_update(Geo g, const R* __restrict__ q, R* __restrict__ r, R* __restrict__ u,
                 const R* __restrict__ p, R* __restrict__ x, const R* __restrict__ invd,
                 const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
                 const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
-                const double* cpart, int G, double* upart, Scalars* sc, int bench, int pre) {
-  sd_update_tiles<R, CPT, PAR>(blockIdx.x, gridDim.x, blockIdx.x, gridDim.x, blockIdx.x == 0, g,
-                               q, r, u, p, x, invd, az_ptr, az_cell, az_lab, az_oth, az_t, e,
-                               cpart, G, upart, sc, bench, pre);
+                const double* cpart, int G, double* upart, Scalars* sc, int bench, int pre,
+                const int32_t* az_pk, const int32_t* tlab, const int32_t* tlab_n) {
+  sd_update_tiles<R, CPT, PAR, PK>(blockIdx.x, gridDim.x, blockIdx.x, gridDim.x,
+                                   blockIdx.x == 0, g, q, r, u, p, x, invd, az_ptr, az_cell,
+                                   az_lab, az_oth, az_t, e, cpart, G, upart, sc, bench, pre,
+                                   az_pk, tlab, tlab_n);
 }
 
 // Step decisions of the two-reduction iteration of parity PAR in one workgroup (the same
@@ -2044,10 +2139,19 @@ struct SdUpdateC {
   struct F {
     static void run(psl_ctx* c, hipStream_t st, int bench) {
       psl::VecSet<R>& v = Prec<R>::vecs(c);
-      hipLaunchKernelGGL((k_sd_update<R, CPT, PAR>), dim3(c->upd_blocks), dim3(kBlock), 0, st,
-                         geo(c), v.q, v.rh, v.u, PAR ? v.p2 : v.p, v.xh, Prec<R>::invd(c),
-                         c->az_ptr, c->az_cell, c->az_lab, c->az_oth, Prec<R>::azt(c), c->e,
-                         c->cpart, coarse_parts(c), c->upart, c->sc, bench, c->pre);
+      if (std::is_same<R, float>::value && c->face_tab)
+        hipLaunchKernelGGL((k_sd_update<R, CPT, PAR, std::is_same<R, float>::value>),
+                           dim3(c->upd_blocks), dim3(kBlock), 0, st, geo(c), v.q, v.rh, v.u,
+                           PAR ? v.p2 : v.p, v.xh, Prec<R>::invd(c), c->az_ptr, c->az_cell,
+                           c->az_lab, c->az_oth, Prec<R>::azt(c), c->e, c->cpart,
+                           coarse_parts(c), c->upart, c->sc, bench, c->pre, c->az_pk, c->tlab,
+                           c->tlab_n);
+      else
+        hipLaunchKernelGGL((k_sd_update<R, CPT, PAR, false>), dim3(c->upd_blocks), dim3(kBlock),
+                           0, st, geo(c), v.q, v.rh, v.u, PAR ? v.p2 : v.p, v.xh,
+                           Prec<R>::invd(c), c->az_ptr, c->az_cell, c->az_lab, c->az_oth,
+                           Prec<R>::azt(c), c->e, c->cpart, coarse_parts(c), c->upart, c->sc,
+                           bench, c->pre, nullptr, nullptr, nullptr);
     }
   };
 };

@@ -1045,3 +1045,38 @@ def test_profile_kernel(gpu_lib):
         else:
             assert len(dur) >= 1
         s.ctx.destroy()
+
+
+FACE_CASES = [("c2", 4, {}, False), ("c3", 4, {"contrast": 1e5}, True), ("ragged", 0, {}, False)]
+
+
+@pytest.mark.parametrize("finish", [1, -1], ids=["finish", "passes"])
+@pytest.mark.parametrize("name,scale,kw,components", FACE_CASES,
+                         ids=["c2-4", "c3-4-components", "ragged-0"])
+def test_face_tables(gpu_lib, name, scale, kw, components, finish):
+    """The float32 update with per-tile coarse tables (each cut face packed into one word of
+    local indices, the tile's coarse values gathered once) against the unpacked faces, with
+    and without finish kernels, in mixed precision: the same terms summed in the same order,
+    so x is bit-identical with equal iteration and refinement counts; and the oracle's
+    residual of x."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _problem(name, scale, kw)
+    say(f"face tables {name}/{scale} components={components} finish={finish} grid={p.grid}")
+    K, b = dev(p.K), dev(p.q)
+    out = {}
+    for ft in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr),
+                           components=components, finish_kernels=finish, face_tables=ft)
+        assert psl.psl_get_info(s.ctx)["face_tables"] == (ft > 0)
+        x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=psl.MIXED)
+        out[ft] = (x.clone(), st)
+        s.ctx.destroy()
+    (x1, st1), (x0, st0) = out[1], out[-1]
+    A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    res = O.relres(A, bh, host(x1))
+    say(f"  tables: iters={st1['iters']} outer={st1['outer']} relres={res:.2e}; "
+        f"unpacked: iters={st0['iters']} outer={st0['outer']}")
+    assert st1["status"] == 0 and res <= 1e-8
+    assert (st1["iters"], st1["outer"]) == (st0["iters"], st0["outer"])
+    assert torch.equal(x1, x0)
