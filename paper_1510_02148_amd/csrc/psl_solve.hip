@@ -3346,22 +3346,30 @@ __global__ void __launch_bounds__(kBlock) k_pc_beta(PcScalars* s, const double* 
 
 // x += alpha p, r -= alpha (w - A Z e): w = A p from the stencil pass, A Z e applied on the
 // tile's cut faces from LDS (the deflation step of w = P1 A p, fused into the update)
-template <typename R>
+template <typename R, bool PK>
 __global__ void __launch_bounds__(kBlock)
     k_pc_update(Geo g, const int32_t* az_ptr, const int32_t* az_cell, const int32_t* az_lab,
                 const int32_t* az_oth, const R* az_t, const double* __restrict__ e,
                 const PcScalars* s, const R* __restrict__ p, const R* __restrict__ w,
-                R* __restrict__ x, R* __restrict__ r) {
+                R* __restrict__ x, R* __restrict__ r, const int32_t* az_pk,
+                const int32_t* tlab, const int32_t* tlab_n) {
+  static_assert(!PK || std::is_same<R, float>::value, "packed faces carry float32 T");
   __shared__ double corr[kTileMax];
   const double ad = s->alpha;
   if (ad == 0.0) return;
   const R a = R(ad);
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
-  FaceRound fr;
-  face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), false, fr);
-  tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
-                         corr, corr, false);
+  if constexpr (PK) {   // packed faces and the tile's coarse table (float32 T)
+    FaceRoundPk fr;
+    face_prefetch_pk(t, az_ptr, az_pk, az32(az_t), tlab, tlab_n, e, false, fr);
+    tile_correction_pk(T, fr, az_pk, az32(az_t), corr, false);
+  } else {
+    FaceRound fr;
+    face_prefetch(t, az_ptr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), false, fr);
+    tile_correction<false>(T, fr, az_cell, az_lab, az_oth, az32(az_t), az64(az_t), e, nullptr,
+                           corr, corr, false);
+  }
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
   for (int j = threadIdx.x; j < T.ncell; j += kBlock) {
     int ix, iy, iz;
@@ -3662,12 +3670,27 @@ void pc_iteration(psl_ctx* c, const PcBufsT<R>& B, const PcPlan& pl, R* x, hipSt
   hipLaunchKernelGGL(k_pc_alpha, dim3(1), dim3(kBlock), 0, st, B.s,
                      static_cast<const double*>(red(c, 0)), c->ntiles,
                      static_cast<const double*>(c->cpart), coarse_parts(c));
-  hipLaunchKernelGGL((k_pc_update<R>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
-                     static_cast<const int32_t*>(c->az_ptr), static_cast<const int32_t*>(c->az_cell),
-                     static_cast<const int32_t*>(c->az_lab), static_cast<const int32_t*>(c->az_oth),
-                     Prec<R>::azt(c), static_cast<const double*>(c->e),
-                     static_cast<const PcScalars*>(B.s), static_cast<const R*>(B.p),
-                     static_cast<const R*>(B.w), x, B.r);
+  if (std::is_same<R, float>::value && c->face_tab)
+    hipLaunchKernelGGL((k_pc_update<R, std::is_same<R, float>::value>), dim3(c->ntiles),
+                       dim3(kBlock), 0, st, geo(c), static_cast<const int32_t*>(c->az_ptr),
+                       static_cast<const int32_t*>(c->az_cell),
+                       static_cast<const int32_t*>(c->az_lab),
+                       static_cast<const int32_t*>(c->az_oth), Prec<R>::azt(c),
+                       static_cast<const double*>(c->e), static_cast<const PcScalars*>(B.s),
+                       static_cast<const R*>(B.p), static_cast<const R*>(B.w), x, B.r,
+                       static_cast<const int32_t*>(c->az_pk),
+                       static_cast<const int32_t*>(c->tlab),
+                       static_cast<const int32_t*>(c->tlab_n));
+  else
+    hipLaunchKernelGGL((k_pc_update<R, false>), dim3(c->ntiles), dim3(kBlock), 0, st, geo(c),
+                       static_cast<const int32_t*>(c->az_ptr),
+                       static_cast<const int32_t*>(c->az_cell),
+                       static_cast<const int32_t*>(c->az_lab),
+                       static_cast<const int32_t*>(c->az_oth), Prec<R>::azt(c),
+                       static_cast<const double*>(c->e), static_cast<const PcScalars*>(B.s),
+                       static_cast<const R*>(B.p), static_cast<const R*>(B.w), x, B.r,
+                       static_cast<const int32_t*>(nullptr), static_cast<const int32_t*>(nullptr),
+                       static_cast<const int32_t*>(nullptr));
   pc_precondition<R>(c, B, pl, B.r, st);
   hipLaunchKernelGGL(k_pc_beta, dim3(1), dim3(kBlock), 0, st, B.s,
                      static_cast<const double*>(B.part), c->ntiles);

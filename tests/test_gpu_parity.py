@@ -1056,9 +1056,10 @@ FACE_CASES = [("c2", 4, {}, False), ("c3", 4, {"contrast": 1e5}, True), ("ragged
 def test_face_tables(gpu_lib, name, scale, kw, components, finish):
     """The float32 update with per-tile coarse tables (each cut face packed into one word of
     local indices, the tile's coarse values gathered once) against the unpacked faces, with
-    and without finish kernels, in mixed precision: the same terms summed in the same order,
-    so x is bit-identical with equal iteration and refinement counts; and the oracle's
-    residual of x."""
+    and without finish kernels, in mixed precision, for the Jacobi CG and the Chebyshev
+    polynomial CG (whose update applies the same correction): the same terms summed in the
+    same order, so x is bit-identical with equal iteration and refinement counts; and the
+    oracle's residual of x."""
     psl = gpu_lib
     from paper_1510_02148_amd import pipeline
     p = _problem(name, scale, kw)
@@ -1070,8 +1071,13 @@ def test_face_tables(gpu_lib, name, scale, kw, components, finish):
                            components=components, finish_kernels=finish, face_tables=ft)
         assert psl.psl_get_info(s.ctx)["face_tables"] == (ft > 0)
         x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=psl.MIXED)
+        xp, stp = psl.psl_solve_poly(s.ctx, b, tol=1e-8, mixed=True)
         out[ft] = (x.clone(), st)
+        out[(ft, "poly")] = (xp.clone(), stp)
         s.ctx.destroy()
+    (xp1, stp1), (xp0, stp0) = out[(1, "poly")], out[(-1, "poly")]
+    say(f"  polynomial CG: tables iters={stp1['iters']}, unpacked iters={stp0['iters']}")
+    assert stp1["iters"] == stp0["iters"] and torch.equal(xp1, xp0)
     (x1, st1), (x0, st0) = out[1], out[-1]
     A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
     res = O.relres(A, bh, host(x1))
