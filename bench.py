@@ -66,6 +66,10 @@ def algorithmic_bytes(kernel: str, grid, d: int, m_faces: int, w: int, two: bool
     nx, ny, nz = grid
     n = nx * ny * nz
     faces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    if kernel == "direction":   # split stencil step: read u, p_prev; write p
+        return 3 * w * n
+    if kernel == "stencil_split":   # its plain stencil: read p, Tx, Ty, Tz, slot; write q
+        return 2 * w * n + w * faces + 1 * n
     if kernel == "stencil":
         if two:   # read u, p_prev, Tx, Ty, Tz, slot; write p, q = A p
             return 4 * w * n + w * faces + 1 * n
@@ -566,10 +570,14 @@ def main():
                                   "us_per_iteration": round(t["us"] / iters, 3),
                                   "total_ms": round(t["total_ms"], 3), "timing": "in-solve"}
     elif args.solver == "dpcg":
-        # inside real solves: every launch of the kernel in the solve's own precision
+        # inside real solves: every launch of the kernel in the solve's own precision (the
+        # direction pass has launches only where the float32 stencil step is split)
+        if mode == psl.MIXED:
+            ids["direction"] = psl.KERNEL_DIRECTION
         times = in_solve_kernel_times(psl, s.ctx, b, prob.tol, mode, ids)
         for name, t in times.items():
-            nbytes = algorithmic_bytes(name, prob.grid, d, m_faces, w, mode == psl.MIXED,
+            model = "stencil_split" if (name == "stencil" and "direction" in times) else name
+            nbytes = algorithmic_bytes(model, prob.grid, d, m_faces, w, mode == psl.MIXED,
                                        bool(info["coarse_sym"]), bool(info["face_tables"]))
             kernels[name] = {"us": round(t["us"], 3), "alg_bytes": int(nbytes),
                              "gbs": round(nbytes / (t["us"] * 1e-6) / 1e9, 1),

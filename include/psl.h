@@ -414,7 +414,10 @@ int psl_get_coarse(psl_ctx* ctx, double* E, double* Einv, int32_t* d, void* stre
 #define PSL_KERNEL_STENCIL        0  /* v = A M^-1 r and the CG inner products (pass 1) */
 #define PSL_KERNEL_COARSE         1  /* e = E^-1 Z^T v (coarse GEMV) and scalar slices    */
 #define PSL_KERNEL_UPDATE         2  /* p, q, x, r updates with A Z e   (pass 2)          */
-#define PSL_KERNEL_DIRECTION      3  /* reserved (the direction update is part of pass 2) */
+#define PSL_KERNEL_DIRECTION      3  /* the direction pass p = u + beta p_prev of the split
+                                        float32 stencil step (finish kernels on);
+                                        psl_profile_kernel only (elsewhere the direction
+                                        update is part of another pass) */
 #define PSL_KERNEL_OUTER_RESIDUAL 4  /* r = b - A x in float64          (refinement step) */
 #define PSL_KERNEL_GMRES_PASS     5  /* deflated GMRES: w -= V h with the dots V^T w (fused
                                         Gram-Schmidt pass over min(m, 32) basis vectors,
@@ -449,8 +452,8 @@ int psl_bench_kernel(psl_ctx* ctx, int32_t kernel, int32_t mode, int32_t reps, v
 /*
  * psl_profile_kernel -- time one kernel of the CG iteration inside the following psl_solve
  * calls on this context: an event is recorded on the solve's stream before and after each
- * launch of `kernel` (PSL_KERNEL_STENCIL (with finish kernels: the direction pass and the
- * stencil pass together), PSL_KERNEL_COARSE (the label sum and the coarse product
+ * launch of `kernel` (PSL_KERNEL_STENCIL, PSL_KERNEL_DIRECTION (the split float32 stencil
+ * step's direction pass), PSL_KERNEL_COARSE (the label sum and the coarse product
  * together), PSL_KERNEL_UPDATE, or PSL_KERNEL_SMALL_SOLVE with PSL_FP64) in the precision
  * of `mode` (PSL_MIXED: the float32 launches of a mixed solve), for up to `max_launches`
  * launches (1 .. 2^20) counted from this call. While the first three are armed, the solves

@@ -2258,11 +2258,17 @@ void launch_sd_stencil(psl_ctx* c, hipStream_t st, int bench) {
     const R* pprev = PAR ? v.p : v.p2;
     R* pout = PAR ? v.p2 : v.p;
     constexpr int64_t per_block = int64_t(kBlock) * (16 / sizeof(R));
+    prof_begin<R>(c, PSL_KERNEL_DIRECTION, st);
     hipLaunchKernelGGL((k_sd_dir<R, PAR>), dim3(unsigned((c->n + per_block - 1) / per_block)),
                        dim3(kBlock), 0, st, int64_t(c->n), v.u, pprev, pout, c->sc, bench);
+    prof_end<R>(c, PSL_KERNEL_DIRECTION, st);
+    prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
     launch_stencil<R, 0>(c, pout, nullptr, v.q, st, c->sc);
+    prof_end<R>(c, PSL_KERNEL_STENCIL, st);
   } else {
+    prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
     with_ns<SdStencilL<R, PAR>::template F>(c->nslot_max, c, st, bench);
+    prof_end<R>(c, PSL_KERNEL_STENCIL, st);
   }
 }
 
@@ -2272,9 +2278,7 @@ void enqueue_sd_iteration(psl_ctx* c, hipStream_t st) {
   if (c->pre)
     hipLaunchKernelGGL(k_sd_finish_b<PAR>, dim3(1), dim3(1024), 0, st, c->upart,
                        c->upd_blocks, c->sc);
-  prof_begin<R>(c, PSL_KERNEL_STENCIL, st);
-  launch_sd_stencil<R, PAR>(c, st, 0);
-  prof_end<R>(c, PSL_KERNEL_STENCIL, st);
+  launch_sd_stencil<R, PAR>(c, st, 0);   // times its own launches when profiling
   prof_begin<R>(c, PSL_KERNEL_COARSE, st);
   launch_coarse<0, 1>(c, 1, st);
   prof_end<R>(c, PSL_KERNEL_COARSE, st);
@@ -2773,7 +2777,8 @@ extern "C" int psl_profile_kernel(psl_ctx* c, int32_t kernel, int32_t mode, int3
     return PSL_OK;
   }
   if ((kernel != PSL_KERNEL_STENCIL && kernel != PSL_KERNEL_COARSE &&
-       kernel != PSL_KERNEL_UPDATE && kernel != PSL_KERNEL_SMALL_SOLVE) ||
+       kernel != PSL_KERNEL_UPDATE && kernel != PSL_KERNEL_DIRECTION &&
+       kernel != PSL_KERNEL_SMALL_SOLVE) ||
       (mode != PSL_FP64 && mode != PSL_MIXED) || max_launches < 1 || max_launches > (1 << 20) ||
       (kernel == PSL_KERNEL_SMALL_SOLVE && mode != PSL_FP64))
     return PSL_EINVAL;
