@@ -442,6 +442,88 @@ __global__ void k_cc_hook(int n, int nx, int ny, int nz, const int32_t* __restri
   if (iz + 1 < nz && key[c + nx * ny] == k) cc_union(parent, c, c + nx * ny);
 }
 
+// The same union-find inside one subdomain box, in LDS. A component never crosses a
+// subdomain boundary (the key holds the subdomain), so each box is labelled on its own:
+// one workgroup per box loads its cells' keys, unites equal-key neighbours with LDS
+// compare-and-swap (larger root under smaller, as above), and writes every cell's root as
+// a global cell index. Local order within a box is global order, so the root of each
+// component is again its smallest cell and the result equals the global kernels'.
+constexpr int kCcLocalMax = 8192;   // cells of the largest box held in LDS
+
+__device__ inline int lcc_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline int lcc_find(int32_t* par, int x) {
+  int cur = x;
+  int next = lcc_load(par + cur);
+  while (next != cur) {
+    const int up = lcc_load(par + next);
+    if (up != next)   // path halving: cur is not a root, so no union targets it
+      __hip_atomic_store(par + cur, up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    cur = next;
+    next = up;
+  }
+  return cur;
+}
+
+__device__ inline void lcc_union(int32_t* par, int a, int b) {
+  a = lcc_find(par, a);
+  b = lcc_find(par, b);
+  while (a != b) {
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    int expected = a;   // a must still be a root
+    if (__hip_atomic_compare_exchange_strong(par + a, &expected, b, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+    a = lcc_find(par, expected);
+    b = lcc_find(par, b);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cc_local(int nx, int ny, int nz, int sx, int sy,
+                                                     int sz, int ncls, const double* K,
+                                                     const int32_t* cls, ThrPack thr,
+                                                     int nkeys, int32_t* parent, int32_t* bad) {
+  __shared__ int32_t lpar[kCcLocalMax];
+  __shared__ int32_t lkey[kCcLocalMax];
+  const int b = blockIdx.x, bx = b % sx, by = (b / sx) % sy, bz = b / (sx * sy);
+  // the box: cells whose floor-partition index is (bx, by, bz)
+  const int x0 = int((int64_t(bx) * nx + sx - 1) / sx), x1 = int((int64_t(bx + 1) * nx + sx - 1) / sx);
+  const int y0 = int((int64_t(by) * ny + sy - 1) / sy), y1 = int((int64_t(by + 1) * ny + sy - 1) / sy);
+  const int z0 = int((int64_t(bz) * nz + sz - 1) / sz), z1 = int((int64_t(bz + 1) * nz + sz - 1) / sz);
+  const int ex = x1 - x0, ey = y1 - y0, m = ex * ey * (z1 - z0);
+  for (int li = threadIdx.x; li < m; li += kBlock) {
+    const int lx = li % ex, ly = (li / ex) % ey, lz = li / (ex * ey);
+    const int c = (x0 + lx) + nx * ((y0 + ly) + ny * (z0 + lz));
+    const int k = cell_key(c, nx, ny, nz, sx, sy, sz, ncls, K, cls, thr);
+    if (k < 0 || k >= nkeys) bad[0] = 1;
+    lkey[li] = k;
+    lpar[li] = li;
+  }
+  __syncthreads();
+  for (int li = threadIdx.x; li < m; li += kBlock) {
+    const int lx = li % ex, ly = (li / ex) % ey, lz = li / (ex * ey);
+    const int k = lkey[li];
+    if (lx + 1 < ex && lkey[li + 1] == k) lcc_union(lpar, li, li + 1);
+    if (ly + 1 < ey && lkey[li + ex] == k) lcc_union(lpar, li, li + ex);
+    if (lz + 1 < z1 - z0 && lkey[li + ex * ey] == k) lcc_union(lpar, li, li + ex * ey);
+  }
+  __syncthreads();
+  for (int li = threadIdx.x; li < m; li += kBlock) {
+    int r = li;
+    while (lpar[r] != r) r = lpar[r];
+    const int lx = li % ex, ly = (li / ex) % ey, lz = li / (ex * ey);
+    const int rx = r % ex, ry = (r / ex) % ey, rz = r / (ex * ey);
+    parent[(x0 + lx) + nx * ((y0 + ly) + ny * (z0 + lz))] =
+        (x0 + rx) + nx * ((y0 + ry) + ny * (z0 + rz));
+  }
+}
+
 // Every cell points straight at its root. The walk does not halve paths: a halving
 // store from one thread could land after another thread has written the root to that
 // cell and leave it pointing at an intermediate node. Here each thread writes only its
@@ -570,10 +652,19 @@ extern "C" int psl_build_Z_cc(const psl_grid* g, const double* K, const int32_t 
   }
   int32_t* parent = labels;   // the output array holds the union-find forest until the end
   hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, bad, 0, int64_t(1));
-  hipLaunchKernelGGL(k_cc_init, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, nsub[0],
-                     nsub[1], nsub[2], ncls, K, cls, tp, nkeys, key, parent, bad);
-  hipLaunchKernelGGL(k_cc_hook, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, key, parent);
-  hipLaunchKernelGGL(k_cc_compress, dim3(nblocks(n)), dim3(kBlock), 0, st, n, parent);
+  // the largest subdomain box of the floor partition
+  const int64_t box_max = int64_t((nx + nsub[0] - 1) / nsub[0]) * ((ny + nsub[1] - 1) / nsub[1]) *
+                          ((nz + nsub[2] - 1) / nsub[2]);
+  if (box_max <= kCcLocalMax) {   // every box in LDS: one workgroup per box
+    hipLaunchKernelGGL(k_cc_local, dim3(nsub[0] * nsub[1] * nsub[2]), dim3(kBlock), 0, st, nx, ny,
+                       nz, nsub[0], nsub[1], nsub[2], ncls, K, cls, tp, nkeys, parent, bad);
+  } else {
+    hipLaunchKernelGGL(k_cc_init, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz,
+                       nsub[0], nsub[1], nsub[2], ncls, K, cls, tp, nkeys, key, parent, bad);
+    hipLaunchKernelGGL(k_cc_hook, dim3(nblocks(n)), dim3(kBlock), 0, st, n, nx, ny, nz, key,
+                       parent);
+    hipLaunchKernelGGL(k_cc_compress, dim3(nblocks(n)), dim3(kBlock), 0, st, n, parent);
+  }
   hipLaunchKernelGGL(k_cc_count, dim3(nblk), dim3(kBlock), 0, st, n, parent, bsum);
   hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bsum, boff, nblk);
   hipLaunchKernelGGL(k_cc_rank, dim3(nblk), dim3(kBlock), 0, st, n, parent, boff, key);
