@@ -206,8 +206,9 @@ __device__ inline T wave_sum(T v) {
 template <int CTRL>
 __device__ inline double dpp_double(double v) {
   const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
-  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false);
+  // the move form (no "old" operand to preset; no source lane is ever out of range)
+  const int lo = __builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(static_cast<long long>(
       (static_cast<unsigned long long>(unsigned(hi)) << 32) | unsigned(lo)));
 }
@@ -219,49 +220,67 @@ __device__ inline double read_lane(double v, int lane) {
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// Sum of a float64 over the 64 lanes of a wave (every lane active), the same value in
-// every lane, in a fixed order: within each row of 16 lanes a butterfly of lane pairs
-// (lane xor 1, xor 2 by quad permutes, then the mirrored quad of each 8 and the mirrored
-// 8 of each 16; a + b and b + a round alike, so every lane of a row holds the same row
-// sum), then the four row sums added in row order. DPP moves and lane reads run on the
-// vector ALU; the generic version's cross-lane permutes go through the LDS unit.
-__device__ inline double wave_sum(double v) {
+// Sum of a float64 over each row of 16 lanes (every lane active), in a fixed order: a
+// butterfly of lane pairs (lane xor 1, xor 2 by quad permutes, then the mirrored quad of
+// each 8 and the mirrored 8 of each 16; a + b and b + a round alike, so every lane of a
+// row ends holding the same row sum). DPP moves run on the vector ALU; the generic
+// version's cross-lane permutes go through the LDS unit.
+__device__ inline double row_sum(double v) {
   v += dpp_double<0xB1>(v);    // quad_perm [1, 0, 3, 2]: lane xor 1
   v += dpp_double<0x4E>(v);    // quad_perm [2, 3, 0, 1]: lane xor 2
   v += dpp_double<0x141>(v);   // row_half_mirror: the other quad of each 8
   v += dpp_double<0x140>(v);   // row_mirror: the other 8 of each 16
+  return v;
+}
+
+// Sum of a float64 over the 64 lanes of a wave, the same value in every lane: the row
+// sums, then the four rows added in row order by lane reads.
+__device__ inline double wave_sum(double v) {
+  v = row_sum(v);
   return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
 }
 
-// Block-wide sum of NV values per thread in a fixed tree order; result valid in
-// every thread. lds must hold NV * (kBlock / kWave) doubles.
-// block_sum of the entries whose bit is set in `active` (the same mask in every thread,
-// so the skips are uniform branches); the other entries are left unreduced and must not
-// be read. Tiles with fewer labels than their kernel's slot count skip the unused slots.
+constexpr int kSumRows = kBlock / 16;   // rows of 16 lanes in a workgroup
+
+// doubles of LDS that block_sum_active<NV> needs
+constexpr int block_sum_lds(int nv) { return nv * (kSumRows + 1); }
+
+// Workgroup sums of the entries of v whose bit is set in `active` (the same mask in every
+// thread, so the skips are uniform branches), in a fixed order: each row of 16 lanes sums
+// by the DPP butterfly, then the 16 row sums of an entry are added in row order by one
+// thread, and every thread reads the results back. The other entries are left unreduced
+// and must not be read. Each wave moves only its row sums, so an entry costs a wave four
+// DPP steps rather than the four steps plus eight lane reads of a whole-wave sum, and the
+// row sums of all entries are added by different threads side by side. lds must hold
+// block_sum_lds(NV) doubles.
 template <int NV>
 __device__ inline void block_sum_active(double (&v)[NV], double* lds, unsigned long long active) {
   static_assert(NV <= 64, "active mask");
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  constexpr int NW = kBlock / kWave;
+  static_assert(NV <= kBlock, "one thread per entry");
+  const int row = threadIdx.x >> 4;
+  double* tot = lds + NV * kSumRows;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
-    if ((active >> k) & 1ull) v[k] = wave_sum(v[k]);
+    if ((active >> k) & 1ull) v[k] = row_sum(v[k]);
   __syncthreads();
-  if (lane == 0) {
+  if ((threadIdx.x & 15) == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if ((active >> k) & 1ull) lds[k * NW + w] = v[k];
+      if ((active >> k) & 1ull) lds[k * kSumRows + row] = v[k];
+  }
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e < NV && ((active >> e) & 1ull)) {
+    const double* r = lds + e * kSumRows;
+    double acc = r[0];
+#pragma unroll
+    for (int j = 1; j < kSumRows; ++j) acc += r[j];
+    tot[e] = acc;
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    if (!((active >> k) & 1ull)) continue;
-    double acc = 0.0;
-#pragma unroll
-    for (int j = 0; j < NW; ++j) acc += lds[k * NW + j];
-    v[k] = acc;
-  }
+  for (int k = 0; k < NV; ++k)
+    if ((active >> k) & 1ull) v[k] = tot[k];
   __syncthreads();
 }
 

@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kBlock)
               const R* __restrict__ in, const double* __restrict__ b, R* __restrict__ out,
               const uint8_t* __restrict__ slot, const int32_t* __restrict__ slot_pos,
               double* zq, double* red, const Scalars* stop) {
-  __shared__ double lds[(NS + 1) * kNW];
+  __shared__ double lds[psl::block_sum_lds(NS + 1)];
   if (stop && stop->done) return;   // an iteration enqueued past the stop
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
@@ -152,21 +152,22 @@ __global__ void __launch_bounds__(kBlock)
       const int fx = c + (iy + ny * iz);          // ix + (nx+1)(iy + ny iz)
       const int fy = c + nx * iz;                 // ix + nx(iy + (ny+1) iz)
       cc[k] = c;
-      pc[k] = in[c];
-      pw[k] = ix > 0 ? in[c - 1] : R(0);
-      pe[k] = ix < nx - 1 ? in[c + 1] : R(0);
-      ps[k] = iy > 0 ? in[c - nx] : R(0);
-      pn[k] = iy < ny - 1 ? in[c + nx] : R(0);
-      pb[k] = iz > 0 ? in[c - sxy] : R(0);
-      pt[k] = iz < nz - 1 ? in[c + sxy] : R(0);
-      t0[k] = Tx[fx];
-      t1[k] = Tx[fx + 1];
-      t2[k] = Ty[fy];
-      t3[k] = Ty[fy + nx];
-      t4[k] = Tz[c];
-      t5[k] = Tz[c + sxy];
-      sl[k] = slot[c];
-      bv[k] = MODE == 1 ? b[c] : 0.0;
+      const uint32_t u = uint32_t(c);
+      pc[k] = psl::ld(in, u);
+      pw[k] = ix > 0 ? psl::ld(in, u - 1u) : R(0);
+      pe[k] = ix < nx - 1 ? psl::ld(in, u + 1u) : R(0);
+      ps[k] = iy > 0 ? psl::ld(in, u - uint32_t(nx)) : R(0);
+      pn[k] = iy < ny - 1 ? psl::ld(in, u + uint32_t(nx)) : R(0);
+      pb[k] = iz > 0 ? psl::ld(in, u - uint32_t(sxy)) : R(0);
+      pt[k] = iz < nz - 1 ? psl::ld(in, u + uint32_t(sxy)) : R(0);
+      t0[k] = psl::ld(Tx, uint32_t(fx));
+      t1[k] = psl::ld(Tx, uint32_t(fx + 1));
+      t2[k] = psl::ld(Ty, uint32_t(fy));
+      t3[k] = psl::ld(Ty, uint32_t(fy + nx));
+      t4[k] = psl::ld(Tz, u);
+      t5[k] = psl::ld(Tz, u + uint32_t(sxy));
+      sl[k] = psl::ld(slot, u);
+      bv[k] = MODE == 1 ? psl::ld(b, u) : 0.0;
     }
   }
   double acc[NS + 1];
@@ -184,17 +185,18 @@ __global__ void __launch_bounds__(kBlock)
     ap += t5[k] * (p0 - pt[k]);
     double v;
     if (MODE == 0) {
-      out[cc[k]] = ap;
+      psl::st(out, uint32_t(cc[k]), ap);
       v = double(ap);
       acc[NS] += double(p0) * v;
     } else {
       const double r = bv[k] - double(ap);
-      out[cc[k]] = R(r);
+      psl::st(out, uint32_t(cc[k]), R(r));
       v = r;
       acc[NS] += r * r;
     }
 #pragma unroll
-    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? v : 0.0;
+    for (int m = 0; m < NS; ++m)
+      if (m < T.nslot) acc[m] += (sl[k] == m) ? v : 0.0;   // uniform: the tile's slots
   }
   psl::block_sum_active<NS + 1>(acc, lds, psl::low_bits(T.nslot) | (1ull << NS));
   double zs[NS];
@@ -218,7 +220,7 @@ __device__ __forceinline__ void cg_stencil_tile(int t, Geo g, const R* __restric
                                        double* zr, double* red, const Scalars* sc) {
   using psl::ld;
   constexpr int NA = NS + 3 + (RP ? NS : 0);
-  __shared__ double lds[NA * kNW];
+  __shared__ double lds[psl::block_sum_lds(NA)];
   // the stop flag is read first but acted on once the cell loads are in flight: the
   // launch then costs one memory round trip less on its critical path
   const bool stop = sc->done != 0;
@@ -278,11 +280,13 @@ __device__ __forceinline__ void cg_stencil_tile(int t, Geo g, const R* __restric
     acc[NS + 1] += double(rc[k] * u0);
     acc[NS + 2] += double(rc[k] * rc[k]);
 #pragma unroll
-    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? vd : 0.0;
+    for (int m = 0; m < NS; ++m)
+      if (m < T.nslot) acc[m] += (sl[k] == m) ? vd : 0.0;
     if (RP) {
       const double rd = double(rc[k]);
 #pragma unroll
-      for (int m = 0; m < NS; ++m) acc[NS + 3 + m] += (sl[k] == m) ? rd : 0.0;
+      for (int m = 0; m < NS; ++m)
+        if (m < T.nslot) acc[NS + 3 + m] += (sl[k] == m) ? rd : 0.0;
     }
   }
   psl::block_sum_active<NA>(acc, lds, psl::low_bits(T.nslot) | (7ull << NS) |
@@ -1031,7 +1035,7 @@ __device__ __forceinline__ void sd_stencil_tile(int t, bool lead_block, Geo g, c
                                        int bench, int pre) {
   using psl::ld;
   using psl::st;
-  __shared__ double lds[(NS + 1) * kNW];
+  __shared__ double lds[psl::block_sum_lds(NS + 1)];
   __shared__ double lds2[2 * kNW];
   const bool stop = sc->done != 0;   // acted on once the cell loads are in flight
   const Tile T = load_tile(g.tiles, t);
@@ -1141,7 +1145,8 @@ __device__ __forceinline__ void sd_stencil_tile(int t, bool lead_block, Geo g, c
     const double qd = double(ap);
     acc[NS] += double(p0) * qd;
 #pragma unroll
-    for (int m = 0; m < NS; ++m) acc[m] += (sl[k] == m) ? qd : 0.0;
+    for (int m = 0; m < NS; ++m)
+      if (m < T.nslot) acc[m] += (sl[k] == m) ? qd : 0.0;
   }
   psl::block_sum_active<NS + 1>(acc, lds, psl::low_bits(T.nslot) | (1ull << NS));
   double zs[NS];
@@ -1535,7 +1540,7 @@ template <int NS>
 __global__ void __launch_bounds__(kBlock)
     k_zt(Geo g, const double* __restrict__ v, const uint8_t* __restrict__ slot,
          const int32_t* __restrict__ slot_pos, double* zq) {
-  __shared__ double lds[NS * kNW];
+  __shared__ double lds[psl::block_sum_lds(NS)];
   const int t = tile_of_block(blockIdx.x, g.ntiles);
   const Tile T = load_tile(g.tiles, t);
   const float inv_sx = 1.0f / T.sx, inv_sxy = 1.0f / (T.sx * T.sy);
