@@ -308,7 +308,14 @@ typedef struct {
                            tile's few coarse values once, early, instead of one per face
                            (bit-identical results); -1 keeps the unpacked faces. A tile
                            with more labels than the table holds keeps them too */
-  int32_t reserved[3];  /* must be 0 */
+  int32_t wide_tiles;   /* 0 (default) or 1: where a subdomain box is under 32 cells wide in
+                           x, each tile spans two x-adjacent boxes, so the rows the passes
+                           read are at least 128 bytes of float32 (whole cache lines) instead
+                           of half lines; tiles then hold the labels of two boxes (a tiling
+                           whose tiles exceed 16 labels falls back to one box per tile
+                           before tiles shrink). -1: tiles inside one box. Results equal to
+                           rounding (the partial sums group cells differently) */
+  int32_t reserved[2];  /* must be 0 */
 } psl_setup_opts;
 
 /* Fill `o` with the defaults (all zero). */
@@ -494,6 +501,8 @@ typedef struct {
                            d <= 32) */
   int32_t face_tables;  /* 1: the float32 update reads packed faces and per-tile coarse
                            tables (psl_setup_opts.face_tables) */
+  int32_t wide_tiles;   /* 1: tiles span two x-adjacent subdomain boxes
+                           (psl_setup_opts.wide_tiles) */
 } psl_ctx_info;
 
 int psl_get_info(const psl_ctx* ctx, psl_ctx_info* info);

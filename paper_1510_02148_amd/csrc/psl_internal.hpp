@@ -87,6 +87,7 @@ struct psl_ctx {
   int nslot_max = 0;
   int tile_max = 0;                   // cells per tile (<= 2048)
   int cpt = 1;                        // cells per thread = ceil(tile_max / kBlock)
+  int wide_tiles = 0;                 // tiles span two x-adjacent subdomain boxes
   int small = 0;                      // float64 inner solves in one workgroup (small grids)
   int16_t* small_lptr = nullptr;      // its label-major cell lists: [d + 1] offsets
   uint16_t* small_lcell = nullptr;    // [n] cells

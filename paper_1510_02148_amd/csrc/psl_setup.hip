@@ -1474,23 +1474,31 @@ static inline int part_lo(int b, int n, int s) {  // first index of part b in a 
   return int((int64_t(b) * n + s - 1) / s);
 }
 
-static std::vector<Tile> make_tiles(int nx, int ny, int nz, const int nsub[3], int tile_max) {
+static std::vector<Tile> make_tiles(int nx, int ny, int nz, const int nsub[3], int tile_max,
+                                    bool span) {
   std::vector<Tile> out;
+  const int bstep = span ? 2 : 1;
   for (int bz = 0; bz < nsub[2]; ++bz)
     for (int by = 0; by < nsub[1]; ++by)
-      for (int bx = 0; bx < nsub[0]; ++bx) {
-        const int x0 = part_lo(bx, nx, nsub[0]), x1 = part_lo(bx + 1, nx, nsub[0]);
+      for (int bx = 0; bx < nsub[0]; bx += bstep) {
+        const int x0 = part_lo(bx, nx, nsub[0]);
+        const int x1 = part_lo(std::min(bx + bstep, nsub[0]), nx, nsub[0]);
         const int y0 = part_lo(by, ny, nsub[1]), y1 = part_lo(by + 1, ny, nsub[1]);
         const int z0 = part_lo(bz, nz, nsub[2]), z1 = part_lo(bz + 1, nz, nsub[2]);
         const int ex = x1 - x0, ey = y1 - y0, ez = z1 - z0;
         if (ex <= 0 || ey <= 0 || ez <= 0) continue;
+        // fewest z chunks whose largest part fits, else whole planes cut into the fewest
+        // y chunks that fit, else rows cut in x
         int cz = 1, cy = 1, cx = 1;
         const int64_t vol = int64_t(ex) * ey * ez;
+        const int64_t plane = int64_t(ex) * ey;
         if (vol > tile_max) {
           cz = int(std::min<int64_t>(ez, (vol + tile_max - 1) / tile_max));
-          if (int64_t(ex) * ey * ((ez + cz - 1) / cz) > tile_max) {
+          while (cz < ez && plane * ((ez + cz - 1) / cz) > tile_max) ++cz;
+          if (plane * ((ez + cz - 1) / cz) > tile_max) {
             cz = ez;
-            cy = int(std::min<int64_t>(ey, (int64_t(ex) * ey + tile_max - 1) / tile_max));
+            cy = int(std::min<int64_t>(ey, (plane + tile_max - 1) / tile_max));
+            while (cy < ey && int64_t(ex) * ((ey + cy - 1) / cy) > tile_max) ++cy;
             if (int64_t(ex) * ((ey + cy - 1) / cy) > tile_max) {
               cy = ey;
               cx = (ex + tile_max - 1) / tile_max;
@@ -1670,6 +1678,7 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
     if (so->coarse_sym < -1 || so->coarse_sym > 1) return PSL_EINVAL;
     if (so->stencil_split < -1 || so->stencil_split > 1) return PSL_EINVAL;
     if (so->face_tables < -1 || so->face_tables > 1) return PSL_EINVAL;
+    if (so->wide_tiles < -1 || so->wide_tiles > 1) return PSL_EINVAL;
     for (int32_t r : so->reserved)
       if (r != 0) return PSL_EINVAL;
   }
@@ -1767,8 +1776,13 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
   // step decisions in finish kernels on large grids (the pass kernels then skip the
   // repeated partial sums; below this size the extra launches cost more)
   c->pre = (so && so->finish_kernels) ? (so->finish_kernels > 0) : (int64_t(n) >= (int64_t(1) << 21));
+  // tiles two subdomain boxes wide when a box is under 32 cells wide: rows of at least 128
+  // bytes in the float32 passes (whole cache lines) instead of half lines; by default not
+  // on grids under 2^15 cells, whose vectors stay in cache
+  bool span = ns[0] >= 2 && nx / ns[0] < 32 &&
+              (so && so->wide_tiles ? so->wide_tiles > 0 : int64_t(n) >= (int64_t(1) << 15));
   for (;;) {
-    c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max);
+    c->h_tiles = make_tiles(nx, ny, nz, ns, tile_max, span);
     c->ntiles = int(c->h_tiles.size());
     c->tiles = nullptr;
     c->tile_lab = nullptr;
@@ -1784,9 +1798,16 @@ extern "C" int psl_setup_E_ex(psl_ctx** out, const psl_grid* g, const double* Tx
     if (read_flags()) PSL_FAIL(PSL_EHIP);
     if (hflags[3]) PSL_FAIL(PSL_EINVAL);  // a label outside [0, d)
     if (hflags[0]) PSL_FAIL(PSL_ENOTSPD);
-    if (!hflags[1]) break;
-    if (tile_max == 1) PSL_FAIL(PSL_EINVAL);
-    tile_max = std::max(1, tile_max / 2);
+    if (!hflags[1]) {
+      c->wide_tiles = span;
+      break;
+    }
+    if (span) {
+      span = false;   // too many labels in a tile: first give up the wide tiles
+    } else {
+      if (tile_max == 1) PSL_FAIL(PSL_EINVAL);
+      tile_max = std::max(1, tile_max / 2);
+    }
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(kBlock), 0, st, flags, 0, int64_t(8));
   }
   // label -> partial lists
@@ -1933,5 +1954,6 @@ extern "C" int psl_get_info(const psl_ctx* c, psl_ctx_info* info) {
   info->coarse_sym = c->coarse_sym;
   info->small_solve = c->small;
   info->face_tables = c->face_tab;
+  info->wide_tiles = c->wide_tiles;
   return PSL_OK;
 }

@@ -27,14 +27,15 @@ def setup(grid: Sequence[int], K: torch.Tensor, dirichlet_mask: int, nsub: Seque
           thr: Sequence[float], cls: Optional[torch.Tensor] = None, ncls: int = 0,
           tile_cells: Optional[int] = None, components: bool = False,
           finish_kernels: int = 0, coarse_sym: int = 0, stencil_split: int = 0,
-          face_tables: int = 0) -> Setup:
+          face_tables: int = 0, wide_tiles: int = 0) -> Setup:
     """psl_assemble_tpfa -> psl_build_Z (or psl_build_Z_cc) -> psl_setup_E on the current
     stream."""
     Tx, Ty, Tz = psl.psl_assemble_tpfa(grid, K, dirichlet_mask)
     labels, d = psl.psl_build_Z(grid, K, nsub, thr, cls=cls, ncls=ncls, components=components)
     ctx = psl.psl_setup_E(grid, Tx, Ty, Tz, labels, d, nsub=nsub, tile_cells=tile_cells,
                           finish_kernels=finish_kernels, coarse_sym=coarse_sym,
-                          stencil_split=stencil_split, face_tables=face_tables)
+                          stencil_split=stencil_split, face_tables=face_tables,
+                          wide_tiles=wide_tiles)
     return Setup(tuple(int(v) for v in grid), Tx, Ty, Tz, labels, d, ctx)
 
 

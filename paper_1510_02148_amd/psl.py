@@ -41,7 +41,8 @@ class psl_grid(ctypes.Structure):
 class psl_setup_opts(ctypes.Structure):
     _fields_ = [("tile_cells", ctypes.c_int32), ("finish_kernels", ctypes.c_int32),
                 ("coarse_sym", ctypes.c_int32), ("stencil_split", ctypes.c_int32),
-                ("face_tables", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("face_tables", ctypes.c_int32), ("wide_tiles", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class psl_solve_opts(ctypes.Structure):
@@ -55,7 +56,7 @@ class psl_ctx_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("m_faces", ctypes.c_int64), ("nslot_max", ctypes.c_int32),
                 ("coarse_sym", ctypes.c_int32), ("small_solve", ctypes.c_int32),
-                ("face_tables", ctypes.c_int32)]
+                ("face_tables", ctypes.c_int32), ("wide_tiles", ctypes.c_int32)]
 
 
 class psl_solve_stats(ctypes.Structure):
@@ -258,9 +259,10 @@ class Context:
 def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
                 labels: torch.Tensor, d: int, nsub=None, tile_cells: Optional[int] = None,
                 finish_kernels: int = 0, coarse_sym: int = 0,
-                stencil_split: int = 0, face_tables: int = 0) -> Context:
+                stencil_split: int = 0, face_tables: int = 0,
+                wide_tiles: int = 0) -> Context:
     """psl_setup_E, or psl_setup_E_ex when a tile size, the finish-kernel, coarse-product,
-    stencil-split or face-table choice is given."""
+    stencil-split, face-table or wide-tile choice is given."""
     n = int(grid[0]) * int(grid[1]) * int(grid[2])
     fx, fy, fz = face_counts(grid)
     g = _grid(grid)
@@ -271,7 +273,7 @@ def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
             _dev(labels, torch.int32, n, "labels"), int(d),
             ns if ns is not None else ctypes.cast(None, _I32P))
     if (tile_cells is None and not finish_kernels and not coarse_sym and not stencil_split
-            and not face_tables):
+            and not face_tables and not wide_tiles):
         _check(_setup_e(*args, _stream()), "psl_setup_E")
     else:
         so = psl_setup_opts()
@@ -281,6 +283,7 @@ def psl_setup_E(grid, Tx: torch.Tensor, Ty: torch.Tensor, Tz: torch.Tensor,
         so.coarse_sym = int(coarse_sym)
         so.stencil_split = int(stencil_split)
         so.face_tables = int(face_tables)
+        so.wide_tiles = int(wide_tiles)
         _check(_setup_e_ex(*args, ctypes.byref(so), _stream()), "psl_setup_E_ex")
     return Context(out.value, grid, int(d))
 

@@ -60,8 +60,10 @@ def test_binding_struct_layout_matches_c(tmp_path):
         " offsetof(psl_poly_opts, degree), offsetof(psl_poly_opts, check_every),"
         " offsetof(psl_poly_opts, mixed), offsetof(psl_gmres_opts, degree));"
         "printf(\"%zu\\n\", offsetof(psl_solve_stats, zt_r_drift));"
-        "printf(\"%zu %zu %zu %zu\\n\", sizeof(psl_ctx_info), offsetof(psl_ctx_info, coarse_sym),"
-        " offsetof(psl_ctx_info, small_solve), offsetof(psl_ctx_info, face_tables));"
+        "printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(psl_ctx_info), offsetof(psl_ctx_info, coarse_sym),"
+        " offsetof(psl_ctx_info, small_solve), offsetof(psl_ctx_info, face_tables),"
+        " offsetof(psl_ctx_info, wide_tiles));"
+        "printf(\"%zu\\n\", offsetof(psl_setup_opts, wide_tiles));"
         "return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
@@ -77,7 +79,8 @@ def test_binding_struct_layout_matches_c(tmp_path):
             psl.psl_poly_opts.check_every.offset, psl.psl_poly_opts.mixed.offset,
             psl.psl_gmres_opts.degree.offset, psl.psl_solve_stats.zt_r_drift.offset,
             ctypes.sizeof(psl.psl_ctx_info), psl.psl_ctx_info.coarse_sym.offset,
-            psl.psl_ctx_info.small_solve.offset, psl.psl_ctx_info.face_tables.offset]
+            psl.psl_ctx_info.small_solve.offset, psl.psl_ctx_info.face_tables.offset,
+            psl.psl_ctx_info.wide_tiles.offset, psl.psl_setup_opts.wide_tiles.offset]
     assert got == want
 
 

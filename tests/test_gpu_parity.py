@@ -1086,3 +1086,37 @@ def test_face_tables(gpu_lib, name, scale, kw, components, finish):
     assert st1["status"] == 0 and res <= 1e-8
     assert (st1["iters"], st1["outer"]) == (st0["iters"], st0["outer"])
     assert torch.equal(x1, x0)
+
+
+@pytest.mark.parametrize("finish", [1, -1], ids=["finish", "passes"])
+@pytest.mark.parametrize("name,scale,kw,components", FACE_CASES,
+                         ids=["c2-4", "c3-4-components", "ragged-0"])
+def test_wide_tiles(gpu_lib, name, scale, kw, components, finish):
+    """Tiles two subdomain boxes wide (whole 128-byte rows of float32) against tiles inside
+    one box: the same operator and deflation space, only the per-tile partial sums grouped
+    differently, so both solutions meet the oracle's residual bound and take nearly the
+    same number of iterations, in float64 and mixed precision."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = _problem(name, scale, kw)
+    nx, sx = p.grid[0], p.nsub[0]
+    expect = sx >= 2 and nx // sx < 32
+    say(f"wide tiles {name}/{scale} grid={p.grid} nsub={p.nsub} expect={expect} finish={finish}")
+    K, b = dev(p.K), dev(p.q)
+    A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+    its = {}
+    for wt in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr),
+                           components=components, finish_kernels=finish, wide_tiles=wt)
+        assert psl.psl_get_info(s.ctx)["wide_tiles"] == int(wt > 0 and expect)
+        for mode in (psl.FP64, psl.MIXED):
+            x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=mode)
+            res = O.relres(A, bh, host(x))
+            say(f"  wide={wt} mode={mode}: iters={st['iters']} outer={st['outer']} "
+                f"relres={res:.2e}")
+            assert st["status"] == 0 and res <= 1e-8
+            its[(wt, mode)] = st["iters"]
+        s.ctx.destroy()
+    for mode in (psl.FP64, psl.MIXED):
+        a, c = its[(1, mode)], its[(-1, mode)]
+        assert abs(a - c) <= max(2, 0.03 * c), (mode, a, c)
