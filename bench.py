@@ -106,10 +106,12 @@ SOLVER_TAGS = {
 }
 
 
-def counter_traffic(kernel: str, workload: str, mode: str, coarse_sym: int = 0):
+def counter_traffic(kernel: str, workload: str, mode: str, coarse_sym: int = 0,
+                    tile_cells=None, wide_tiles: int = 0):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary
     (FETCH_SIZE / WRITE_SIZE scaled by the copy-kernel calibration), or None when no
-    summary covers this kernel, workload and mode or the kernel source changed since."""
+    summary covers this kernel, workload, mode and tiling (tile size, wide tiles) or the
+    kernel source changed since."""
     import glob
     import hashlib
     src_path = os.path.join(ROOT, "paper_1510_02148_amd", "csrc", "psl_solve.hip")
@@ -123,6 +125,9 @@ def counter_traffic(kernel: str, workload: str, mode: str, coarse_sym: int = 0):
                 (kernel, workload, mode):
             continue
         if kernel == "coarse" and int(fields.get("coarse_sym", "0")) != int(coarse_sym):
+            continue
+        if (fields.get("tile_cells"), fields.get("wide_tiles")) != \
+                (str(tile_cells), str(int(wide_tiles))):
             continue
         src = open(src_path).read()
         # the kernel and every device function it inlines, each from its marker to the
@@ -635,7 +640,9 @@ def main():
         else:   # the solver's own pass; the CG stencil is only the SpMV reference there
             dominant = next(k for k in kernels if k != "stencil")
         kd = kernels[dominant]
-        traffic = counter_traffic(dominant, args.workload, args.mode, int(info["coarse_sym"]))
+        traffic = counter_traffic(dominant, args.workload, args.mode, int(info["coarse_sym"]),
+                                  tiles["f32" if args.mode == "mixed" else "f64"],
+                                  int(info["wide_tiles"]))
         roofline = {"bound": "hbm", "kernel": dominant, "achieved": kd["gbs"],
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(kd["gbs"] / HBM_PEAK_GBS, 4),
