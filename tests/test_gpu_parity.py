@@ -1120,3 +1120,67 @@ def test_wide_tiles(gpu_lib, name, scale, kw, components, finish):
     for mode in (psl.FP64, psl.MIXED):
         a, c = its[(1, mode)], its[(-1, mode)]
         assert abs(a - c) <= max(2, 0.03 * c), (mode, a, c)
+
+
+def _tile_count(grid, nsub, tile_max, span):
+    """Tiles of the documented split rule: boxes of the floor partition (pairs of
+    x-adjacent boxes when spanning), each cut into the fewest z chunks whose largest part
+    holds at most tile_max cells, else whole planes into the fewest y chunks that fit,
+    else rows cut in x."""
+    def lo(b, n, s):
+        return (b * n + s - 1) // s
+
+    def cdiv(a, b):
+        return (a + b - 1) // b
+    nx, ny, nz = grid
+    step = 2 if span else 1
+    count = 0
+    for bz in range(nsub[2]):
+        for by in range(nsub[1]):
+            for bx in range(0, nsub[0], step):
+                ex = lo(min(bx + step, nsub[0]), nx, nsub[0]) - lo(bx, nx, nsub[0])
+                ey = lo(by + 1, ny, nsub[1]) - lo(by, ny, nsub[1])
+                ez = lo(bz + 1, nz, nsub[2]) - lo(bz, nz, nsub[2])
+                cz = cy = cx = 1
+                if ex * ey * ez > tile_max:
+                    cz = min(ez, cdiv(ex * ey * ez, tile_max))
+                    while cz < ez and ex * ey * cdiv(ez, cz) > tile_max:
+                        cz += 1
+                    if ex * ey * cdiv(ez, cz) > tile_max:
+                        cz = ez
+                        cy = min(ey, cdiv(ex * ey, tile_max))
+                        while cy < ey and ex * cdiv(ey, cy) > tile_max:
+                            cy += 1
+                        if ex * cdiv(ey, cy) > tile_max:
+                            cy, cx = ey, cdiv(ex, tile_max)
+                count += cx * cy * cz
+    return count
+
+
+TILE_RULE_CASES = [((87, 87, 87), (4, 4, 4), 256), ((64, 48, 32), (4, 3, 2), 512),
+                   ((37, 29, 11), (5, 3, 2), 128), ((96, 80, 48), (6, 5, 3), 1024)]
+
+
+@pytest.mark.parametrize("grid,nsub,tile", TILE_RULE_CASES)
+def test_tile_split_rule(gpu_lib, grid, nsub, tile):
+    """The library's tiling follows the split rule on boxes one and two wide (a box whose
+    planes do not fit is cut into the fewest y chunks that fit, not into rows: a rounding
+    slip there once made 44-cell tiles on an 87^3 grid), and a solve on it is correct."""
+    psl = gpu_lib
+    from paper_1510_02148_amd import pipeline
+    p = pi.layered3d(*grid, nlayers=4, contrast=1e4, nsub=nsub, seed=5)
+    say(f"tile rule grid={grid} nsub={nsub} tile={tile}")
+    K = dev(p.K)
+    for wt in (1, -1):
+        s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), tile_cells=tile,
+                           wide_tiles=wt)
+        info = psl.psl_get_info(s.ctx)
+        want = _tile_count(grid, nsub, tile, bool(info["wide_tiles"]))
+        say(f"  wide={info['wide_tiles']}: ntiles={info['ntiles']} rule={want}")
+        assert info["wide_tiles"] == int(wt > 0 and grid[0] // nsub[0] < 32)
+        assert info["ntiles"] == want
+        if wt > 0:
+            x, st = psl.psl_solve(s.ctx, dev(p.q), tol=1e-8, mode=psl.MIXED)
+            A, bh = O.assemble(p.K, p.grid, p.dirichlet_mask, p.q)
+            assert st["status"] == 0 and O.relres(A, bh, host(x)) <= 1e-8
+        s.ctx.destroy()
