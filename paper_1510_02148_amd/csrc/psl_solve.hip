@@ -3450,6 +3450,7 @@ __global__ void __launch_bounds__(kBlock)
 // Arithmetic in R; the partials in float64.
 template <typename R, int CPT, bool FIRST, bool LAST>
 __global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && CPT >= 4 ? 8 : 1)))
     k_pc_cheb(Geo g, const R* __restrict__ Tx, const R* __restrict__ Ty,
               const R* __restrict__ Tz, const R* __restrict__ r,
               const R* __restrict__ invd, const R* __restrict__ yin, R* d,
@@ -3465,58 +3466,63 @@ __global__ void __launch_bounds__(kBlock)
   const R it = R(inv_theta), c1 = R(c1d), c2 = R(c2d);
   // y_s at a cell: stored, or D^-1 r / theta for the first step
   auto ys = [&](int c) -> R { return FIRST ? r[c] * invd[c] * it : yin[c]; };
-  int cc[CPT];
-  R yc[CPT], yw[CPT], ye[CPT], ysn[CPT], yn[CPT], yb[CPT], yt[CPT];
-  R t0[CPT], t1[CPT], t2[CPT], t3[CPT], t4[CPT], t5[CPT], rc[CPT], ic[CPT], dc[CPT];
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const int j = threadIdx.x + k * kBlock;
-    cc[k] = -1;
-    if (j < T.ncell) {
-      int ix, iy, iz;
-      cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
-      const int c = ix + nx * (iy + ny * iz);
-      const int fx = c + (iy + ny * iz);
-      const int fy = c + nx * iz;
-      cc[k] = c;
-      yc[k] = ys(c);
-      yw[k] = ix > 0 ? ys(c - 1) : R(0);
-      ye[k] = ix < nx - 1 ? ys(c + 1) : R(0);
-      ysn[k] = iy > 0 ? ys(c - nx) : R(0);
-      yn[k] = iy < ny - 1 ? ys(c + nx) : R(0);
-      yb[k] = iz > 0 ? ys(c - sxy) : R(0);
-      yt[k] = iz < nz - 1 ? ys(c + sxy) : R(0);
-      t0[k] = Tx[fx];
-      t1[k] = Tx[fx + 1];
-      t2[k] = Ty[fy];
-      t3[k] = Ty[fy + nx];
-      t4[k] = Tz[c];
-      t5[k] = Tz[c + sxy];
-      rc[k] = r[c];
-      ic[k] = invd[c];
-      dc[k] = FIRST ? R(0) : d[c];
-    }
-  }
+  // the thread's cells in chunks of at most two (as in k_stencil), in the same order
+  constexpr int CH = CPT < 2 ? CPT : 2;
   double acc[2] = {0.0, 0.0};
+#pragma unroll 1
+  for (int k0 = 0; k0 < CPT; k0 += CH) {
+    int cc[CH];
+    R yc[CH], yw[CH], ye[CH], ysn[CH], yn[CH], yb[CH], yt[CH];
+    R t0[CH], t1[CH], t2[CH], t3[CH], t4[CH], t5[CH], rc[CH], ic[CH], dc[CH];
 #pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    if (cc[k] < 0) continue;
-    const R y0 = yc[k];
-    R ap = t0[k] * (y0 - yw[k]);
-    ap += t1[k] * (y0 - ye[k]);
-    ap += t2[k] * (y0 - ysn[k]);
-    ap += t3[k] * (y0 - yn[k]);
-    ap += t4[k] * (y0 - yb[k]);
-    ap += t5[k] * (y0 - yt[k]);
-    const R dprev = FIRST ? y0 : dc[k];
-    const R dn = c1 * dprev + c2 * ic[k] * (rc[k] - ap);
-    const R ynew = y0 + dn;
-    yout[cc[k]] = ynew;
-    if (LAST) {
-      acc[0] += double(rc[k]) * double(ynew);
-      acc[1] += double(rc[k]) * double(rc[k]);
-    } else {
-      d[cc[k]] = dn;
+    for (int k = 0; k < CH; ++k) {
+      const int j = threadIdx.x + (k0 + k) * kBlock;
+      cc[k] = -1;
+      if (j < T.ncell) {
+        int ix, iy, iz;
+        cell_coords(T, j, inv_sx, inv_sxy, ix, iy, iz);
+        const int c = ix + nx * (iy + ny * iz);
+        const int fx = c + (iy + ny * iz);
+        const int fy = c + nx * iz;
+        cc[k] = c;
+        yc[k] = ys(c);
+        yw[k] = ix > 0 ? ys(c - 1) : R(0);
+        ye[k] = ix < nx - 1 ? ys(c + 1) : R(0);
+        ysn[k] = iy > 0 ? ys(c - nx) : R(0);
+        yn[k] = iy < ny - 1 ? ys(c + nx) : R(0);
+        yb[k] = iz > 0 ? ys(c - sxy) : R(0);
+        yt[k] = iz < nz - 1 ? ys(c + sxy) : R(0);
+        t0[k] = Tx[fx];
+        t1[k] = Tx[fx + 1];
+        t2[k] = Ty[fy];
+        t3[k] = Ty[fy + nx];
+        t4[k] = Tz[c];
+        t5[k] = Tz[c + sxy];
+        rc[k] = r[c];
+        ic[k] = invd[c];
+        dc[k] = FIRST ? R(0) : d[c];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      if (cc[k] < 0) continue;
+      const R y0 = yc[k];
+      R ap = t0[k] * (y0 - yw[k]);
+      ap += t1[k] * (y0 - ye[k]);
+      ap += t2[k] * (y0 - ysn[k]);
+      ap += t3[k] * (y0 - yn[k]);
+      ap += t4[k] * (y0 - yb[k]);
+      ap += t5[k] * (y0 - yt[k]);
+      const R dprev = FIRST ? y0 : dc[k];
+      const R dn = c1 * dprev + c2 * ic[k] * (rc[k] - ap);
+      const R ynew = y0 + dn;
+      yout[cc[k]] = ynew;
+      if (LAST) {
+        acc[0] += double(rc[k]) * double(ynew);
+        acc[1] += double(rc[k]) * double(rc[k]);
+      } else {
+        d[cc[k]] = dn;
+      }
     }
   }
   if (LAST) {
