@@ -122,6 +122,9 @@ __device__ inline void write_slots(const double (&acc)[NS], int nslot, const int
 // residual). Partials per tile: Z^T out (zq) and (in, out) resp. ||out||^2 (red[t]).
 // With `stop` set, the pass returns at once once a solve's stop flag is raised.
 // ---------------------------------------------------------------------------------------
+// float32 instances on four or more cells per thread with at most eight slots are compiled
+// for eight waves per SIMD: with the cells taken two at a time they fit in 64 registers
+// without spilling (more slots, or float64, would spill)
 template <typename R, int MODE, int NS, int CPT>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && CPT >= 4 && NS <= 8 ? 8 : 1)))
@@ -3448,6 +3451,8 @@ __global__ void __launch_bounds__(kBlock)
 // FIRST: y_1 = d_1 = D^-1 r / theta, formed here for the cell and its neighbours.
 // LAST: store y_{s+1} only, with the partials (r, y), (r, r) per tile; else store d, y.
 // Arithmetic in R; the partials in float64.
+// float32 instances on four or more cells per thread are compiled for eight waves per
+// SIMD (the cells are taken two at a time; no spills)
 template <typename R, int CPT, bool FIRST, bool LAST>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && CPT >= 4 ? 8 : 1)))
