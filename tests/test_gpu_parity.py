@@ -970,24 +970,26 @@ def test_coarse_symmetric(gpu_lib, name, scale, kw, nsub):
     assert not failures, failures
 
 
+@pytest.mark.parametrize("tile", [None, 1024], ids=["default-tiles", "tiles-1024"])
 @pytest.mark.parametrize("name,scale,kw", FINISH_CASES,
                          ids=[f"{c[0]}-{c[1]}" for c in FINISH_CASES])
-def test_stencil_split(gpu_lib, name, scale, kw):
+def test_stencil_split(gpu_lib, name, scale, kw, tile):
     """The float32 stencil pass split in two (the direction update p = u + beta p_prev in
     a pass of its own, then the plain stencil q = A p with its partials) against the
     fused pass that recomputes the neighbours' p, both with finish kernels (forced on for
     these small grids), in mixed precision: the same fused multiply-add and the same sums
     in the same order, so x is bit-identical with equal iteration and refinement counts;
-    and the oracle's residual of x."""
+    and the oracle's residual of x. With 1024-cell tiles each thread owns four cells,
+    which the plain stencil takes two at a time and the fused pass all at once."""
     psl = gpu_lib
     from paper_1510_02148_amd import pipeline
     p = _problem(name, scale, kw)
-    say(f"stencil split {name}/{scale} grid={p.grid}")
+    say(f"stencil split {name}/{scale} grid={p.grid} tile={tile}")
     K, b = dev(p.K), dev(p.q)
     out = {}
     for split in (1, -1):
         s = pipeline.setup(p.grid, K, p.dirichlet_mask, p.nsub, list(p.thr), finish_kernels=1,
-                           stencil_split=split)
+                           stencil_split=split, tile_cells=tile)
         x, st = psl.psl_solve(s.ctx, b, tol=1e-8, mode=psl.MIXED)
         out[split] = (x.clone(), st)
         s.ctx.destroy()
